@@ -1,0 +1,1059 @@
+// Host side of the DECO library: the C ABI of include/deco.h.
+//
+// A handle binds a caller-owned graph, iterate X and workspace. deco_init validates the
+// graph on the device, keeps a host copy of row_ptr and builds the work schedule: rows are
+// cut into items of bounded edge count, every item is paired with each initialisation tile,
+// and items are grouped per XCD (workgroup i runs on XCD i % 8), either by contiguous row
+// ranges or by initialisation tile, so that one XCD's L2 keeps serving the gathers of the
+// rows / tile it owns. deco_autotune times a set of candidate schedules on the device.
+// deco_solve is the host loop of pDECO (Alg. 3) with the evolutionary search of Sec. 4.3.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/deco.h"
+#include "internal.h"
+
+using namespace deco;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Schedule {
+  int vec = 4;
+  int Wc = 1;
+  int split = 1;
+  int rows_per_item = 256;
+  int nnz_per_item = 4096;
+  int xcd_mode = 0;   // 0 rows per XCD, 1 initialisation tiles per XCD
+  int blocks_per_xcd = 128;
+  int grid = 0;
+  int nitems = 0;
+  std::vector<int4> items;
+  int seg[9] = {0};
+};
+
+struct Layout {
+  size_t xalt, bits0, bits1, best_bits, mask, acc, cur_cut, best_cut, best_step, ctrl, dw, eta,
+      items, seg, goff, thr, delta, l_active, flags, total;
+  long long items_cap;
+  int R;
+};
+
+int elem_size(int dtype) { return dtype == DECO_BF16 ? 2 : 4; }
+int nby_of(int B) { return (B + 7) / 8; }
+
+bool supported_B(int B) { return B == 1 || B == 2 || B == 4 || (B > 0 && B % 8 == 0); }
+
+int vec_for(int dtype, int B) { return (B % 8 == 0) ? native_vec(dtype) : 1; }
+
+// Largest lane count per row (power of two, <= 64) whose tile divides B.
+int max_wc(int vec, int B) {
+  int wc = 1;
+  while (wc * 2 <= 64 && B % (wc * 2 * vec) == 0) wc *= 2;
+  return wc;
+}
+
+Layout layout_for(long long n, long long nnz, int G, const deco_params* p) {
+  Layout L{};
+  const int C = p->l * p->B;
+  const int NBY = nby_of(p->B);
+  const int vec = vec_for(p->x_dtype, p->B);
+  const long long nbt_max = std::max(1, p->B / std::max(1, vec));  // tiles of >= one lane
+  L.R = G >= 16 ? 1 : 16;
+  L.items_cap = nbt_max * (n / 16 + (long long)G + 16);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 1));
+    return o;
+  };
+  L.xalt = take((size_t)n * C * elem_size(p->x_dtype));
+  L.bits0 = take((size_t)n * NBY);
+  L.bits1 = take((size_t)n * NBY);
+  L.best_bits = take((size_t)n * NBY);
+  L.mask = take((size_t)G * NBY);
+  L.acc = take(sizeof(double) * (size_t)L.R * G * p->B);
+  L.cur_cut = take(sizeof(double) * (size_t)G * p->B);
+  L.best_cut = take(sizeof(double) * (size_t)G * p->B);
+  L.best_step = take(sizeof(int) * (size_t)G * p->B);
+  L.ctrl = take(sizeof(DevCtrl));
+  L.dw = take(sizeof(float) * (size_t)n);
+  L.eta = take(sizeof(float) * (size_t)p->B);
+  L.items = take(sizeof(int4) * (size_t)L.items_cap);
+  L.seg = take(sizeof(int) * 16);
+  L.goff = take(sizeof(int) * (size_t)(G + 1));
+  L.thr = take(sizeof(double) * (size_t)G);
+  L.delta = take(sizeof(int) * (size_t)G);
+  L.l_active = take(sizeof(int) * (size_t)p->B);
+  L.flags = take(sizeof(int) * 4);
+  L.total = off;
+  (void)nnz;
+  return L;
+}
+
+}  // namespace
+
+struct deco_handle {
+  deco_graph g{};
+  deco_params p{};
+  hipStream_t stream = nullptr;
+  long long n = 0, nnz = 0;
+  int G = 1, C = 1, NBY = 1, R = 1, dtype = 0;
+  bool unit = true;
+  bool poisoned = false;
+  Layout lay{};
+  char* ws = nullptr;
+  void* X = nullptr;
+  StepArgs args{};
+  Schedule sched;
+  std::vector<int> rp_host;
+  std::vector<int> goff_host;
+  long long t_host = 0;
+  double* trace = nullptr;
+  int trace_cap = 0;
+  std::map<int, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+deco_status poison(deco_handle* h, hipError_t e) {
+  if (e == hipSuccess) return DECO_OK;
+  if (h) h->poisoned = true;
+  return DECO_E_DEVICE;
+}
+
+#define HIP_TRY(h, expr)                        \
+  do {                                          \
+    hipError_t e__ = (expr);                    \
+    if (e__ != hipSuccess) return poison((h), e__); \
+  } while (0)
+
+// Split each graph's rows into chunks of at most rows_per_item rows and roughly
+// nnz_per_item stored entries; a single long row forms a chunk of its own.
+std::vector<int4> row_chunks(const std::vector<int>& rp, const std::vector<int>& goff,
+                             int rows_per_item, int nnz_per_item) {
+  std::vector<int4> ch;
+  const int G = (int)goff.size() - 1;
+  for (int g = 0; g < G; ++g) {
+    int r = goff[g];
+    while (r < goff[g + 1]) {
+      int r1 = r + 1;
+      long long e = rp[r + 1] - rp[r];
+      while (r1 < goff[g + 1] && r1 - r < rows_per_item &&
+             e + (rp[r1 + 1] - rp[r1]) <= nnz_per_item) {
+        e += rp[r1 + 1] - rp[r1];
+        ++r1;
+      }
+      ch.push_back(make_int4(r, r1, g, 0));
+      r = r1;
+    }
+  }
+  return ch;
+}
+
+// Cut the chunk list into 'parts' contiguous groups of about equal weight (rows + edges).
+std::vector<int> balance(const std::vector<int4>& ch, const std::vector<int>& rp, int parts) {
+  std::vector<int> cut(parts + 1, 0);
+  long long total = 0;
+  for (auto& c : ch) total += (c.y - c.x) + (rp[c.y] - rp[c.x]);
+  long long acc = 0;
+  int p = 1;
+  for (size_t i = 0; i < ch.size() && p < parts; ++i) {
+    acc += (ch[i].y - ch[i].x) + (rp[ch[i].y] - rp[ch[i].x]);
+    while (p < parts && acc * parts >= total * p) cut[p++] = (int)i + 1;
+  }
+  while (p < parts) cut[p++] = (int)ch.size();
+  cut[parts] = (int)ch.size();
+  return cut;
+}
+
+bool build_schedule(deco_handle* h, Schedule& s) {
+  const int B = h->p.B;
+  const int Bt = s.Wc * s.vec;
+  if (Bt <= 0 || B % Bt != 0 || (B >= 8 && Bt % 8 != 0)) return false;
+  if (s.Wc * s.split > 64) return false;
+  const int nbt = B / Bt;
+  auto ch = row_chunks(h->rp_host, h->goff_host, s.rows_per_item, s.nnz_per_item);
+  std::vector<int4> items;
+  int seg[9];
+  const bool tiles = s.xcd_mode == 1 && nbt >= 2 && (nbt >= 8 || 8 % nbt == 0);
+  if (!tiles) {
+    auto cut = balance(ch, h->rp_host, 8);
+    for (int x = 0; x < 8; ++x) {
+      seg[x] = (int)items.size();
+      for (int bt = 0; bt < nbt; ++bt)
+        for (int i = cut[x]; i < cut[x + 1]; ++i) items.push_back(make_int4(ch[i].x, ch[i].y, ch[i].z, bt));
+    }
+  } else if (nbt >= 8) {
+    for (int x = 0; x < 8; ++x) {
+      seg[x] = (int)items.size();
+      for (int bt = x; bt < nbt; bt += 8)
+        for (auto& c : ch) items.push_back(make_int4(c.x, c.y, c.z, bt));
+    }
+  } else {
+    const int parts = 8 / nbt;
+    auto cut = balance(ch, h->rp_host, parts);
+    for (int x = 0; x < 8; ++x) {
+      seg[x] = (int)items.size();
+      const int bt = x % nbt, part = x / nbt;
+      for (int i = cut[part]; i < cut[part + 1]; ++i) items.push_back(make_int4(ch[i].x, ch[i].y, ch[i].z, bt));
+    }
+  }
+  seg[8] = (int)items.size();
+  if ((long long)items.size() > h->lay.items_cap) return false;
+  int maxper = 1;
+  for (int x = 0; x < 8; ++x) maxper = std::max(maxper, seg[x + 1] - seg[x]);
+  s.grid = 8 * std::min(s.blocks_per_xcd, maxper);
+  s.nitems = (int)items.size();
+  s.items = std::move(items);
+  std::memcpy(s.seg, seg, sizeof(seg));
+  return true;
+}
+
+deco_status upload_schedule(deco_handle* h) {
+  char* ws = h->ws;
+  HIP_TRY(h, hipMemcpyAsync(ws + h->lay.items, h->sched.items.data(), sizeof(int4) * h->sched.items.size(),
+                            hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(ws + h->lay.seg, h->sched.seg, sizeof(int) * 9, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  h->args.Wc = h->sched.Wc;
+  h->args.split = h->sched.split;
+  for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+  h->graphs.clear();
+  return DECO_OK;
+}
+
+Schedule default_schedule(deco_handle* h) {
+  Schedule s;
+  s.vec = vec_for(h->dtype, h->p.B);
+  s.Wc = max_wc(s.vec, h->p.B);
+  const double deg = h->n > 0 ? (double)h->nnz / (double)h->n : 0.0;
+  int split = 1;
+  while (split * 2 * s.Wc <= 64 && split * 2 <= deg / 4.0) split *= 2;
+  s.split = split;
+  s.xcd_mode = 0;
+  s.blocks_per_xcd = 128;
+  // enough items for every workgroup, each worth at least a few row groups
+  const long long target = std::max<long long>(256, (h->nnz + h->n) / (8LL * s.blocks_per_xcd * 2));
+  s.nnz_per_item = (int)std::min<long long>(target, 1 << 20);
+  s.rows_per_item = std::max(16, (int)std::min<long long>(4096, s.nnz_per_item / std::max(1.0, deg) + 1));
+  return s;
+}
+
+std::mutex g_cache_mu;
+std::map<std::tuple<long long, long long, int, int, int, int, int>, Schedule> g_cache;
+
+std::tuple<long long, long long, int, int, int, int, int> cache_key(const deco_handle* h) {
+  return std::make_tuple(h->n, h->nnz, h->G, h->p.B, h->p.l, h->dtype, h->unit ? 1 : 0);
+}
+
+deco_status check_graph_args(const deco_graph* g) {
+  if (!g || g->n < 1 || g->nnz < 0 || !g->row_ptr || (g->nnz > 0 && !g->col_idx)) return DECO_E_INVAL;
+  if (g->num_graphs < 1 || (g->num_graphs > 1 && !g->graph_row_offset)) return DECO_E_INVAL;
+  if (g->n >= (1LL << 31) - 1 || g->nnz >= (1LL << 31) - 1) return DECO_E_UNSUPPORTED;
+  if (g->num_graphs > g->n) return DECO_E_INVAL;
+  return DECO_OK;
+}
+
+deco_status check_params(const deco_params* p) {
+  if (!p) return DECO_E_INVAL;
+  if (p->B < 1 || p->l < 1 || p->score_every < 1) return DECO_E_INVAL;
+  if (p->x_dtype != DECO_F32 && p->x_dtype != DECO_BF16) return DECO_E_INVAL;
+  if (p->grad_form != DECO_GRAD_CUT && p->grad_form != DECO_GRAD_LAPLACIAN) return DECO_E_INVAL;
+  if (!p->lifted && p->l != 1) return DECO_E_INVAL;
+  if (!std::isfinite(p->eta)) return DECO_E_NONFINITE;
+  if (!supported_B(p->B) || p->l > 4) return DECO_E_UNSUPPORTED;
+  return DECO_OK;
+}
+
+deco_status launch_steps(deco_handle* h, int steps, int do_update, int force) {
+  StepArgs a = h->args;
+  a.do_update = do_update;
+  a.force_score = force;
+  for (int s = 0; s < steps; ++s) {
+    const hipError_t e = launch_step(a, h->dtype, h->sched.vec, h->unit, h->sched.grid, h->stream);
+    if (e != hipSuccess) return poison(h, e);
+  }
+  return DECO_OK;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* deco_status_string(deco_status s) {
+  switch (s) {
+    case DECO_OK: return "ok";
+    case DECO_E_INVAL: return "invalid argument or graph";
+    case DECO_E_NOMEM: return "workspace too small or allocation failed";
+    case DECO_E_DEVICE: return "device error";
+    case DECO_E_STATE: return "handle poisoned by an earlier device error";
+    case DECO_E_NONFINITE: return "non-finite weight or starting value";
+    case DECO_E_UNSUPPORTED: return "unsupported shape";
+    default: return "unknown status";
+  }
+}
+
+deco_status deco_workspace_size(const deco_graph* g, const deco_params* p, size_t* bytes) {
+  deco_status st = check_graph_args(g);
+  if (st) return st;
+  if ((st = check_params(p))) return st;
+  if (!bytes) return DECO_E_INVAL;
+  *bytes = layout_for(g->n, g->nnz, g->num_graphs, p).total;
+  return DECO_OK;
+}
+
+deco_status deco_init(deco_handle** out, const deco_graph* g, const deco_params* p, void* X,
+                      void* workspace, size_t workspace_bytes, void* stream) {
+  if (!out) return DECO_E_INVAL;
+  *out = nullptr;
+  deco_status st = check_graph_args(g);
+  if (st) return st;
+  if ((st = check_params(p))) return st;
+  if (!X || !workspace) return DECO_E_INVAL;
+  if (((uintptr_t)X % 16) != 0 || ((uintptr_t)workspace % kAlign) != 0) return DECO_E_INVAL;
+  Layout lay = layout_for(g->n, g->nnz, g->num_graphs, p);
+  if (workspace_bytes < lay.total) return DECO_E_NOMEM;
+
+  deco_handle* h = new deco_handle();
+  h->g = *g;
+  h->p = *p;
+  h->stream = reinterpret_cast<hipStream_t>(stream);
+  h->n = g->n;
+  h->nnz = g->nnz;
+  h->G = g->num_graphs;
+  h->C = p->l * p->B;
+  h->NBY = nby_of(p->B);
+  h->R = lay.R;
+  h->dtype = p->x_dtype;
+  h->unit = g->w == nullptr;
+  h->lay = lay;
+  h->ws = reinterpret_cast<char*>(workspace);
+  h->X = X;
+
+  // host copies of the row structure (schedule, IDI statistics, DUI maxima)
+  h->rp_host.resize(g->n + 1);
+  hipError_t e = hipMemcpyAsync(h->rp_host.data(), g->row_ptr, sizeof(int) * (g->n + 1),
+                                hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    delete h;
+    return DECO_E_DEVICE;
+  }
+  h->goff_host.assign(h->G + 1, 0);
+  if (g->graph_row_offset) {
+    e = hipMemcpyAsync(h->goff_host.data(), g->graph_row_offset, sizeof(int) * (h->G + 1),
+                       hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+      delete h;
+      return DECO_E_DEVICE;
+    }
+  } else {
+    h->goff_host[1] = (int)g->n;
+  }
+  bool ok = h->rp_host[0] == 0 && h->rp_host[g->n] == g->nnz;
+  for (long long v = 0; ok && v < g->n; ++v) ok = h->rp_host[v] <= h->rp_host[v + 1];
+  ok = ok && h->goff_host[0] == 0 && h->goff_host[h->G] == g->n;
+  for (int i = 0; ok && i < h->G; ++i) ok = h->goff_host[i] < h->goff_host[i + 1];
+  if (!ok) {
+    delete h;
+    return DECO_E_INVAL;
+  }
+  char* ws = h->ws;
+  StepArgs& a = h->args;
+  a.rp = g->row_ptr;
+  a.ci = g->col_idx;
+  a.w = g->w;
+  a.dw = reinterpret_cast<float*>(ws + lay.dw);
+  a.x[0] = X;
+  a.x[1] = ws + lay.xalt;
+  a.C = h->C;
+  a.B = p->B;
+  a.L = p->l;
+  a.lifted = p->lifted;
+  a.items = reinterpret_cast<int4*>(ws + lay.items);
+  a.seg = reinterpret_cast<int*>(ws + lay.seg);
+  a.cW = p->grad_form == DECO_GRAD_CUT ? -0.5f : -1.0f;
+  a.cD = p->grad_form == DECO_GRAD_CUT ? 0.0f : 1.0f;
+  a.eta = reinterpret_cast<float*>(ws + lay.eta);
+  a.bits[0] = reinterpret_cast<uint8_t*>(ws + lay.bits0);
+  a.bits[1] = reinterpret_cast<uint8_t*>(ws + lay.bits1);
+  a.best_bits = reinterpret_cast<uint8_t*>(ws + lay.best_bits);
+  a.mask = reinterpret_cast<uint8_t*>(ws + lay.mask);
+  a.NBY = h->NBY;
+  a.acc = reinterpret_cast<double*>(ws + lay.acc);
+  a.R = lay.R;
+  a.G = h->G;
+  a.cur_cut = reinterpret_cast<double*>(ws + lay.cur_cut);
+  a.best_cut = reinterpret_cast<double*>(ws + lay.best_cut);
+  a.best_step = reinterpret_cast<int*>(ws + lay.best_step);
+  a.trace = nullptr;
+  a.trace_cap = 1;
+  a.ctrl = reinterpret_cast<DevCtrl*>(ws + lay.ctrl);
+  a.do_update = 1;
+
+  int* goff_dev = reinterpret_cast<int*>(ws + lay.goff);
+  int* flags = reinterpret_cast<int*>(ws + lay.flags);
+  int hflags = 0;
+  e = hipMemcpyAsync(goff_dev, h->goff_host.data(), sizeof(int) * (h->G + 1), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(flags, 0, sizeof(int) * 4, h->stream);
+  if (e == hipSuccess)
+    e = launch_validate(g->n, g->row_ptr, g->col_idx, g->w, goff_dev, h->G, const_cast<float*>(a.dw), flags,
+                        h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    delete h;
+    return DECO_E_DEVICE;
+  }
+  if (hflags & (1 | 2 | 8)) {
+    delete h;
+    return DECO_E_INVAL;
+  }
+  if (hflags & 4) {
+    delete h;
+    return DECO_E_NONFINITE;
+  }
+
+  // schedule: cached winner of an earlier autotune for this shape, else the default
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find(cache_key(h));
+    h->sched = it != g_cache.end() ? it->second : default_schedule(h);
+  }
+  if (!build_schedule(h, h->sched)) {
+    h->sched = default_schedule(h);
+    if (!build_schedule(h, h->sched)) {
+      delete h;
+      return DECO_E_UNSUPPORTED;
+    }
+  }
+  if (upload_schedule(h) != DECO_OK) {
+    delete h;
+    return DECO_E_DEVICE;
+  }
+  e = launch_fill_eta(const_cast<float*>(a.eta), p->B, p->eta, h->stream);
+  if (e == hipSuccess) e = launch_reset(a, a.acc, (long long)lay.R * h->G * p->B, p->score_every, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    delete h;
+    return DECO_E_DEVICE;
+  }
+  *out = h;
+  return DECO_OK;
+}
+
+deco_status deco_start(deco_handle* h, const deco_start_args* s) {
+  if (!h || !s) return DECO_E_INVAL;
+  if (h->poisoned) return DECO_E_STATE;
+  if (s->kind < DECO_INIT_USER || s->kind > DECO_INIT_MEAN) return DECO_E_INVAL;
+  if (s->kind == DECO_INIT_USER && !s->x0) return DECO_E_INVAL;
+  if (s->kind == DECO_INIT_MEAN && !s->mean_z) return DECO_E_INVAL;
+  if (!(s->scale > 0.0) || !(s->sigma2 >= 0.0) || !std::isfinite(s->scale) || !std::isfinite(s->sigma2))
+    return DECO_E_INVAL;
+  char* ws = h->ws;
+  const Layout& lay = h->lay;
+  int* lact = nullptr;
+  if (s->l_active) {
+    for (int b = 0; b < h->p.B; ++b)
+      if (s->l_active[b] < 0 || s->l_active[b] > h->p.l) return DECO_E_INVAL;
+    lact = reinterpret_cast<int*>(ws + lay.l_active);
+    HIP_TRY(h, hipMemcpyAsync(lact, s->l_active, sizeof(int) * h->p.B, hipMemcpyHostToDevice, h->stream));
+  }
+  int* goff_dev = reinterpret_cast<int*>(ws + lay.goff);
+  if (s->kind == DECO_INIT_USER) {
+    int* flags = reinterpret_cast<int*>(ws + lay.flags) + 1;
+    int nf = 0;
+    HIP_TRY(h, hipMemsetAsync(flags, 0, sizeof(int), h->stream));
+    HIP_TRY(h, launch_convert_user(s->x0, h->X, h->n * h->C, h->dtype, lact, h->C, h->p.B, flags, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(&nf, flags, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (nf) return DECO_E_NONFINITE;
+  } else {
+    InitArgs ia{};
+    ia.n = h->n;
+    ia.C = h->C;
+    ia.B = h->p.B;
+    ia.L = h->p.l;
+    ia.rp = h->g.row_ptr;
+    ia.ci = h->g.col_idx;
+    ia.w = h->g.w;
+    ia.goff = goff_dev;
+    ia.G = h->G;
+    ia.mean_z = s->mean_z;
+    ia.l_active = lact;
+    ia.scratch = reinterpret_cast<int8_t*>(ws + lay.xalt);
+    ia.scale = s->scale;
+    ia.sd = std::sqrt(s->sigma2);
+    ia.seed = h->p.seed;
+    ia.batch = s->batch;
+    ia.kind = s->kind;
+    ia.dtype = h->dtype;
+    ia.X = h->X;
+    double* thr = reinterpret_cast<double*>(ws + lay.thr);
+    int* delta = reinterpret_cast<int*>(ws + lay.delta);
+    if (s->kind == DECO_INIT_IDI || s->kind == DECO_INIT_DUI) {
+      // per-graph degree statistics on the host copy of row_ptr (Sec. 4.1)
+      std::vector<double> th(h->G);
+      std::vector<int> dl(h->G);
+      for (int gi = 0; gi < h->G; ++gi) {
+        const int r0 = h->goff_host[gi], r1 = h->goff_host[gi + 1];
+        const double cnt = (double)(r1 - r0);
+        double sum = 0.0;
+        int mx = 0;
+        for (int v = r0; v < r1; ++v) {
+          const int d = h->rp_host[v + 1] - h->rp_host[v];
+          sum += (double)d;
+          mx = std::max(mx, d);
+        }
+        const double mean = sum / cnt;
+        double ss = 0.0;
+        for (int v = r0; v < r1; ++v) {
+          const double dev = (double)(h->rp_host[v + 1] - h->rp_host[v]) - mean;
+          ss += dev * dev;
+        }
+        th[gi] = mean + s->beta * std::sqrt(ss / cnt);
+        dl[gi] = mx;
+      }
+      HIP_TRY(h, hipMemcpyAsync(thr, th.data(), sizeof(double) * h->G, hipMemcpyHostToDevice, h->stream));
+      HIP_TRY(h, hipMemcpyAsync(delta, dl.data(), sizeof(int) * h->G, hipMemcpyHostToDevice, h->stream));
+      HIP_TRY(h, hipStreamSynchronize(h->stream));
+    }
+    ia.thr = thr;
+    ia.delta = delta;
+    HIP_TRY(h, launch_init(ia, h->stream));
+  }
+  HIP_TRY(h, launch_reset(h->args, h->args.acc, (long long)h->R * h->G * h->p.B, h->p.score_every, h->stream));
+  h->t_host = 0;
+  return DECO_OK;
+}
+
+deco_status deco_set_eta(deco_handle* h, const float* eta_host) {
+  if (!h || !eta_host) return DECO_E_INVAL;
+  if (h->poisoned) return DECO_E_STATE;
+  for (int b = 0; b < h->p.B; ++b)
+    if (!std::isfinite(eta_host[b])) return DECO_E_NONFINITE;
+  HIP_TRY(h, hipMemcpyAsync(const_cast<float*>(h->args.eta), eta_host, sizeof(float) * h->p.B,
+                            hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return DECO_OK;
+}
+
+deco_status deco_step(deco_handle* h, int32_t steps, int32_t use_graph) {
+  if (!h || steps < 0) return DECO_E_INVAL;
+  if (h->poisoned) return DECO_E_STATE;
+  if (steps == 0) return DECO_OK;
+  if (!use_graph) {
+    deco_status st = launch_steps(h, steps, 1, 0);
+    if (st) return st;
+  } else {
+    if (h->stream == nullptr) return DECO_E_INVAL;
+    auto it = h->graphs.find(steps);
+    if (it == h->graphs.end()) {
+      hipGraph_t graph;
+      HIP_TRY(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      deco_status st = launch_steps(h, steps, 1, 0);
+      hipError_t e = hipStreamEndCapture(h->stream, &graph);
+      if (st) return st;
+      HIP_TRY(h, e);
+      hipGraphExec_t exec;
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      HIP_TRY(h, e);
+      it = h->graphs.emplace(steps, exec).first;
+    }
+    HIP_TRY(h, hipGraphLaunch(it->second, h->stream));
+  }
+  h->t_host += steps;
+  return DECO_OK;
+}
+
+deco_status deco_round_score(deco_handle* h, double* cut_out, uint8_t* bits_out) {
+  if (!h) return DECO_E_INVAL;
+  if (h->poisoned) return DECO_E_STATE;
+  deco_status st = launch_steps(h, 1, 0, 1);
+  if (st) return st;
+  const size_t gb = (size_t)h->G * h->p.B;
+  if (cut_out)
+    HIP_TRY(h, hipMemcpyAsync(cut_out, h->args.cur_cut, sizeof(double) * gb, hipMemcpyDeviceToDevice, h->stream));
+  if (bits_out)
+    HIP_TRY(h, hipMemcpyAsync(bits_out, h->args.bits[h->t_host & 1], (size_t)h->n * h->NBY,
+                              hipMemcpyDeviceToDevice, h->stream));
+  return DECO_OK;
+}
+
+deco_status deco_best(deco_handle* h, double* best_cut, int32_t* best_step, uint8_t* best_bits) {
+  if (!h || !best_cut) return DECO_E_INVAL;
+  if (h->poisoned) return DECO_E_STATE;
+  const size_t gb = (size_t)h->G * h->p.B;
+  const int* goff_dev = reinterpret_cast<int*>(h->ws + h->lay.goff);
+  HIP_TRY(h, launch_merge(h->args, h->n, goff_dev, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(best_cut, h->args.best_cut, sizeof(double) * gb, hipMemcpyDeviceToHost, h->stream));
+  if (best_step)
+    HIP_TRY(h, hipMemcpyAsync(best_step, h->args.best_step, sizeof(int) * gb, hipMemcpyDeviceToHost, h->stream));
+  if (best_bits)
+    HIP_TRY(h, hipMemcpyAsync(best_bits, h->args.best_bits, (size_t)h->n * h->NBY, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return DECO_OK;
+}
+
+deco_status deco_read_x(deco_handle* h, void* dst) {
+  if (!h || !dst) return DECO_E_INVAL;
+  if (h->poisoned) return DECO_E_STATE;
+  HIP_TRY(h, hipMemcpyAsync(dst, h->args.x[h->t_host & 1], (size_t)h->n * h->C * elem_size(h->dtype),
+                            hipMemcpyDeviceToDevice, h->stream));
+  return DECO_OK;
+}
+
+deco_status deco_set_trace(deco_handle* h, double* trace, int32_t capacity) {
+  if (!h || (trace && capacity < 1)) return DECO_E_INVAL;
+  h->args.trace = trace;
+  h->args.trace_cap = trace ? capacity : 1;
+  for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+  h->graphs.clear();
+  return DECO_OK;
+}
+
+int64_t deco_current_step(const deco_handle* h) { return h ? h->t_host : -1; }
+
+deco_status deco_autotune(deco_handle* h, int32_t steps) {
+  if (!h || steps < 1) return DECO_E_INVAL;
+  if (h->poisoned) return DECO_E_STATE;
+  const Schedule base = default_schedule(h);
+  std::vector<Schedule> cand;
+  const int vec = base.vec;
+  const int wmax = max_wc(vec, h->p.B);
+  for (int Wc = wmax; Wc >= 1 && Wc * vec >= std::min(8, h->p.B); Wc /= 2) {
+    if (Wc * 4 < wmax) break;
+    for (int split = 1; Wc * split <= 64; split *= 2) {
+      if (split > 1 && split * 2 > (double)h->nnz / (double)h->n) break;
+      for (int mode = 0; mode < 2; ++mode) {
+        if (mode == 1 && h->p.B / (Wc * vec) < 2) continue;
+        for (int bpx : {64, 128, 256}) {
+          Schedule s = base;
+          s.Wc = Wc;
+          s.split = split;
+          s.xcd_mode = mode;
+          s.blocks_per_xcd = bpx;
+          cand.push_back(s);
+        }
+      }
+    }
+  }
+  hipEvent_t e0, e1;
+  HIP_TRY(h, hipEventCreate(&e0));
+  HIP_TRY(h, hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  Schedule best = h->sched;
+  deco_start_args sa{};
+  sa.kind = DECO_INIT_UNIFORM;
+  sa.scale = 1.0;
+  for (auto& s : cand) {
+    if (!build_schedule(h, s)) continue;
+    h->sched = s;
+    if (upload_schedule(h) != DECO_OK) return DECO_E_DEVICE;
+    deco_status st = deco_start(h, &sa);
+    if (st) return st;
+    if ((st = launch_steps(h, 2, 1, 0))) return st;  // warm caches
+    HIP_TRY(h, hipEventRecord(e0, h->stream));
+    if ((st = launch_steps(h, steps, 1, 0))) return st;
+    HIP_TRY(h, hipEventRecord(e1, h->stream));
+    HIP_TRY(h, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = s;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->sched = best;
+  if (!build_schedule(h, h->sched)) return DECO_E_UNSUPPORTED;
+  deco_status st = upload_schedule(h);
+  if (st) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    Schedule keep = h->sched;
+    keep.items.clear();
+    g_cache[cache_key(h)] = keep;
+  }
+  return deco_start(h, &sa);
+}
+
+deco_status deco_schedule_string(const deco_handle* h, char* buf, int32_t cap) {
+  if (!h || !buf || cap < 1) return DECO_E_INVAL;
+  const Schedule& s = h->sched;
+  std::snprintf(buf, (size_t)cap,
+                "vec=%d Wc=%d split=%d tile=%d tiles=%d xcd_mode=%d grid=%d items=%d rows_per_item=%d "
+                "nnz_per_item=%d R=%d",
+                s.vec, s.Wc, s.split, s.Wc * s.vec, h->p.B / (s.Wc * s.vec), s.xcd_mode, s.grid, s.nitems,
+                s.rows_per_item, s.nnz_per_item, h->R);
+  return DECO_OK;
+}
+
+void deco_destroy(deco_handle* h) {
+  if (!h) return;
+  for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+  delete h;
+}
+
+void deco_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+  philox4x32_10(c, key[0], key[1]);
+  for (int i = 0; i < 4; ++i) out[i] = c[i];
+}
+
+deco_status deco_philox_device(uint32_t c1, uint32_t c2, uint32_t c3, uint64_t seed, int32_t count,
+                               uint32_t* out, void* stream) {
+  if (count < 0 || (count > 0 && !out)) return DECO_E_INVAL;
+  hipError_t e = launch_philox_test(c1, c2, c3, seed, count, out, reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? DECO_OK : DECO_E_DEVICE;
+}
+
+static double box_muller(uint32_t r0, uint32_t r1) {
+  const double u1 = ((double)(r0 >> 8) + 1.0) * (1.0 / 16777216.0);
+  const double u2 = (double)(r1 >> 8) * (1.0 / 16777216.0);
+  return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+}
+
+deco_status deco_evo_next(int32_t K, const double* fitness, const double* eq, const double* el,
+                          const int32_t* l, double lo, double hi, int32_t lmax, uint64_t seed,
+                          uint32_t round, double* eq_out, double* el_out, int32_t* l_out) {
+  if (K < 1 || !fitness || !eq || !el || !l || !eq_out || !el_out || !l_out || lmax < 1 || !(lo <= hi))
+    return DECO_E_INVAL;
+  std::vector<int> order(K);
+  for (int i = 0; i < K; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return fitness[a] > fitness[b]; });
+  const int keep = K / 2;
+  std::vector<double> q(K), m(K);
+  std::vector<int32_t> ll(K);
+  for (int i = 0; i < keep; ++i) {
+    q[i] = eq[order[i]];
+    m[i] = el[order[i]];
+    ll[i] = l[order[i]];
+  }
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  for (int i = keep; i < K; ++i) {
+    const int src = order[i - keep];
+    uint32_t c[4] = {round, (uint32_t)i, kSearch, 0u};
+    philox4x32_10(c, k0, k1);
+    const double a = eq[src] + 0.2 * box_muller(c[0], c[1]);
+    const double b = el[src] + 0.2 * box_muller(c[2], c[3]);
+    q[i] = std::min(hi, std::max(lo, a));
+    m[i] = std::min(hi, std::max(lo, b));
+    uint32_t d[4] = {round, (uint32_t)i, kSearch, 1u};
+    philox4x32_10(d, k0, k1);
+    const int nl = l[src] + (int)(d[0] % 3u) - 1;
+    ll[i] = std::min(lmax, std::max(1, nl));
+  }
+  for (int i = 0; i < K; ++i) {
+    eq_out[i] = q[i];
+    el_out[i] = m[i];
+    l_out[i] = ll[i];
+  }
+  return DECO_OK;
+}
+
+}  // extern "C"
+
+struct deco_solver {
+  deco_graph g{};
+  deco_solve_params p{};
+  hipStream_t s = nullptr;
+  char* mem = nullptr;
+  deco_handle* hq = nullptr;
+  deco_handle* hl = nullptr;
+  uint8_t* mean_dev = nullptr;
+  int B = 0, K = 0, per = 0, G = 1, lmax = 1, NBY = 1;
+  long long n = 0;
+  std::vector<double> eq, el, gbest, fit, fitg, bc, target;
+  std::vector<int32_t> lk, lact;
+  std::vector<uint8_t> best_z, zmean, bits;
+  std::vector<float> eta;
+  std::vector<int> goff;
+  int round = 0;
+  uint32_t batch = 0;
+  long long steps_done = 0;
+  double eu = 0.0;
+};
+
+namespace {
+
+void solver_free(deco_solver* v) {
+  if (!v) return;
+  if (v->hq) deco_destroy(v->hq);
+  if (v->hl) deco_destroy(v->hl);
+  if (v->mem) {
+    (void)hipStreamSynchronize(v->s);
+    (void)hipFree(v->mem);
+  }
+  delete v;
+}
+
+// Fold one batch's best into the global best, update member fitness (max over the
+// member's columns, per graph), and make the batch's best vector the next mean (Sec. 4.2).
+deco_status absorb(deco_solver* v, deco_handle* h) {
+  deco_status r = deco_best(h, v->bc.data(), nullptr, v->bits.data());
+  if (r) return r;
+  const int B = v->B, K = v->K, G = v->G;
+  for (int gi = 0; gi < G; ++gi) {
+    int arg = 0;
+    for (int b = 1; b < B; ++b)
+      if (v->bc[(size_t)gi * B + b] > v->bc[(size_t)gi * B + arg]) arg = b;
+    const double best = v->bc[(size_t)gi * B + arg];
+    const bool better = best > v->gbest[gi];
+    for (int row = v->goff[gi]; row < v->goff[gi + 1]; ++row) {
+      const uint8_t z = (v->bits[(size_t)row * v->NBY + arg / 8] >> (arg % 8)) & 1;
+      v->zmean[row] = z;
+      if (better) v->best_z[row] = z;
+    }
+    if (better) v->gbest[gi] = best;
+    for (int k = 0; k < K; ++k)
+      for (int b = k * v->per; b < (k + 1) * v->per; ++b)
+        v->fitg[(size_t)k * G + gi] = std::max(v->fitg[(size_t)k * G + gi], v->bc[(size_t)gi * B + b]);
+  }
+  if (hipMemcpyAsync(v->mean_dev, v->zmean.data(), (size_t)v->n, hipMemcpyHostToDevice, v->s) != hipSuccess)
+    return DECO_E_DEVICE;
+  return DECO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+deco_status deco_solver_create(deco_solver** out, const deco_graph* g, const deco_solve_params* sp, void* stream) {
+  if (!out) return DECO_E_INVAL;
+  *out = nullptr;
+  deco_status st = check_graph_args(g);
+  if (st) return st;
+  if (!sp) return DECO_E_INVAL;
+  if (sp->K < 1 || sp->B < 1 || sp->B % sp->K != 0 || sp->l_max < 1 || sp->l_max > 4 || sp->T_q < 0 ||
+      sp->T_l < 0 || sp->evo_rounds < 0 || !(sp->scale > 0.0) || !(sp->sigma2 >= 0.0))
+    return DECO_E_INVAL;
+  if (sp->init_kind != DECO_INIT_IDI && sp->init_kind != DECO_INIT_DUI && sp->init_kind != DECO_INIT_UNIFORM)
+    return DECO_E_INVAL;
+  if (!supported_B(sp->B)) return DECO_E_UNSUPPORTED;
+  deco_solver* v = new deco_solver();
+  v->g = *g;
+  v->p = *sp;
+  v->p.eq0 = v->p.el0 = nullptr;
+  v->p.l0 = nullptr;
+  v->p.target_cut = nullptr;
+  v->s = reinterpret_cast<hipStream_t>(stream);
+  v->B = sp->B;
+  v->K = sp->K;
+  v->per = sp->B / sp->K;
+  v->G = g->num_graphs;
+  v->lmax = sp->l_max;
+  v->NBY = nby_of(sp->B);
+  v->n = g->n;
+  deco_params pq{};
+  pq.B = v->B;
+  pq.l = 1;
+  pq.lifted = 0;
+  pq.grad_form = sp->grad_form;
+  pq.x_dtype = sp->x_dtype;
+  pq.score_every = 1;
+  pq.eta = 0.1f;
+  pq.seed = sp->seed;
+  deco_params pl = pq;
+  pl.l = v->lmax;
+  pl.lifted = 1;
+  size_t wq = 0, wl = 0;
+  if ((st = deco_workspace_size(g, &pq, &wq)) || (st = deco_workspace_size(g, &pl, &wl))) {
+    delete v;
+    return st;
+  }
+  const size_t es = elem_size(sp->x_dtype);
+  const size_t xq_b = align_up((size_t)v->n * v->B * es), xl_b = align_up((size_t)v->n * v->lmax * v->B * es);
+  const size_t total = xq_b + xl_b + align_up(wq) + align_up(wl) + align_up((size_t)v->n);
+  if (hipMalloc(&v->mem, total) != hipSuccess) {
+    v->mem = nullptr;
+    solver_free(v);
+    return DECO_E_NOMEM;
+  }
+  char* xq = v->mem;
+  char* xl = xq + xq_b;
+  char* wsq = xl + xl_b;
+  char* wsl = wsq + align_up(wq);
+  v->mean_dev = reinterpret_cast<uint8_t*>(wsl + align_up(wl));
+  if ((st = deco_init(&v->hq, g, &pq, xq, wsq, wq, stream)) || (st = deco_init(&v->hl, g, &pl, xl, wsl, wl, stream))) {
+    solver_free(v);
+    return st;
+  }
+  if (sp->autotune) {
+    if ((st = deco_autotune(v->hq, 10)) || (st = deco_autotune(v->hl, 10))) {
+      solver_free(v);
+      return st;
+    }
+  }
+  const int K = v->K;
+  v->eq.resize(K);
+  v->el.resize(K);
+  v->lk.resize(K);
+  for (int k = 0; k < K; ++k) {
+    v->eq[k] = sp->eq0 ? sp->eq0[k] : -1.0;
+    v->el[k] = sp->el0 ? sp->el0[k] : -3.0;
+    v->lk[k] = std::min(v->lmax, std::max(1, sp->l0 ? sp->l0[k] : 2));
+  }
+  if (sp->target_cut) v->target.assign(sp->target_cut, sp->target_cut + v->G);
+  v->bc.resize((size_t)v->G * v->B);
+  v->bits.resize((size_t)v->n * v->NBY);
+  v->zmean.assign((size_t)v->n, 0);
+  v->best_z.assign((size_t)v->n, 0);
+  v->gbest.assign(v->G, -INFINITY);
+  v->fit.resize(K);
+  v->fitg.resize((size_t)K * v->G);
+  v->eta.resize(v->B);
+  v->lact.resize(v->B);
+  v->goff.assign(v->G + 1, 0);
+  if (g->graph_row_offset) {
+    if (hipMemcpy(v->goff.data(), g->graph_row_offset, sizeof(int) * (v->G + 1), hipMemcpyDeviceToHost) !=
+        hipSuccess) {
+      solver_free(v);
+      return DECO_E_DEVICE;
+    }
+  } else {
+    v->goff[1] = (int)v->n;
+  }
+  *out = v;
+  return DECO_OK;
+}
+
+deco_status deco_solver_run(deco_solver* v, int32_t rounds, double* best_cut, uint8_t* best_z, double* round_time,
+                            double* round_best, deco_solve_report* report) {
+  if (!v || rounds < 0) return DECO_E_INVAL;
+  const double t_start = now_s();
+  const deco_solve_params& sp = v->p;
+  const int B = v->B, K = v->K, G = v->G;
+  deco_status st;
+  int done_here = 0;
+  for (int rr = 0; rr < rounds; ++rr) {
+    const int r = v->round;
+    std::fill(v->fitg.begin(), v->fitg.end(), -INFINITY);
+    // 1. unlifted batch (Alg. 1): member k's columns step with 10^eq[k]
+    for (int b = 0; b < B; ++b) v->eta[b] = (float)std::pow(10.0, v->eq[b / v->per]);
+    if ((st = deco_set_eta(v->hq, v->eta.data()))) return st;
+    deco_start_args sa{};
+    sa.kind = r == 0 ? sp.init_kind : DECO_INIT_MEAN;
+    sa.mean_z = v->mean_dev;
+    sa.scale = (sp.init_kind == DECO_INIT_UNIFORM && r == 0) ? 1.0 : sp.scale;
+    sa.sigma2 = sp.sigma2;
+    sa.beta = sp.beta;
+    sa.batch = v->batch++;
+    if ((st = deco_start(v->hq, &sa))) return st;
+    if ((st = deco_step(v->hq, sp.T_q, sp.use_graph))) return st;
+    if ((st = deco_round_score(v->hq, nullptr, nullptr))) return st;
+    if ((st = absorb(v, v->hq))) return st;
+    v->steps_done += sp.T_q;
+    v->eu += (double)v->g.nnz * B * sp.T_q;
+    // 2. lift its best vector (Alg. 3 step 2) and run the lifted batch (Alg. 2); member k
+    //    keeps lk[k] of the lmax components and steps with 10^el[k]; 3. project back
+    for (int b = 0; b < B; ++b) {
+      v->eta[b] = (float)std::pow(10.0, v->el[b / v->per]);
+      v->lact[b] = v->lk[b / v->per];
+    }
+    if ((st = deco_set_eta(v->hl, v->eta.data()))) return st;
+    sa.kind = DECO_INIT_MEAN;
+    sa.scale = sp.scale;
+    sa.batch = v->batch++;
+    sa.l_active = v->lact.data();
+    if ((st = deco_start(v->hl, &sa))) return st;
+    if ((st = deco_step(v->hl, sp.T_l, sp.use_graph))) return st;
+    if ((st = deco_round_score(v->hl, nullptr, nullptr))) return st;
+    if ((st = absorb(v, v->hl))) return st;
+    v->steps_done += sp.T_l;
+    v->eu += (double)v->g.nnz * B * v->lmax * sp.T_l;
+    for (int k = 0; k < K; ++k) {
+      v->fit[k] = 0.0;
+      for (int gi = 0; gi < G; ++gi) v->fit[k] += v->fitg[(size_t)k * G + gi];
+    }
+    if (round_time) round_time[rr] = now_s() - t_start;
+    if (round_best)
+      for (int gi = 0; gi < G; ++gi) round_best[(size_t)rr * G + gi] = v->gbest[gi];
+    // 4. evolutionary search between batches (Sec. 4.3)
+    if (r < sp.evo_rounds) {
+      std::vector<double> q(K), m(K);
+      std::vector<int32_t> ll(K);
+      if ((st = deco_evo_next(K, v->fit.data(), v->eq.data(), v->el.data(), v->lk.data(), -4.0, -1.0, v->lmax,
+                              sp.seed, (uint32_t)r, q.data(), m.data(), ll.data())))
+        return st;
+      v->eq = q;
+      v->el = m;
+      v->lk = ll;
+      if (r == sp.evo_rounds - 1)
+        for (int k = 1; k < K; ++k) {
+          v->eq[k] = v->eq[0];
+          v->el[k] = v->el[0];
+          v->lk[k] = v->lk[0];
+        }
+    }
+    v->round++;
+    done_here++;
+    bool stop = sp.time_budget_s > 0 && now_s() - t_start >= sp.time_budget_s;
+    if (!v->target.empty()) {
+      bool all = true;
+      for (int gi = 0; gi < G; ++gi) all = all && v->gbest[gi] >= v->target[gi];
+      stop = stop || all;
+    }
+    if (stop) break;
+  }
+  if (best_cut)
+    for (int gi = 0; gi < G; ++gi) best_cut[gi] = v->gbest[gi];
+  if (best_z) std::memcpy(best_z, v->best_z.data(), (size_t)v->n);
+  if (report) {
+    report->rounds_done = done_here;
+    report->steps_done = v->steps_done;
+    report->edge_updates = v->eu;
+    report->seconds = now_s() - t_start;
+    report->eq_best = v->eq[0];
+    report->el_best = v->el[0];
+    report->l_best = v->lk[0];
+  }
+  return DECO_OK;
+}
+
+deco_status deco_solver_set_target(deco_solver* v, const double* target_cut) {
+  if (!v) return DECO_E_INVAL;
+  if (target_cut)
+    v->target.assign(target_cut, target_cut + v->G);
+  else
+    v->target.clear();
+  return DECO_OK;
+}
+
+void deco_solver_destroy(deco_solver* v) { solver_free(v); }
+
+deco_status deco_solve(const deco_graph* g, const deco_solve_params* sp, void* stream, double* best_cut,
+                       uint8_t* best_z, double* round_time, double* round_best, deco_solve_report* report) {
+  if (!sp || !best_cut || !best_z) return DECO_E_INVAL;
+  if (sp->rounds < 1) return DECO_E_INVAL;
+  const double t0 = now_s();
+  deco_solver* v = nullptr;
+  deco_status st = deco_solver_create(&v, g, sp, stream);
+  if (st) return st;
+  st = deco_solver_run(v, sp->rounds, best_cut, best_z, round_time, round_best, report);
+  if (!st && report) report->seconds = now_s() - t0;
+  solver_free(v);
+  return st;
+}
+
+}  // extern "C"

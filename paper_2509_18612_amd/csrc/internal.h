@@ -1,0 +1,112 @@
+// Internal interface between the host side (api.hip) and the kernels (kernels.hip) of the
+// DECO library. Not installed; the public ABI is include/deco.h.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace deco {
+
+// Device-resident control block of one handle. The step kernels read it at their start
+// and the last workgroup of every step updates it, so a captured graph of step launches
+// can be replayed without host involvement.
+struct DevCtrl {
+  unsigned int ticket;  // workgroups that finished the current launch
+  int pending_slot;     // bit slot whose improvements are not yet folded into best_bits
+  long long t;          // index of the current iterate
+  int score_every;
+  int pad;
+};
+
+// One work item: rows [x, y) of graph z, initialisation tile w.
+// Items are grouped by XCD: items[seg[x] .. seg[x+1]) run on workgroups with
+// blockIdx % 8 == x.
+
+struct StepArgs {
+  const int* rp;
+  const int* ci;
+  const float* w;   // NULL = unit weights
+  const float* dw;  // weighted degree (Laplacian form), may be NULL for the cut form
+  void* x[2];       // ping-pong iterates; x[t & 1] holds X_t
+  int C, B, L, lifted;
+  int Wc, split;    // lanes per row sub-group, sub-groups per row
+  const int4* items;
+  const int* seg;   // [9]
+  float cW, cD;     // G = cW * (W X) + cD * (d_w . X)
+  const float* eta; // [B]
+  uint8_t* bits[2]; // cut bits of the iterate scored at step t live in bits[t & 1]
+  uint8_t* best_bits;
+  uint8_t* mask;    // [G][NBY] improvements of the last scored step
+  int NBY;
+  double* acc;      // [R][G][B] partial sums of w 1{z_v != z_u}
+  int R, G;
+  double* cur_cut;  // [G][B]
+  double* best_cut; // [G][B]
+  int* best_step;   // [G][B]
+  double* trace;    // optional [trace_cap][G][B]
+  int trace_cap;
+  DevCtrl* ctrl;
+  int do_update;    // 0: score-only pass (no new iterate, step counter unchanged)
+  int force_score;  // score this launch regardless of score_every
+};
+
+// Kernel launchers (kernels.hip). dtype: 0 float32, 1 bfloat16. vec: elements per lane
+// per load (the native 16-byte width, or 1).
+hipError_t launch_step(const StepArgs& a, int dtype, int vec, bool unit, int grid,
+                       hipStream_t s);
+int native_vec(int dtype);
+
+hipError_t launch_validate(long long n, const int* rp, const int* ci, const float* w,
+                           const int* goff, int G, float* dw, int* flags, hipStream_t s);
+hipError_t launch_reset(StepArgs a, double* acc_all, long long acc_count, int score_every,
+                        hipStream_t s);
+hipError_t launch_merge(StepArgs a, long long n, const int* goff, hipStream_t s);
+hipError_t launch_fill_eta(float* eta, int B, float v, hipStream_t s);
+
+struct InitArgs {
+  long long n;
+  int C, B, L;
+  const int* rp;
+  const int* ci;
+  const float* w;
+  const int* goff;   // [G+1] device
+  int G;
+  const double* thr; // IDI threshold per graph [G]
+  const int* delta;  // max degree per graph [G]
+  const uint8_t* mean_z;
+  const int* l_active; // device [B] or NULL
+  int8_t* scratch;   // n*C bytes (IDI important signs)
+  double scale, sd;
+  unsigned long long seed;
+  unsigned batch;
+  int kind;
+  int dtype;
+  void* X;
+};
+hipError_t launch_init(const InitArgs& a, hipStream_t s);
+hipError_t launch_convert_user(const void* x0, void* X, long long count, int dtype,
+                               const int* l_active, int C, int B, int* nonfinite,
+                               hipStream_t s);
+hipError_t launch_philox_test(uint32_t c1, uint32_t c2, uint32_t c3, unsigned long long seed,
+                              int count, uint32_t* out, hipStream_t s);
+
+// Counter-based generator shared by host and device code of the library.
+__host__ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[1] = (uint32_t)p1;
+    c[3] = (uint32_t)p0;
+    c[0] = n0;
+    c[2] = n2;
+  }
+}
+
+enum Purpose : uint32_t { kUniform = 1, kDui = 2, kIdiSign = 3, kIdiTie = 4, kGauss = 5, kSearch = 6 };
+
+}  // namespace deco

@@ -1,0 +1,90 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports every entry
+point that include/deco.h declares, and its host utilities agree with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_18612_amd import deco
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "deco.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(deco_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_named_entry_points():
+    names = declared_functions()
+    for required in ["deco_init", "deco_step", "deco_round_score", "deco_solve", "deco_best", "deco_start",
+                     "deco_destroy", "deco_workspace_size", "deco_status_string"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = deco.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert set(deco.EXPORTS) == set(declared_functions())
+
+
+def test_status_strings():
+    for s in [0, -1, -2, -3, -4, -5, -6]:
+        assert deco.status_string(s) and deco.status_string(s) != "unknown status"
+    assert deco.status_string(-99) == "unknown status"
+
+
+def test_host_philox_matches_published_vectors(golden_dir):
+    with open(os.path.join(golden_dir, "philox4x32_10_kat.txt")) as f:
+        for ln in f:
+            if ln.startswith("#") or not ln.strip():
+                continue
+            t = [int(x, 16) for x in ln.split()]
+            assert [int(x) for x in deco.philox(t[0:4], t[4:6])] == t[6:10]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 12345])
+def test_evolution_step_matches_oracle_exactly(seed):
+    rng = np.random.default_rng(seed)
+    for rnd in range(5):
+        K = 8
+        fit = rng.integers(0, 5, K).astype(float)  # ties on purpose
+        eq = rng.uniform(-4, -1, K)
+        el = rng.uniform(-4, -1, K)
+        lk = rng.integers(1, 5, K).astype(np.int32)
+        a = deco.evo_next(fit, eq, el, lk, seed, rnd)
+        b = oracle.evo_next(fit, eq, el, lk, seed, rnd)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_workspace_size_and_argument_errors_without_device():
+    g = deco.deco_graph(100, 400, 1, 1, None, 1, None)  # fake non-null pointers, never dereferenced
+    import ctypes as ct
+    nb = ct.c_size_t(0)
+    p = deco.deco_params(16, 1, 0, 0, 0, 1, 0.1, 0)
+    assert deco.lib().deco_workspace_size(ct.byref(g), ct.byref(p), ct.byref(nb)) == 0 and nb.value > 0
+    bad = [deco.deco_params(3, 1, 0, 0, 0, 1, 0.1, 0),   # B = 3 unsupported
+           deco.deco_params(16, 5, 1, 0, 0, 1, 0.1, 0),  # l = 5 unsupported
+           deco.deco_params(16, 2, 0, 0, 0, 1, 0.1, 0),  # l > 1 needs lifted rounding
+           deco.deco_params(16, 1, 0, 7, 0, 1, 0.1, 0),  # bad gradient form
+           deco.deco_params(16, 1, 0, 0, 0, 0, 0.1, 0),  # score_every = 0
+           deco.deco_params(16, 1, 0, 0, 0, 1, float("nan"), 0)]
+    want = [deco.E_UNSUPPORTED, deco.E_UNSUPPORTED, deco.E_INVAL, deco.E_INVAL, deco.E_INVAL, deco.E_NONFINITE]
+    for q, w in zip(bad, want):
+        assert deco.lib().deco_workspace_size(ct.byref(g), ct.byref(q), ct.byref(nb)) == w
+    big = deco.deco_graph(100, 2 ** 31, 1, 1, None, 1, None)
+    assert deco.lib().deco_workspace_size(ct.byref(big), ct.byref(p), ct.byref(nb)) == deco.E_UNSUPPORTED
+    empty = deco.deco_graph(0, 0, 1, 1, None, 1, None)
+    assert deco.lib().deco_workspace_size(ct.byref(empty), ct.byref(p), ct.byref(nb)) == deco.E_INVAL
+
+
+def test_bits_round_trip():
+    rng = np.random.default_rng(0)
+    for B in [1, 2, 4, 8, 24, 64]:
+        z = rng.integers(0, 2, (37, B)).astype(np.uint8)
+        assert np.array_equal(deco.bits_to_z(deco.z_to_bits(z), B), z)

@@ -1,0 +1,365 @@
+"""GPU parity of the fused step kernel against the CPU oracle (through the C ABI).
+
+Floating point: teacher forcing. For every step t the oracle's FP64 step from the GPU's
+own X_t must agree with the GPU's X_{t+1} to 1e-5 (the per-step bound for float32
+iterates), or to the float32 summation bound where a high-degree row makes that larger
+(Higham's gamma_k bound, reported). Cuts: the GPU's cut of its own sign vector equals
+the oracle's eq. (1) cut of that vector bit for bit. Running best: equal to the oracle's
+bookkeeping over the GPU's cut sequence. BF16 storage: within one bfloat16 ulp of the
+oracle's emulation (exact step, rounded to float32 then to bfloat16).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_18612_amd import deco, synth
+
+from gpu_util import bf16_ulp, oracle_cuts, run_teacher_forced, step_bound, to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+
+def cw_of(form):
+    return -0.5 if form == deco.GRAD_CUT else -1.0
+
+
+def check_run(g, B, steps, l=1, lifted=False, form=deco.GRAD_CUT, dtype=deco.F32, eta=0.1, x0=None, seed=3,
+              schedule_tune=False, eta_per_init=None):
+    r = run_teacher_forced(g, B, steps, l, lifted, form, dtype, eta, x0, seed, schedule_tune, eta_per_init)
+    xs = r["xs"]
+    C = l * B
+    eta_cols = (np.full(C, eta) if eta_per_init is None
+                else np.tile(np.asarray(eta_per_init, np.float32).astype(np.float64), l))
+    worst = 0.0
+    widened = 0
+    G = 1 if g.graph_row_offset is None else len(g.graph_row_offset) - 1
+    gbest = np.full((G, B), -np.inf)
+    gstep = np.full((G, B), -1)
+    for t in range(steps + 1):
+        cuts, z = oracle_cuts(g, xs[t], B, l, lifted)
+        # exact cut of the GPU's own sign vector, per graph and initialisation
+        assert np.array_equal(r["trace"][t], cuts), f"cut mismatch at step {t}"
+        imp = cuts > gbest
+        gbest[imp] = cuts[imp]
+        gstep[imp] = t
+        if t == steps:
+            break
+        want = oracle.step(g, xs[t], eta_cols, form)
+        if dtype == deco.BF16:
+            emu = oracle.to_bf16(want.astype(np.float32)).astype(np.float64)
+            tol = bf16_ulp(emu) + step_bound(g, xs[t], eta_cols, cw_of(form), form)
+            diff = np.abs(xs[t + 1] - emu)
+        else:
+            bound = step_bound(g, xs[t], eta_cols, cw_of(form), form)
+            tol = np.maximum(1e-5, bound)
+            widened += int((bound > 1e-5).sum())
+            diff = np.abs(xs[t + 1] - want)
+        worst = max(worst, float(diff.max()))
+        bad = diff > tol
+        assert not bad.any(), f"step {t}: {bad.sum()} elements off, max {diff.max():.3e}"
+    # final iterate scored by round_score, then the running best
+    assert np.array_equal(r["cut_T"], oracle_cuts(g, xs[steps], B, l, lifted)[0])
+    bc, bs, bb = r["best"]
+    assert np.array_equal(bc, gbest)
+    assert np.array_equal(bs, gstep)
+    zb = deco.bits_to_z(bb, B)
+    for gi in range(G):
+        for b in range(B):
+            zt = oracle.round_signs(xs[gstep[gi, b]], B, l, lifted)
+            r0 = 0 if g.graph_row_offset is None else g.graph_row_offset[gi]
+            r1 = g.n if g.graph_row_offset is None else g.graph_row_offset[gi + 1]
+            assert np.array_equal(zb[r0:r1, b], zt[r0:r1, b])
+    # the best vector's cut, recomputed from its bits
+    assert np.array_equal(oracle.cut_batch(g, zb), bc)
+    r["handle"].destroy()
+    return worst, widened, r["schedule"]
+
+
+CASES = {
+    "er_unit_B16": (lambda: synth.erdos_renyi(500, 0.05, 1), 16, {}),
+    "ba_hubs_B64": (lambda: synth.barabasi_albert(600, 3, 2), 64, {}),
+    "er_pm1_B24_tiles": (lambda: synth.with_rademacher_weights(synth.erdos_renyi(400, 0.1, 3), 4), 24, {}),
+    "laplacian_B16": (lambda: synth.erdos_renyi(400, 0.05, 6), 16, dict(form=deco.GRAD_LAPLACIAN, eta=0.01)),
+    "lifted_l2_B16": (lambda: synth.erdos_renyi(400, 0.06, 7), 16, dict(l=2, lifted=True)),
+    "lifted_l3_B8": (lambda: synth.barabasi_albert(300, 4, 8), 8, dict(l=3, lifted=True)),
+    "lifted_l4_B32": (lambda: synth.erdos_renyi(300, 0.05, 9), 32, dict(l=4, lifted=True)),
+    "B1": (lambda: synth.erdos_renyi(200, 0.05, 10), 1, {}),
+    "B2": (lambda: synth.erdos_renyi(200, 0.05, 11), 2, {}),
+    "B4_lifted": (lambda: synth.erdos_renyi(200, 0.05, 12), 4, dict(l=2, lifted=True)),
+    "B256_wide": (lambda: synth.barabasi_albert(400, 4, 13), 256, {}),
+    "unlifted_as_l1_lifted": (lambda: synth.erdos_renyi(300, 0.05, 14), 16, dict(l=1, lifted=True)),
+    "per_init_eta": (lambda: synth.erdos_renyi(300, 0.06, 15), 16,
+                     dict(eta_per_init=np.geomspace(1e-3, 0.3, 16).astype(np.float32))),
+}
+
+
+def _intw_graph():
+    g = synth.erdos_renyi(300, 0.08, 5)
+    m = g.nnz // 2
+    return synth.with_weights(g, np.random.default_rng(1).integers(1, 5, m).astype(np.float32))
+
+
+CASES["er_intw_B8"] = (_intw_graph, 8, {})
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_fp32_teacher_forced_parity(name):
+    make, B, kw = CASES[name]
+    g = make()
+    worst, widened, sched = check_run(g, B, 30, **kw)
+    print(f"{name}: max |dX| = {worst:.2e}, rows on the gamma_k bound: {widened}, schedule: {sched}")
+
+
+@pytest.mark.parametrize("name", ["er_unit_B16", "ba_hubs_B64", "lifted_l2_B16", "er_pm1_B24_tiles",
+                                  "laplacian_B16"])
+def test_bf16_teacher_forced_parity(name):
+    make, B, kw = CASES[name]
+    g = make()
+    worst, _, sched = check_run(g, B, 20, dtype=deco.BF16, **kw)
+    print(f"{name} bf16: max |dX| = {worst:.2e}, schedule: {sched}")
+
+
+def test_float_weights_cut_within_bound():
+    g = synth.erdos_renyi(300, 0.06, 21)
+    m = g.nnz // 2
+    g = synth.with_weights(g, np.random.default_rng(3).uniform(0.1, 2.0, m).astype(np.float32))
+    r = run_teacher_forced(g, 16, 10)
+    for t, X in enumerate(r["xs"]):
+        cuts, _ = oracle_cuts(g, X, 16, 1, False)
+        tol = g.nnz * 2.0 ** -52 * np.abs(g.w).sum()
+        assert np.all(np.abs(r["trace"][t] - cuts) <= tol)
+        want = oracle.step(g, X, 0.1) if t < 10 else None
+        if want is not None:
+            assert np.abs(r["xs"][t + 1] - want).max() <= 1e-5
+    r["handle"].destroy()
+
+
+def test_multi_graph_batch_parity():
+    gs = [synth.erdos_renyi(150, 0.1, 1), synth.barabasi_albert(220, 3, 2), synth.cycle(9), synth.star(40),
+          synth.erdos_renyi(90, 0.2, 3)]
+    bd = synth.block_diagonal(gs)
+    worst, _, sched = check_run(bd, 8, 25)
+    print(f"multi-graph: {worst:.2e} {sched}")
+
+
+def test_autotuned_schedule_keeps_parity():
+    g = synth.barabasi_albert(3000, 4, 5)
+    worst, _, sched = check_run(g, 64, 8, schedule_tune=True)
+    print(f"autotuned: {sched}, {worst:.2e}")
+
+
+def test_negated_start_gives_bitwise_negated_trajectory():
+    g = synth.barabasi_albert(500, 3, 1)
+    x0 = synth.uniform_batch(g.n, 32, 9)
+    a = run_teacher_forced(g, 32, 15, x0=x0)
+    b = run_teacher_forced(g, 32, 15, x0=-x0)
+    for xa, xb in zip(a["xs"], b["xs"]):
+        assert np.array_equal(xa, -xb)
+    if not any(np.any(x == 0) for x in a["xs"]):
+        assert np.array_equal(a["trace"], b["trace"])
+    a["handle"].destroy()
+    b["handle"].destroy()
+
+
+def test_lifted_columns_equal_unlifted_runs_bitwise():
+    g = synth.erdos_renyi(400, 0.05, 2)
+    B, l = 16, 3
+    x0 = synth.uniform_batch(g.n, l * B, 4)
+    lifted = run_teacher_forced(g, B, 10, l=l, lifted=True, x0=x0)
+    for i in range(l):
+        un = run_teacher_forced(g, B, 10, x0=np.ascontiguousarray(x0[:, i * B:(i + 1) * B]))
+        for xl, xu in zip(lifted["xs"], un["xs"]):
+            assert np.array_equal(xl[:, i * B:(i + 1) * B], xu)
+        un["handle"].destroy()
+    lifted["handle"].destroy()
+
+
+def test_determinism_bitwise():
+    g = synth.barabasi_albert(2000, 3, 3)
+    a = run_teacher_forced(g, 64, 12)
+    b = run_teacher_forced(g, 64, 12)
+    for xa, xb in zip(a["xs"], b["xs"]):
+        assert np.array_equal(xa, xb)
+    assert np.array_equal(a["trace"], b["trace"])
+    for u, v in zip(a["best"], b["best"]):
+        assert np.array_equal(u, v)
+    a["handle"].destroy()
+    b["handle"].destroy()
+
+
+def test_score_every_and_graph_replay():
+    g = synth.erdos_renyi(600, 0.03, 5)
+    B = 32
+    G = deco.Graph(g)
+    h = deco.Handle(G, B=B, eta=0.1, score_every=5, seed=2)
+    x0 = torch.from_numpy(synth.uniform_batch(g.n, B, 1)).cuda()
+    h.start(deco.INIT_USER, x0=x0)
+    tr = h.set_trace(64)
+    xs = [to_np(h.read_x()).astype(np.float64)]
+    for _ in range(20):
+        h.step(1)
+        xs.append(to_np(h.read_x()).astype(np.float64))
+    trn = tr.cpu().numpy()
+    for t in range(20):
+        if t % 5 == 0:
+            assert np.array_equal(trn[t], oracle_cuts(g, xs[t], B, 1, False)[0])
+        else:
+            assert np.all(np.isnan(trn[t]))
+    # the same 20 steps replayed through a captured graph give the same iterate
+    h2 = deco.Handle(G, B=B, eta=0.1, score_every=5, seed=2)
+    h2.start(deco.INIT_USER, x0=x0)
+    h2.step(10, use_graph=True)
+    h2.step(10, use_graph=True)
+    assert h2.current_step() == 20
+    assert np.array_equal(to_np(h2.read_x()).astype(np.float64), xs[20])
+    b1 = h.best()
+    b2 = h2.best()
+    for u, v in zip(b1, b2):
+        assert np.array_equal(u, v)
+    # replays of one graph, with eager work between them, agree with eager steps
+    h3 = deco.Handle(G, B=B, eta=0.1, score_every=5, seed=2)
+    h3.start(deco.INIT_USER, x0=x0)
+    for _ in range(4):
+        h3.step(5, use_graph=True)
+        h3.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()
+    assert np.array_equal(to_np(h3.read_x()).astype(np.float64), xs[20])
+    for hh in (h, h2, h3):
+        hh.destroy()
+
+
+def test_start_kinds_match_oracle():
+    g = synth.barabasi_albert(700, 3, 4)
+    B = 32
+    seed = 77
+    G = deco.Graph(g)
+    h = deco.Handle(G, B=B, seed=seed)
+    h.start(deco.INIT_UNIFORM, batch=3)
+    x = to_np(h.read_x()).astype(np.float64)
+    assert np.array_equal(x, oracle.init_uniform(g.n, B, seed, 3))
+    # IDI signs: with no noise the start is h / scale exactly
+    h.start(deco.INIT_IDI, scale=1.0, sigma2=0.0, beta=0.2, batch=5)
+    x = to_np(h.read_x()).astype(np.float64)
+    assert np.array_equal(x, oracle.init_idi(g, B, seed, 5, 0.2))
+    # DUI and the Gaussian exploration around a mean: within float rounding
+    h.start(deco.INIT_DUI, scale=1.0, sigma2=0.0, batch=6)
+    x = to_np(h.read_x()).astype(np.float64)
+    assert np.abs(x - oracle.init_dui(g, B, seed, 6)).max() <= 2 ** -23
+    h.start(deco.INIT_IDI, scale=1e4, sigma2=0.8, beta=0.2, batch=7)
+    x = to_np(h.read_x()).astype(np.float64)
+    want = oracle.init_gauss(oracle.init_idi(g, B, seed, 7, 0.2), 0.8, 1e4, seed, 7)
+    assert np.all(np.abs(x - want) <= 2 * np.spacing(np.abs(want).astype(np.float32)).astype(np.float64))
+    z = torch.from_numpy((np.arange(g.n) % 3 == 0).astype(np.uint8)).cuda()
+    h.start(deco.INIT_MEAN, mean_z=z, scale=2.0, sigma2=0.5, batch=8)
+    x = to_np(h.read_x()).astype(np.float64)
+    M = np.repeat(np.where(z.cpu().numpy() == 1, 1.0, -1.0)[:, None], B, 1)
+    want = oracle.init_gauss(M, 0.5, 2.0, seed, 8)
+    assert np.all(np.abs(x - want) <= 2 * np.spacing(np.abs(want).astype(np.float32)).astype(np.float64))
+    h.destroy()
+
+
+def test_idi_per_graph_statistics_in_a_batch():
+    gs = [synth.star(30), synth.barabasi_albert(200, 2, 1), synth.erdos_renyi(100, 0.1, 2)]
+    bd = synth.block_diagonal(gs)
+    G = deco.Graph(bd)
+    h = deco.Handle(G, B=16, seed=5)
+    h.start(deco.INIT_IDI, scale=1.0, sigma2=0.0, batch=1)
+    x = to_np(h.read_x()).astype(np.float64)
+    assert np.array_equal(x, oracle.init_idi(bd, 16, 5, 1))
+    star = x[:30]
+    assert np.all(star[1:] == -star[0:1])
+    h.destroy()
+
+
+def test_inactive_lift_components_stay_zero():
+    g = synth.erdos_renyi(300, 0.05, 3)
+    B, l = 16, 4
+    G = deco.Graph(g)
+    h = deco.Handle(G, B=B, l=l, lifted=True, seed=1)
+    la = np.array([1, 2, 3, 4] * 4, np.int32)
+    z = torch.ones(g.n, dtype=torch.uint8, device="cuda")
+    h.start(deco.INIT_MEAN, mean_z=z, scale=1e4, sigma2=0.8, batch=2, l_active=la)
+    h.step(25)
+    x = to_np(h.read_x())
+    for b in range(B):
+        for i in range(l):
+            col = x[:, i * B + b]
+            if i >= la[b]:
+                assert np.all(col == 0.0)
+            else:
+                assert np.any(col != 0.0)
+    h.destroy()
+
+
+def test_philox_device_matches_host_and_oracle():
+    out = deco.philox_device(5, 7, 11, 0x1234_5678_9ABC, 257)
+    for i in [0, 1, 100, 256]:
+        ctr = [i, 5, 7, 11]
+        key = [0x5678_9ABC, 0x1234]
+        assert list(out[i]) == list(oracle.philox(ctr, key)) == list(deco.philox(ctr, key))
+
+
+# ------------------------------------------------------------------ edge cases
+def test_tiny_and_empty_graphs():
+    for g in [synth.edgeless(1), synth.edgeless(7), synth.path(2)]:
+        r = run_teacher_forced(g, 8, 3)
+        for t, X in enumerate(r["xs"]):
+            assert np.array_equal(r["trace"][t], oracle_cuts(g, X, 8, 1, False)[0])
+        if g.nnz == 0:
+            assert np.array_equal(r["xs"][0], r["xs"][-1])  # no neighbours: the cut-form gradient is zero
+        r["handle"].destroy()
+
+
+def test_invalid_inputs_are_rejected_before_any_launch():
+    g = synth.cycle(8)
+    bad = synth.CSR(g.n, g.row_ptr.copy(), g.col_idx.copy())
+    bad.col_idx[1] = 5  # row 0 -> 5 has no mirror entry
+    with pytest.raises(deco.DecoError) as e:
+        deco.Handle(deco.Graph(bad), B=8)
+    assert e.value.status == deco.E_INVAL
+    bad2 = synth.CSR(g.n, g.row_ptr.copy(), g.col_idx.copy())
+    bad2.col_idx[0] = 0  # self loop
+    with pytest.raises(deco.DecoError) as e:
+        deco.Handle(deco.Graph(bad2), B=8)
+    assert e.value.status == deco.E_INVAL
+    bad3 = synth.CSR(g.n, g.row_ptr.copy(), g.col_idx.copy(), np.ones(g.nnz, np.float32))
+    bad3.w[3] = np.nan
+    with pytest.raises(deco.DecoError) as e:
+        deco.Handle(deco.Graph(bad3), B=8)
+    assert e.value.status in (deco.E_NONFINITE, deco.E_INVAL)
+    bad4 = synth.CSR(g.n, g.row_ptr.copy(), g.col_idx.copy())
+    bad4.row_ptr[-1] = g.nnz - 1  # row_ptr end does not match nnz
+    with pytest.raises(deco.DecoError) as e:
+        deco.Handle(deco.Graph(bad4), B=8)
+    assert e.value.status == deco.E_INVAL
+    h = deco.Handle(deco.Graph(g), B=8)
+    x0 = torch.zeros((g.n, 8), device="cuda")
+    x0[2, 3] = float("nan")
+    with pytest.raises(deco.DecoError) as e:
+        h.start(deco.INIT_USER, x0=x0)
+    assert e.value.status == deco.E_NONFINITE
+    with pytest.raises(deco.DecoError) as e:
+        h.start(deco.INIT_MEAN)  # no mean vector
+    assert e.value.status == deco.E_INVAL
+    with pytest.raises(deco.DecoError):
+        deco.Handle(deco.Graph(g), B=3)
+    h.destroy()
+
+
+def test_workspace_too_small():
+    import ctypes as ct
+    g = synth.erdos_renyi(100, 0.1, 1)
+    G = deco.Graph(g)
+    p = deco.deco_params(16, 1, 0, 0, 0, 1, 0.1, 0)
+    nb = ct.c_size_t(0)
+    assert deco.lib().deco_workspace_size(ct.byref(G.struct), ct.byref(p), ct.byref(nb)) == 0
+    X = torch.zeros((g.n, 16), device="cuda")
+    ws = torch.zeros(nb.value, dtype=torch.uint8, device="cuda")
+    h = ct.c_void_p()
+    st = deco.lib().deco_init(ct.byref(h), ct.byref(G.struct), ct.byref(p), X.data_ptr(), ws.data_ptr(),
+                              nb.value - 1, None)
+    assert st == deco.E_NOMEM and not h.value
