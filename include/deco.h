@@ -27,8 +27,10 @@
  *   DECO_GRAD_LAPLACIAN uses G = L X = D_w X - W X exactly as eq. (6) prints it.
  * Rounding: unlifted z_v = 1{x_v > 0} (eq. (5)); lifted z_v = 1{sum_i X[v,i,b] >= 0} with
  *   the sum formed in float32 in component order (Sec. 3.2).
- * Exact cut: sum over rows of w_vu 1{z_v != z_u}, halved; accumulated in double, so it is
- *   exact (and order-free) for integer weights below 2^53 in total.
+ * Exact cut: sum over rows of w_vu 1{z_v != z_u}, halved. Integer weights of magnitude
+ *   <= 1024 (unit and +-1 included) are summed in int32 per work item and double across
+ *   items, so the cut is exact and order-free (below 2^53). Other weights use float32 per
+ *   item (at most 2048 terms per partial), then double: |error| <= sum|w| * 2^-14.
  *
  * Errors: every function returns a deco_status. Arguments are validated before anything
  * is launched, so an error return has no side effect on the device. An asynchronous
@@ -168,6 +170,19 @@ int64_t deco_current_step(const deco_handle *h);
  * handle and in a per-process cache keyed by the graph and batch shape. It overwrites X
  * and the running best (call deco_start afterwards). Synchronous. */
 deco_status deco_autotune(deco_handle *h, int32_t steps);
+
+/* Set the kernel schedule explicitly (instead of the default or the autotuner's choice).
+ * lanes_per_row: lanes holding one row's initialisation tile (power of two <= 64; the tile
+ * is lanes_per_row * (16 bytes / element size) columns and must divide B); split: lanes
+ * groups sharing one row (power of two, lanes_per_row * split <= 64); long_row: rows with
+ * more neighbours get a workgroup of their own (32..256); xcd_mode: 0 = each XCD owns a row
+ * range for every tile, 1 = each XCD owns tiles; blocks_per_xcd: persistent workgroups per
+ * XCD; nnz_per_item: target edges per work item (<= 2048). DECO_E_INVAL when the values do
+ * not fit B or the limits. Synchronous (uploads the work list). */
+typedef struct deco_schedule {
+  int32_t lanes_per_row, split, long_row, xcd_mode, blocks_per_xcd, nnz_per_item;
+} deco_schedule;
+deco_status deco_set_schedule(deco_handle *h, const deco_schedule *s);
 
 /* Describe the schedule in use (NUL-terminated text into buf[cap]). */
 deco_status deco_schedule_string(const deco_handle *h, char *buf, int32_t cap);

@@ -28,14 +28,16 @@ using namespace deco;
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kMinChunkRows = 8;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Schedule {
   int vec = 4;
   int Wc = 1;
-  int split = 1;
+  int split = 1;      // sub-groups sharing a row
+  int dlong = 64;     // rows with more neighbours get a workgroup of their own
   int rows_per_item = 256;
-  int nnz_per_item = 4096;
+  int nnz_per_item = 2048;
   int xcd_mode = 0;   // 0 rows per XCD, 1 initialisation tiles per XCD
   int blocks_per_xcd = 128;
   int grid = 0;
@@ -70,9 +72,14 @@ Layout layout_for(long long n, long long nnz, int G, const deco_params* p) {
   const int C = p->l * p->B;
   const int NBY = nby_of(p->B);
   const int vec = vec_for(p->x_dtype, p->B);
-  const long long nbt_max = std::max(1, p->B / std::max(1, vec));  // tiles of >= one lane
+  // initialisation tiles are at least 8 wide (or the whole of B < 8); row chunks hold at
+  // least kMinChunkRows rows except the last chunk of each graph
+  const long long nbt_max = p->B >= 8 ? p->B / 8 : 1;
+  (void)vec;
   L.R = G >= 16 ? 1 : 16;
-  L.items_cap = nbt_max * (n / 16 + (long long)G + 16);
+  // chunks: at most n / kMinChunkRows full ones, plus per long row (at least 33
+  // neighbours) the row itself and one cut-short chunk before it, plus one per graph
+  L.items_cap = nbt_max * (n / kMinChunkRows + 2 * (nnz / 32) + (long long)G + 8);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -99,7 +106,6 @@ Layout layout_for(long long n, long long nnz, int G, const deco_params* p) {
   L.l_active = take(sizeof(int) * (size_t)p->B);
   L.flags = take(sizeof(int) * 4);
   L.total = off;
-  (void)nnz;
   return L;
 }
 
@@ -140,25 +146,40 @@ deco_status poison(deco_handle* h, hipError_t e) {
     if (e__ != hipSuccess) return poison((h), e__); \
   } while (0)
 
-// Split each graph's rows into chunks of at most rows_per_item rows and roughly
-// nnz_per_item stored entries; a single long row forms a chunk of its own.
-std::vector<int4> row_chunks(const std::vector<int>& rp, const std::vector<int>& goff,
-                             int rows_per_item, int nnz_per_item) {
+// Split each graph's rows into work chunks: a row with more than dlong neighbours is a
+// chunk of its own (flag 1 in .w); other rows are grouped into chunks of at most kRmax and
+// rows_per_item rows and kEmax edges, closing a chunk at about nnz_per_item edges once it
+// holds kMinChunkRows rows.
+std::vector<int4> row_chunks(const std::vector<int>& rp, const std::vector<int>& goff, int rows_per_item,
+                             int nnz_per_item, int dlong) {
   std::vector<int4> ch;
   const int G = (int)goff.size() - 1;
+  const int rmax = std::min(rows_per_item, kRmax);
   for (int g = 0; g < G; ++g) {
-    int r = goff[g];
-    while (r < goff[g + 1]) {
-      int r1 = r + 1;
-      long long e = rp[r + 1] - rp[r];
-      while (r1 < goff[g + 1] && r1 - r < rows_per_item &&
-             e + (rp[r1 + 1] - rp[r1]) <= nnz_per_item) {
-        e += rp[r1 + 1] - rp[r1];
-        ++r1;
+    int start = -1;
+    long long e = 0;
+    for (int r = goff[g]; r < goff[g + 1]; ++r) {
+      const int d = rp[r + 1] - rp[r];
+      if (d > dlong) {
+        if (start >= 0) ch.push_back(make_int4(start, r, g, 0));
+        start = -1;
+        e = 0;
+        ch.push_back(make_int4(r, r + 1, g, 1 << 16));
+        continue;
       }
-      ch.push_back(make_int4(r, r1, g, 0));
-      r = r1;
+      if (start >= 0) {
+        const int rows = r - start;
+        const bool fits = rows < rmax && e + d <= kEmax && (rows < kMinChunkRows || e + d <= nnz_per_item);
+        if (!fits) {
+          ch.push_back(make_int4(start, r, g, 0));
+          start = -1;
+          e = 0;
+        }
+      }
+      if (start < 0) start = r;
+      e += d;
     }
+    if (start >= 0) ch.push_back(make_int4(start, goff[g + 1], g, 0));
   }
   return ch;
 }
@@ -183,9 +204,10 @@ bool build_schedule(deco_handle* h, Schedule& s) {
   const int B = h->p.B;
   const int Bt = s.Wc * s.vec;
   if (Bt <= 0 || B % Bt != 0 || (B >= 8 && Bt % 8 != 0)) return false;
-  if (s.Wc * s.split > 64) return false;
+  if (s.Wc > 64 || s.split < 1 || s.Wc * s.split > 64 || (s.split & (s.split - 1)) != 0) return false;
+  if (s.dlong < 32 || s.dlong > kEmax / kMinChunkRows) return false;
   const int nbt = B / Bt;
-  auto ch = row_chunks(h->rp_host, h->goff_host, s.rows_per_item, s.nnz_per_item);
+  auto ch = row_chunks(h->rp_host, h->goff_host, s.rows_per_item, s.nnz_per_item, s.dlong);
   std::vector<int4> items;
   int seg[9];
   const bool tiles = s.xcd_mode == 1 && nbt >= 2 && (nbt >= 8 || 8 % nbt == 0);
@@ -194,13 +216,13 @@ bool build_schedule(deco_handle* h, Schedule& s) {
     for (int x = 0; x < 8; ++x) {
       seg[x] = (int)items.size();
       for (int bt = 0; bt < nbt; ++bt)
-        for (int i = cut[x]; i < cut[x + 1]; ++i) items.push_back(make_int4(ch[i].x, ch[i].y, ch[i].z, bt));
+        for (int i = cut[x]; i < cut[x + 1]; ++i) items.push_back(make_int4(ch[i].x, ch[i].y, ch[i].z, ch[i].w | bt));
     }
   } else if (nbt >= 8) {
     for (int x = 0; x < 8; ++x) {
       seg[x] = (int)items.size();
       for (int bt = x; bt < nbt; bt += 8)
-        for (auto& c : ch) items.push_back(make_int4(c.x, c.y, c.z, bt));
+        for (auto& c : ch) items.push_back(make_int4(c.x, c.y, c.z, c.w | bt));
     }
   } else {
     const int parts = 8 / nbt;
@@ -208,7 +230,7 @@ bool build_schedule(deco_handle* h, Schedule& s) {
     for (int x = 0; x < 8; ++x) {
       seg[x] = (int)items.size();
       const int bt = x % nbt, part = x / nbt;
-      for (int i = cut[part]; i < cut[part + 1]; ++i) items.push_back(make_int4(ch[i].x, ch[i].y, ch[i].z, bt));
+      for (int i = cut[part]; i < cut[part + 1]; ++i) items.push_back(make_int4(ch[i].x, ch[i].y, ch[i].z, ch[i].w | bt));
     }
   }
   seg[8] = (int)items.size();
@@ -239,16 +261,17 @@ Schedule default_schedule(deco_handle* h) {
   Schedule s;
   s.vec = vec_for(h->dtype, h->p.B);
   s.Wc = max_wc(s.vec, h->p.B);
+  // sub-groups per row: about one per 8 neighbours, within one wave
   const double deg = h->n > 0 ? (double)h->nnz / (double)h->n : 0.0;
-  int split = 1;
-  while (split * 2 * s.Wc <= 64 && split * 2 <= deg / 4.0) split *= 2;
-  s.split = split;
+  s.split = 1;
+  while (s.split * 2 * s.Wc <= 64 && s.split * 8 < deg) s.split *= 2;
+  s.dlong = 64;
   s.xcd_mode = 0;
   s.blocks_per_xcd = 128;
-  // enough items for every workgroup, each worth at least a few row groups
-  const long long target = std::max<long long>(256, (h->nnz + h->n) / (8LL * s.blocks_per_xcd * 2));
-  s.nnz_per_item = (int)std::min<long long>(target, 1 << 20);
-  s.rows_per_item = std::max(16, (int)std::min<long long>(4096, s.nnz_per_item / std::max(1.0, deg) + 1));
+  // about two items per workgroup of the persistent grid, within the LDS limits
+  const long long per = (h->nnz + 8LL * s.blocks_per_xcd * 2 - 1) / (8LL * s.blocks_per_xcd * 2);
+  s.nnz_per_item = (int)std::max<long long>(256, std::min<long long>(kEmax, per));
+  s.rows_per_item = kRmax;
   return s;
 }
 
@@ -283,7 +306,7 @@ deco_status launch_steps(deco_handle* h, int steps, int do_update, int force) {
   a.do_update = do_update;
   a.force_score = force;
   for (int s = 0; s < steps; ++s) {
-    const hipError_t e = launch_step(a, h->dtype, h->sched.vec, h->unit, h->sched.grid, h->stream);
+    const hipError_t e = launch_step(a, h->dtype, h->sched.vec, h->sched.grid, h->stream);
     if (e != hipSuccess) return poison(h, e);
   }
   return DECO_OK;
@@ -431,6 +454,7 @@ deco_status deco_init(deco_handle** out, const deco_graph* g, const deco_params*
     delete h;
     return DECO_E_NONFINITE;
   }
+  a.intw = (hflags & 16) ? 0 : 1;
 
   // schedule: cached winner of an earlier autotune for this shape, else the default
   {
@@ -640,19 +664,23 @@ deco_status deco_autotune(deco_handle* h, int32_t steps) {
   std::vector<Schedule> cand;
   const int vec = base.vec;
   const int wmax = max_wc(vec, h->p.B);
-  for (int Wc = wmax; Wc >= 1 && Wc * vec >= std::min(8, h->p.B); Wc /= 2) {
-    if (Wc * 4 < wmax) break;
-    for (int split = 1; Wc * split <= 64; split *= 2) {
-      if (split > 1 && split * 2 > (double)h->nnz / (double)h->n) break;
-      for (int mode = 0; mode < 2; ++mode) {
-        if (mode == 1 && h->p.B / (Wc * vec) < 2) continue;
-        for (int bpx : {64, 128, 256}) {
-          Schedule s = base;
-          s.Wc = Wc;
-          s.split = split;
-          s.xcd_mode = mode;
-          s.blocks_per_xcd = bpx;
-          cand.push_back(s);
+  const double deg = h->n > 0 ? (double)h->nnz / (double)h->n : 0.0;
+  for (int Wc = wmax; Wc >= 1 && Wc * vec >= std::min(8, h->p.B) && Wc * 4 >= wmax; Wc /= 2) {
+    for (int split = 1; Wc * split <= 64 && (split == 1 || split * 2 <= deg); split *= 2) {
+      for (int dlong : {32, 64, 256}) {
+        for (int mode = 0; mode < 2; ++mode) {
+          if (mode == 1 && h->p.B / (Wc * vec) < 2) continue;
+          for (int bpx : {64, 128, 256}) {
+            Schedule s = base;
+            s.Wc = Wc;
+            s.split = split;
+            s.dlong = dlong;
+            s.xcd_mode = mode;
+            s.blocks_per_xcd = bpx;
+            const long long per = (h->nnz + 8LL * bpx * 2 - 1) / (8LL * bpx * 2);
+            s.nnz_per_item = (int)std::max<long long>(256, std::min<long long>(kEmax, per));
+            cand.push_back(s);
+          }
         }
       }
     }
@@ -698,13 +726,32 @@ deco_status deco_autotune(deco_handle* h, int32_t steps) {
   return deco_start(h, &sa);
 }
 
+deco_status deco_set_schedule(deco_handle* h, const deco_schedule* q) {
+  if (!h || !q) return DECO_E_INVAL;
+  if (h->poisoned) return DECO_E_STATE;
+  if (q->lanes_per_row < 1 || (q->lanes_per_row & (q->lanes_per_row - 1)) || q->split < 1 ||
+      q->blocks_per_xcd < 1 || q->blocks_per_xcd > 4096 || q->nnz_per_item < 1 || q->nnz_per_item > kEmax ||
+      (q->xcd_mode != 0 && q->xcd_mode != 1))
+    return DECO_E_INVAL;
+  Schedule s = default_schedule(h);
+  s.Wc = q->lanes_per_row;
+  s.split = q->split;
+  s.dlong = q->long_row;
+  s.xcd_mode = q->xcd_mode;
+  s.blocks_per_xcd = q->blocks_per_xcd;
+  s.nnz_per_item = q->nnz_per_item;
+  if (!build_schedule(h, s)) return DECO_E_INVAL;
+  h->sched = std::move(s);
+  return upload_schedule(h);
+}
+
 deco_status deco_schedule_string(const deco_handle* h, char* buf, int32_t cap) {
   if (!h || !buf || cap < 1) return DECO_E_INVAL;
   const Schedule& s = h->sched;
   std::snprintf(buf, (size_t)cap,
-                "vec=%d Wc=%d split=%d tile=%d tiles=%d xcd_mode=%d grid=%d items=%d rows_per_item=%d "
-                "nnz_per_item=%d R=%d",
-                s.vec, s.Wc, s.split, s.Wc * s.vec, h->p.B / (s.Wc * s.vec), s.xcd_mode, s.grid, s.nitems,
+                "vec=%d Wc=%d split=%d dlong=%d tile=%d tiles=%d xcd_mode=%d grid=%d items=%d "
+                "rows_per_item=%d nnz_per_item=%d R=%d",
+                s.vec, s.Wc, s.split, s.dlong, s.Wc * s.vec, h->p.B / (s.Wc * s.vec), s.xcd_mode, s.grid, s.nitems,
                 s.rows_per_item, s.nnz_per_item, h->R);
   return DECO_OK;
 }

@@ -10,14 +10,20 @@ namespace deco {
 // and the last workgroup of every step updates it, so a captured graph of step launches
 // can be replayed without host involvement.
 struct DevCtrl {
-  unsigned int ticket;  // workgroups that finished the current launch
+  unsigned int ticket;  // XCDs whose workgroups all finished the current launch
   int pending_slot;     // bit slot whose improvements are not yet folded into best_bits
   long long t;          // index of the current iterate
   int score_every;
   int pad;
+  unsigned int xticket[8][64];  // per-XCD completion counters, 256 bytes apart
 };
 
-// One work item: rows [x, y) of graph z, initialisation tile w.
+// Work-item limits of the step kernel (LDS staging of one item's CSR slice).
+constexpr int kEmax = 2048;  // edges staged at a time
+constexpr int kRmax = 512;   // rows of a normal item
+
+// One work item: rows [x, y) of graph z, initialisation tile (w & 0xFFFF); (w >> 16) != 0
+// marks a single long row handled by the whole workgroup.
 // Items are grouped by XCD: items[seg[x] .. seg[x+1]) run on workgroups with
 // blockIdx % 8 == x.
 
@@ -28,7 +34,8 @@ struct StepArgs {
   const float* dw;  // weighted degree (Laplacian form), may be NULL for the cut form
   void* x[2];       // ping-pong iterates; x[t & 1] holds X_t
   int C, B, L, lifted;
-  int Wc, split;    // lanes per row sub-group, sub-groups per row
+  int Wc;           // lanes per row sub-group (power of two, <= 64)
+  int split;        // sub-groups sharing one row of a normal item (power of two, Wc*split <= 64)
   const int4* items;
   const int* seg;   // [9]
   float cW, cD;     // G = cW * (W X) + cD * (d_w . X)
@@ -47,12 +54,12 @@ struct StepArgs {
   DevCtrl* ctrl;
   int do_update;    // 0: score-only pass (no new iterate, step counter unchanged)
   int force_score;  // score this launch regardless of score_every
+  int intw;         // all weights are integers of magnitude <= 1024 (int32 score partials)
 };
 
 // Kernel launchers (kernels.hip). dtype: 0 float32, 1 bfloat16. vec: elements per lane
 // per load (the native 16-byte width, or 1).
-hipError_t launch_step(const StepArgs& a, int dtype, int vec, bool unit, int grid,
-                       hipStream_t s);
+hipError_t launch_step(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s);
 int native_vec(int dtype);
 
 hipError_t launch_validate(long long n, const int* rp, const int* ci, const float* w,

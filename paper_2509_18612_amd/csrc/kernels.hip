@@ -5,23 +5,30 @@
 // iterate it reads (eq. (5) / lifted rounding, eq. (1)) and the running best of Alg. 1-2:
 //
 //   for every row v and initialisation b (all l components):
-//     acc   = sum_{u in N(v)} w_vu X_t[u, i, b]           (float32, CSR order per sub-group)
+//     acc   = sum_{u in N(v)} w_vu X_t[u, i, b]           (float32)
 //     X_t+1 = clip(X_t[v] + eta_b (cW acc + cD d_w(v) X_t[v]), -1, 1)
 //     score += w_vu 1{z_t(v) != z_t(u)}                   (double, exact for integer w)
 //
-// Mapping: node-major X (row v holds all l*B values contiguously). A row is handled by a
-// sub-group of Wc lanes, each lane owning VEC consecutive initialisations of a tile of
-// Bt = Wc*VEC, for every component (16-byte loads). 'split' sub-groups share one row and
-// split its neighbour list (long rows); a wave therefore covers 64/(Wc*split) rows. Work
-// items (row range x initialisation tile) are grouped per XCD and walked by a persistent
-// grid, so an XCD's L2 serves the gathers of its own rows / tile. Neighbour gathers are
-// issued four at a time to keep loads in flight. The score partials stay in registers
-// until the workgroup changes (graph, tile), then go through a wave reduction, an LDS
-// reduction and one double atomic per initialisation into one of R replicated
-// accumulators. The last workgroup of the launch (ticket counter) turns the sums into
-// cuts, updates the running best and the improvement mask, and advances the step counter.
-// The cut bits of an improved step are folded into best_bits by the next launch, row by
-// row, before that launch overwrites the same bit slot.
+// Mapping. X is node-major: row v holds its l*B values contiguously. A row of one
+// initialisation tile (Bt = Wc*VEC columns, for every component) is handled by a
+// sub-group of Wc lanes with 16-byte loads; a 256-thread workgroup has NS = 256/Wc
+// sub-groups. Work items are row ranges of one graph and one tile, grouped per XCD
+// (workgroup i runs on XCD i % 8) and walked by a persistent grid:
+//  * a normal item (rows of degree <= the long-row threshold, at most kEmax edges and
+//    kRmax rows) first copies its row_ptr / col_idx / weight slice into LDS with coalesced
+//    loads, so no gather waits on a dependent index load. Sub-group s takes the rows whose
+//    first edge lies in the s-th equal share of the item's edges and walks RB of them at
+//    once, issuing their own-row loads and up to RB*U neighbour gathers together;
+//  * a long-row item holds one row: all sub-groups split its edges in contiguous chunks
+//    (staged through LDS kEmax at a time), and their float32 partial sums are reduced
+//    through LDS in sub-group order (deterministic), then sub-group 0 finishes the row.
+// Score partials stay in registers (int32 for integer weights, exact; float otherwise)
+// until the item ends; then a wave reduction and an LDS reduction in double and one double
+// atomic per initialisation into one of R replicated accumulators. Completion uses a two-level ticket (per XCD, then global) so
+// no address takes more than one atomic per workgroup of one XCD. The last workgroup turns
+// the sums into cuts, updates best / best step / improvement mask and advances the step
+// counter; the next launch folds the improved cut bits into best_bits row by row, before
+// it overwrites that bit slot.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -40,13 +47,16 @@ __device__ __forceinline__ uint32_t f2bf(float f) {
   return u >> 16;
 }
 
+// Raw 16-byte (or scalar) loads kept packed while in flight, unpacked to float at use.
 template <typename T, int VEC>
 struct VecIO;
 
 template <>
 struct VecIO<float, 4> {
-  static __device__ __forceinline__ void load(const float* p, float (&o)[4]) {
-    const float4 v = *reinterpret_cast<const float4*>(p);
+  using raw = float4;
+  static __device__ __forceinline__ raw load_raw(const float* p) { return *reinterpret_cast<const float4*>(p); }
+  static __device__ __forceinline__ raw zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+  static __device__ __forceinline__ void unpack(const raw& v, float (&o)[4]) {
     o[0] = v.x;
     o[1] = v.y;
     o[2] = v.z;
@@ -59,14 +69,19 @@ struct VecIO<float, 4> {
 
 template <>
 struct VecIO<float, 1> {
-  static __device__ __forceinline__ void load(const float* p, float (&o)[1]) { o[0] = *p; }
+  using raw = float;
+  static __device__ __forceinline__ raw load_raw(const float* p) { return *p; }
+  static __device__ __forceinline__ raw zero() { return 0.f; }
+  static __device__ __forceinline__ void unpack(const raw& v, float (&o)[1]) { o[0] = v; }
   static __device__ __forceinline__ void store(float* p, const float (&o)[1]) { *p = o[0]; }
 };
 
 template <>
 struct VecIO<uint16_t, 8> {
-  static __device__ __forceinline__ void load(const uint16_t* p, float (&o)[8]) {
-    const uint4 v = *reinterpret_cast<const uint4*>(p);
+  using raw = uint4;
+  static __device__ __forceinline__ raw load_raw(const uint16_t* p) { return *reinterpret_cast<const uint4*>(p); }
+  static __device__ __forceinline__ raw zero() { return make_uint4(0u, 0u, 0u, 0u); }
+  static __device__ __forceinline__ void unpack(const raw& v, float (&o)[8]) {
     o[0] = bf2f(v.x & 0xFFFFu);
     o[1] = bf2f(v.x >> 16);
     o[2] = bf2f(v.y & 0xFFFFu);
@@ -88,13 +103,16 @@ struct VecIO<uint16_t, 8> {
 
 template <>
 struct VecIO<uint16_t, 1> {
-  static __device__ __forceinline__ void load(const uint16_t* p, float (&o)[1]) { o[0] = bf2f(*p); }
+  using raw = uint32_t;
+  static __device__ __forceinline__ raw load_raw(const uint16_t* p) { return *p; }
+  static __device__ __forceinline__ raw zero() { return 0u; }
+  static __device__ __forceinline__ void unpack(const raw& v, float (&o)[1]) { o[0] = bf2f(v); }
   static __device__ __forceinline__ void store(uint16_t* p, const float (&o)[1]) {
     *p = (uint16_t)f2bf(o[0]);
   }
 };
 
-// Rounding of one initialisation from its l component values (float32, order i = 0..l-1).
+// Side of one initialisation from its l component values (float32, order i = 0..l-1).
 template <int L>
 __device__ __forceinline__ bool side_of(const float (&x)[L], int lifted) {
   if (!lifted) return x[0] > 0.0f;
@@ -104,24 +122,189 @@ __device__ __forceinline__ bool side_of(const float (&x)[L], int lifted) {
   return s >= 0.0f;
 }
 
-constexpr int kWaves = 4;  // waves per workgroup
-constexpr int kUnroll = 4; // neighbour gathers in flight per sub-group
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
 
-template <typename T, int VEC, int L, bool UNIT>
-__global__ __launch_bounds__(256) void k_step(StepArgs a) {
-  __shared__ double s_red[kWaves][64 * VEC];
+template <int L, int VEC>
+struct Tune {
+  // rows walked together per sub-group, and gathers issued per row per batch: 16 loads in
+  // flight per lane for float32 / scalar data, 8 for bfloat16 (8 values per load)
+  static constexpr int RB = (L == 1) ? 2 : 1;
+  static constexpr int kLoads = (VEC == 8) ? 8 : 16;
+  static constexpr int U = (kLoads / (L * RB)) < 2 ? 2 : kLoads / (L * RB);
+};
+
+// Weight modes: unit weights (no weight loads), integer weights of magnitude <= 1024
+// (int32 score partials, exact), real weights (float32 score partials).
+enum : int { kUnitW = 0, kIntW = 1, kRealW = 2 };
+template <int WM>
+struct ScoreType {
+  using type = int;
+};
+template <>
+struct ScoreType<kRealW> {
+  using type = float;
+};
+
+// Sides of the VEC initialisations of one lane as a bit mask.
+template <int L, int VEC>
+__device__ __forceinline__ uint32_t side_mask(const float (&x)[L][VEC], int lifted) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) {
+    float g[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) g[i] = x[i][e];
+    m |= (side_of<L>(g, lifted) ? 1u : 0u) << e;
+  }
+  return m;
+}
+
+// Accumulate the edges kb[r], kb[r] + S, ... < ke[r] of RB rows (indices and weights
+// from the LDS copy of the item's slice) into acc[r] and, when scoring, sc. Every batch
+// issues the gathers of all RB rows before any of them is used; the sides of the rows
+// themselves (zm) are formed only after the first batch is in flight.
+template <typename T, int VEC, int L, int WM, int RB>
+__device__ __forceinline__ void gather_rows(const T* __restrict__ X, const int* s_ci, const float* s_w,
+                                            const int (&kb)[RB], const int (&ke)[RB], int S, size_t C, size_t B,
+                                            int bl, const float (&xv)[RB][L][VEC], float (&acc)[RB][L][VEC],
+                                            uint32_t (&zm)[RB], typename ScoreType<WM>::type (&sc)[VEC],
+                                            bool do_score, int lifted) {
+  using IO = VecIO<T, VEC>;
+  constexpr int U = Tune<L, VEC>::U;
+  int len = 0;
+#pragma unroll
+  for (int r = 0; r < RB; ++r) len = max(len, ke[r] - kb[r]);
+  bool have_z = false;
+  for (int j = 0; j < len; j += U * S) {
+    int u[RB][U];
+    float wk[RB][U];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int k = kb[r] + j + q * S;
+        const bool ok = k < ke[r];
+        u[r][q] = ok ? s_ci[k] : -1;
+        wk[r][q] = ok ? (WM == kUnitW ? 1.0f : s_w[k]) : 0.0f;
+      }
+    typename IO::raw xr[RB][U][L];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int q = 0; q < U; ++q)
+#pragma unroll
+        for (int i = 0; i < L; ++i)
+          xr[r][q][i] = u[r][q] >= 0 ? IO::load_raw(X + (size_t)u[r][q] * C + i * B + bl) : IO::zero();
+    if (!have_z) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r) zm[r] = side_mask<L, VEC>(xv[r], lifted);
+      have_z = true;
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        float xu[L][VEC];
+#pragma unroll
+        for (int i = 0; i < L; ++i) IO::unpack(xr[r][q][i], xu[i]);
+#pragma unroll
+        for (int i = 0; i < L; ++i)
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) {
+            if (WM == kUnitW)
+              acc[r][i][e] += xu[i][e];
+            else
+              acc[r][i][e] = fmaf(wk[r][q], xu[i][e], acc[r][i][e]);
+          }
+        if (do_score && u[r][q] >= 0) {
+          const uint32_t d = side_mask<L, VEC>(xu, lifted) ^ zm[r];
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) {
+            if ((d >> e) & 1u) {
+              if (WM == kUnitW)
+                sc[e] += 1;
+              else if (WM == kIntW)
+                sc[e] += (int)wk[r][q];
+              else
+                sc[e] += wk[r][q];
+            }
+          }
+        }
+      }
+  }
+  if (!have_z) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r) zm[r] = side_mask<L, VEC>(xv[r], lifted);
+  }
+}
+
+// Projected update of one row (team leader lanes), its cut bits, and the fold of the
+// previous scored step's improvements into best_bits (inputs prefetched by the caller).
+template <typename T, int VEC, int L>
+__device__ __forceinline__ void finish_row(const StepArgs& a, T* __restrict__ Y, uint8_t* __restrict__ bw,
+                                           bool do_score, int row, bool active, int bl, int lc, int gb,
+                                           const float (&xv)[L][VEC], const float (&acc)[L][VEC], uint32_t zm,
+                                           uint32_t m, uint32_t mo, uint32_t mb) {
+  if (a.do_update && active) {
+    const float dwv = (a.cD != 0.0f) ? a.dw[row] : 0.0f;
+    float eta[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) eta[e] = a.eta[bl + e];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      float y[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        float g = a.cW * acc[i][e];
+        if (a.cD != 0.0f) g = fmaf(a.cD * dwv, xv[i][e], g);
+        const float v = fmaf(eta[e], g, xv[i][e]);
+        y[e] = fminf(1.0f, fmaxf(-1.0f, v));
+      }
+      VecIO<T, VEC>::store(Y + (size_t)row * a.C + (size_t)i * a.B + bl, y);
+    }
+  }
+  // cut bits of X_t: one byte per 8 initialisations, assembled over gb lanes
+  uint32_t byte = (zm & ((1u << VEC) - 1u)) << ((lc * VEC) & 7);
+  for (int s = 1; s < gb; s <<= 1) byte |= __shfl_xor(byte, s);
+  if (active && (lc % gb) == 0) {
+    const size_t bi = (size_t)row * a.NBY + (bl >> 3);
+    if (m) a.best_bits[bi] = (uint8_t)((mb & ~m) | (mo & m));
+    if (do_score) bw[bi] = (uint8_t)byte;
+  }
+}
+
+#ifndef DECO_STEP_WAVES_PER_EU
+#define DECO_STEP_WAVES_PER_EU 1
+#endif
+
+template <typename T, int VEC, int L, int WM>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(DECO_STEP_WAVES_PER_EU)))
+void k_step(StepArgs a) {
+  constexpr int RB = Tune<L, VEC>::RB;
+  using ST = typename ScoreType<WM>::type;
+  using IO = VecIO<T, VEC>;
+  __shared__ int s_ci[kEmax];
+  __shared__ float s_w[WM == kUnitW ? 1 : kEmax];
+  __shared__ int s_rp[kRmax + 1];
+  // score flush (double per initialisation per wave) / long-row reduction (float per lane)
+  constexpr int kRedBytes = (kWaves * 64 * VEC * 8 > kThreads * L * VEC * 4) ? kWaves * 64 * VEC * 8
+                                                                              : kThreads * L * VEC * 4;
+  __shared__ __align__(16) unsigned char s_red_raw[kRedBytes];
   __shared__ int s_last;
+  double* s_red = reinterpret_cast<double*>(s_red_raw);
+  float* s_acc = reinterpret_cast<float*>(s_red_raw);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
   const int Wc = a.Wc;
-  const int split = a.split;
-  const int gw = Wc * split;
-  const int lc = lane & (Wc - 1);
-  const int sg = (lane / Wc) & (split - 1);
-  const int rs = lane / gw;
-  const int rpw = 64 / gw;
+  const int S = a.split;        // sub-groups per row (a team) in normal items
+  const int NS = kThreads / Wc;
+  const int NT = NS / S;
+  const int lc = tid & (Wc - 1);
+  const int sgi = tid / Wc;
+  const int team = sgi / S, mem = sgi % S;
 
   const long long t = a.ctrl->t;
   const bool do_score = a.force_score || (t % a.ctrl->score_every) == 0;
@@ -131,195 +314,200 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a) {
   T* __restrict__ Y = reinterpret_cast<T*>(a.x[par ^ 1]);
   uint8_t* __restrict__ bw = a.bits[par];
   const uint8_t* bm = pend >= 0 ? a.bits[pend] : nullptr;
-  const int C = a.C, B = a.B, NBY = a.NBY;
+  const size_t C = (size_t)a.C, B = (size_t)a.B;
   const int Bt = Wc * VEC;
-  const int gb = VEC >= 8 ? 1 : (8 / VEC < Wc ? 8 / VEC : Wc);  // lanes per cut-bit byte
+  const int gb = VEC >= 8 ? 1 : (8 / VEC < Wc ? 8 / VEC : Wc);
 
   const int xcd = blockIdx.x & 7;
   const int kb = blockIdx.x >> 3;
   const int nbx = ((int)gridDim.x - xcd + 7) >> 3;
   const int it0 = a.seg[xcd], it1 = a.seg[xcd + 1];
 
-  double sc[VEC];
+  ST sc[VEC];
 #pragma unroll
-  for (int e = 0; e < VEC; ++e) sc[e] = 0.0;
-  float eta_l[VEC];
+  for (int e = 0; e < VEC; ++e) sc[e] = 0;
   int cg = -1, cbt = -1;
 
   for (int it = it0 + kb;; it += nbx) {
     const bool have = it < it1;
     int4 item = make_int4(0, 0, -1, -1);
     if (have) item = a.items[it];
-    if (do_score && cg >= 0 && (!have || item.z != cg || item.w != cbt)) {
-      // flush the partial scores of (cg, cbt): wave, then workgroup, then one atomic
+    if (do_score && cg >= 0) {
+      // flush the previous item's score partials: wave, then workgroup, then one atomic
+      double d[VEC];
 #pragma unroll
-      for (int e = 0; e < VEC; ++e)
-        for (int s = Wc; s < 64; s <<= 1) sc[e] += __shfl_xor(sc[e], s);
-      if (lane < Wc) {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) s_red[wv][lane * VEC + e] = sc[e];
+      for (int e = 0; e < VEC; ++e) {
+        d[e] = (double)sc[e];
+        for (int s = Wc; s < 64; s <<= 1) d[e] += __shfl_xor(d[e], s);
       }
       __syncthreads();
-      for (int j = tid; j < Bt; j += 256) {
-        double v = s_red[0][j];
+      if (lane < Wc) {
 #pragma unroll
-        for (int q = 1; q < kWaves; ++q) v += s_red[q][j];
+        for (int e = 0; e < VEC; ++e) s_red[wv * 64 * VEC + lane * VEC + e] = d[e];
+      }
+      __syncthreads();
+      for (int j = tid; j < Bt; j += kThreads) {
+        double v = s_red[j];
+#pragma unroll
+        for (int q = 1; q < kWaves; ++q) v += s_red[q * 64 * VEC + j];
         if (v != 0.0) {
-          double* dst = a.acc + ((size_t)(blockIdx.x % a.R) * a.G + cg) * B + cbt * Bt + j;
+          double* dst = a.acc + ((size_t)(blockIdx.x % a.R) * a.G + cg) * B + (size_t)cbt * Bt + j;
           unsafeAtomicAdd(dst, v);
         }
       }
-      __syncthreads();
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) sc[e] = 0.0;
+      for (int e = 0; e < VEC; ++e) sc[e] = 0;
     }
     if (!have) break;
+    const bool longrow = (item.w >> 16) != 0;
     cg = item.z;
-    cbt = item.w;
+    cbt = item.w & 0xFFFF;
     const int bl = cbt * Bt + lc * VEC;  // first initialisation of this lane
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) eta_l[e] = a.eta[bl + e];
+    const int e0 = a.rp[item.x], e1 = a.rp[item.y];
+    // improvement mask of the previous scored step for this lane's cut-bit byte
+    const bool owner = (lc % gb) == 0;
+    const uint32_t mlane = (pend >= 0 && owner) ? a.mask[cg * a.NBY + (bl >> 3)] : 0u;
+    __syncthreads();  // LDS of the previous item is free
 
-    for (int rb = item.x + wv * rpw; rb < item.y; rb += kWaves * rpw) {
-      const int row = rb + rs;
-      const bool valid = row < item.y;
-      int beg = 0, end = 0;
-      float xv[L][VEC];
-      if (valid) {
-        beg = a.rp[row];
-        end = a.rp[row + 1];
-#pragma unroll
-        for (int i = 0; i < L; ++i)
-          VecIO<T, VEC>::load(X + (size_t)row * C + (size_t)i * B + bl, xv[i]);
-      } else {
-#pragma unroll
-        for (int i = 0; i < L; ++i)
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) xv[i][e] = 0.0f;
+    if (!longrow) {
+      const int E = e1 - e0, R = item.y - item.x;
+      for (int k = tid; k < E; k += kThreads) {
+        s_ci[k] = a.ci[e0 + k];
+        if (WM != kUnitW) s_w[k] = a.w[e0 + k];
       }
-      bool zv[VEC];
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        float g[L];
-#pragma unroll
-        for (int i = 0; i < L; ++i) g[i] = xv[i][e];
-        zv[e] = side_of<L>(g, a.lifted);
+      for (int i = tid; i <= R; i += kThreads) s_rp[i] = a.rp[item.x + i] - e0;
+      __syncthreads();
+      // rows whose first edge lies in this team's share [c0, c1) of the edges
+      const int c0 = (int)(((long long)E * team) / NT);
+      const int c1 = (int)(((long long)E * (team + 1)) / NT);
+      int lo = 0, hi = R;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s_rp[mid] < c0) lo = mid + 1; else hi = mid;
       }
-      float acc[L][VEC];
-#pragma unroll
-      for (int i = 0; i < L; ++i)
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[i][e] = 0.0f;
-
-      for (int k = beg + sg; k < end; k += split * kUnroll) {
-        int u[kUnroll];
-        float wk[kUnroll];
-#pragma unroll
-        for (int q = 0; q < kUnroll; ++q) {
-          const int kk = k + q * split;
-          const bool ok = kk < end;
-          u[q] = ok ? a.ci[kk] : -1;
-          wk[q] = ok ? (UNIT ? 1.0f : a.w[kk]) : 0.0f;
+      const int i0 = lo;
+      int i1 = R;
+      if (team != NT - 1) {
+        lo = i0;
+        hi = R;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (s_rp[mid] < c1) lo = mid + 1; else hi = mid;
         }
-        float xu[kUnroll][L][VEC];
+        i1 = lo;
+      }
+      for (int i = i0; i < i1; i += RB) {
+        float xv[RB][L][VEC];
+        float acc[RB][L][VEC];
+        uint32_t zm[RB], mo[RB], mb[RB];
+        int kb2[RB], ke2[RB];
 #pragma unroll
-        for (int q = 0; q < kUnroll; ++q) {
-          if (u[q] >= 0) {
+        for (int r = 0; r < RB; ++r) {
+          const bool ok = i + r < i1;
+          const int row = item.x + i + r;
 #pragma unroll
-            for (int i = 0; i < L; ++i)
-              VecIO<T, VEC>::load(X + (size_t)u[q] * C + (size_t)i * B + bl, xu[q][i]);
-          } else {
+          for (int ii = 0; ii < L; ++ii) {
+            IO::unpack(ok ? IO::load_raw(X + (size_t)row * C + ii * B + bl) : IO::zero(), xv[r][ii]);
 #pragma unroll
-            for (int i = 0; i < L; ++i)
-#pragma unroll
-              for (int e = 0; e < VEC; ++e) xu[q][i][e] = 0.0f;
+            for (int e = 0; e < VEC; ++e) acc[r][ii][e] = 0.0f;
           }
-        }
-#pragma unroll
-        for (int q = 0; q < kUnroll; ++q) {
-#pragma unroll
-          for (int i = 0; i < L; ++i)
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-              if (UNIT)
-                acc[i][e] += xu[q][i][e];
-              else
-                acc[i][e] = fmaf(wk[q], xu[q][i][e], acc[i][e]);
-            }
-        }
-        if (do_score) {
-#pragma unroll
-          for (int q = 0; q < kUnroll; ++q) {
-            if (u[q] >= 0) {
-#pragma unroll
-              for (int e = 0; e < VEC; ++e) {
-                float g[L];
-#pragma unroll
-                for (int i = 0; i < L; ++i) g[i] = xu[q][i][e];
-                if (side_of<L>(g, a.lifted) != zv[e]) sc[e] += (double)wk[q];
-              }
-            }
+          mo[r] = mb[r] = 0u;
+          if (ok && mlane && mem == 0) {
+            const size_t bi = (size_t)row * a.NBY + (bl >> 3);
+            mo[r] = bm[bi];
+            mb[r] = a.best_bits[bi];
           }
+          kb2[r] = ok ? s_rp[i + r] + mem : 0;
+          ke2[r] = ok ? s_rp[i + r + 1] : 0;
+        }
+        gather_rows<T, VEC, L, WM, RB>(X, s_ci, s_w, kb2, ke2, S, C, B, bl, xv, acc, zm, sc, do_score, a.lifted);
+        // combine the team members that split these rows' neighbours
+        for (int s = Wc; s < Wc * S; s <<= 1) {
+#pragma unroll
+          for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int ii = 0; ii < L; ++ii)
+#pragma unroll
+              for (int e = 0; e < VEC; ++e) acc[r][ii][e] += __shfl_xor(acc[r][ii][e], s);
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const bool ok = i + r < i1;
+          finish_row<T, VEC, L>(a, Y, bw, do_score, item.x + i + r, ok && mem == 0, bl, lc, gb, xv[r], acc[r],
+                                zm[r], mlane, mo[r], mb[r]);
         }
       }
-      // combine the sub-groups that split this row's neighbours
-      for (int s = Wc; s < gw; s <<= 1) {
+    } else {
+      // one long row: every sub-group takes a contiguous share of each staged chunk
+      const int row = item.x;
+      float xv[1][L][VEC];
+      float acc[1][L][VEC];
+      uint32_t zm[1];
 #pragma unroll
-        for (int i = 0; i < L; ++i)
+      for (int ii = 0; ii < L; ++ii) {
+        IO::unpack(IO::load_raw(X + (size_t)row * C + ii * B + bl), xv[0][ii]);
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) acc[i][e] += __shfl_xor(acc[i][e], s);
+        for (int e = 0; e < VEC; ++e) acc[0][ii][e] = 0.0f;
       }
-      const bool lead = valid && sg == 0;
-      if (a.do_update && lead) {
-        const float dwv = (a.cD != 0.0f) ? a.dw[row] : 0.0f;
-#pragma unroll
-        for (int i = 0; i < L; ++i) {
-          float y[VEC];
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) {
-            float g = a.cW * acc[i][e];
-            if (a.cD != 0.0f) g = fmaf(a.cD * dwv, xv[i][e], g);
-            float v = fmaf(eta_l[e], g, xv[i][e]);
-            y[e] = fminf(1.0f, fmaxf(-1.0f, v));
-          }
-          VecIO<T, VEC>::store(Y + (size_t)row * C + (size_t)i * B + bl, y);
+      uint32_t mo = 0u, mb = 0u;
+      if (mlane && sgi == 0) {
+        const size_t bi = (size_t)row * a.NBY + (bl >> 3);
+        mo = bm[bi];
+        mb = a.best_bits[bi];
+      }
+      for (int sb = e0; sb < e1; sb += kEmax) {
+        const int E = (e1 - sb) < kEmax ? (e1 - sb) : kEmax;
+        __syncthreads();
+        for (int k = tid; k < E; k += kThreads) {
+          s_ci[k] = a.ci[sb + k];
+          if (WM != kUnitW) s_w[k] = a.w[sb + k];
         }
+        __syncthreads();
+        const int c0[1] = {(int)(((long long)E * sgi) / NS)};
+        const int c1[1] = {(int)(((long long)E * (sgi + 1)) / NS)};
+        gather_rows<T, VEC, L, WM, 1>(X, s_ci, s_w, c0, c1, 1, C, B, bl, xv, acc, zm, sc, do_score, a.lifted);
       }
-      // cut bits of X_t: assemble bytes across the gb lanes that share one
-      uint32_t byte = 0;
+      if (e1 == e0) zm[0] = side_mask<L, VEC>(xv[0], a.lifted);
+      __syncthreads();
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) byte |= (zv[e] ? 1u : 0u) << e;
-      byte <<= (lc * VEC) & 7;
-      for (int s = 1; s < gb; s <<= 1) byte |= __shfl_xor(byte, s);
-      if (lead && (lc % gb) == 0) {
-        const size_t bi = (size_t)row * NBY + (bl >> 3);
-        if (pend >= 0) {
-          const uint32_t m = a.mask[cg * NBY + (bl >> 3)];
-          if (m) {
-            const uint32_t old = bm[bi];
-            const uint32_t bb = a.best_bits[bi];
-            a.best_bits[bi] = (uint8_t)((bb & ~m) | (old & m));
-          }
-        }
-        if (do_score) bw[bi] = (uint8_t)byte;
+      for (int ii = 0; ii < L; ++ii)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) s_acc[(sgi * Wc + lc) * (L * VEC) + ii * VEC + e] = acc[0][ii][e];
+      __syncthreads();
+      if (sgi == 0) {
+        for (int q = 1; q < NS; ++q)
+#pragma unroll
+          for (int ii = 0; ii < L; ++ii)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc[0][ii][e] += s_acc[(q * Wc + lc) * (L * VEC) + ii * VEC + e];
       }
+      finish_row<T, VEC, L>(a, Y, bw, do_score, row, sgi == 0, bl, lc, gb, xv[0], acc[0], zm[0], mlane, mo, mb);
     }
   }
 
-  // ---- last workgroup: cuts, running best, improvement mask, step counter
-  __threadfence();
+  // ---- completion: two-level ticket, then the last workgroup finishes the step.
+  // Inside a launch, workgroups exchange data only through device-scope atomics (score
+  // accumulators, tickets), so no L2 write-back fence is needed: every lane waits until its
+  // own atomics are acknowledged, then one lane takes the XCD ticket; the last workgroup of
+  // each XCD takes the global ticket. Plain stores (iterate, bits) are consumed by the next
+  // launch, after the kernel boundary.
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (tid == 0) {
-    const unsigned prev = atomicAdd(&a.ctrl->ticket, 1u);
-    s_last = (prev == gridDim.x - 1);
+    bool last = false;
+    const unsigned p = atomicAdd(&a.ctrl->xticket[xcd][0], 1u);
+    if (p == (unsigned)nbx - 1u) {
+      const unsigned q = atomicAdd(&a.ctrl->ticket, 1u);
+      last = (q == 7u);
+    }
+    s_last = last;
   }
   __syncthreads();
   if (!s_last) return;
-  __threadfence();
-  const int GB = a.G * B;
+  const int GB = a.G * a.B;
   if (do_score) {
-    const int chunk = B < 8 ? B : 8;
-    for (int base = 0; base < GB; base += 256) {
+    const int chunk = a.B < 8 ? a.B : 8;
+    for (int base = 0; base < GB; base += kThreads) {
       const int idx = base + tid;
       const bool in = idx < GB;
       bool imp = false;
@@ -341,11 +529,12 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a) {
       }
       const unsigned long long bal = __ballot(imp);
       if (in && (idx % chunk) == 0) {
-        const int g = idx / B, b = idx % B;
-        a.mask[g * NBY + (b >> 3)] = (uint8_t)((bal >> lane) & ((1ull << chunk) - 1ull));
+        const int g = idx / a.B, b = idx % a.B;
+        a.mask[g * a.NBY + (b >> 3)] = (uint8_t)((bal >> lane) & ((1ull << chunk) - 1ull));
       }
     }
   }
+  if (tid < 8) a.ctrl->xticket[tid][0] = 0u;
   if (tid == 0) {
     a.ctrl->pending_slot = do_score ? par : -1;
     if (a.do_update) a.ctrl->t = t + 1;
@@ -354,13 +543,15 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a) {
 }
 
 template <typename T, int VEC>
-hipError_t step_dispatch_l(const StepArgs& a, bool unit, int grid, hipStream_t s) {
-  dim3 g(grid), b(256);
-#define DECO_LAUNCH(LL)                                                           \
-  if (unit)                                                                       \
-    hipLaunchKernelGGL((k_step<T, VEC, LL, true>), g, b, 0, s, a);                \
-  else                                                                            \
-    hipLaunchKernelGGL((k_step<T, VEC, LL, false>), g, b, 0, s, a);
+hipError_t step_dispatch_l(const StepArgs& a, int wmode, int grid, hipStream_t s) {
+  dim3 g(grid), b(kThreads);
+#define DECO_LAUNCH(LL)                                                              \
+  if (wmode == kUnitW)                                                               \
+    hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW>), g, b, 0, s, a);                 \
+  else if (wmode == kIntW)                                                           \
+    hipLaunchKernelGGL((k_step<T, VEC, LL, kIntW>), g, b, 0, s, a);                  \
+  else                                                                               \
+    hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW>), g, b, 0, s, a);
   switch (a.L) {
     case 1: DECO_LAUNCH(1); break;
     case 2: DECO_LAUNCH(2); break;
@@ -399,7 +590,7 @@ __global__ void k_validate(long long n, const int* rp, const int* ci, const floa
     prev = u;
     if (u < g0 || u >= g1) f |= 8;
     if (!isfinite(wk)) f |= 4;
-    if (wk != floorf(wk) || fabsf(wk) > 1048576.0f) f |= 16;
+    if (wk != floorf(wk) || fabsf(wk) > 1024.0f) f |= 16;
     s += wk;
     // mirror entry: binary search v in row u
     int a0 = rp[u], a1 = rp[u + 1] - 1;
@@ -430,6 +621,7 @@ __global__ void k_reset(StepArgs a, double* acc_all, long long acc_count, int sc
     a.cur_cut[i] = -__builtin_inf();
   }
   if (i < (long long)a.G * a.NBY) a.mask[i] = 0;
+  if (i < 8) a.ctrl->xticket[i][0] = 0u;
   if (i == 0) {
     a.ctrl->ticket = 0u;
     a.ctrl->pending_slot = -1;
@@ -610,14 +802,14 @@ inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1)
 
 int native_vec(int dtype) { return dtype == 0 ? 4 : 8; }
 
-hipError_t launch_step(const StepArgs& a, int dtype, int vec, bool unit, int grid,
-                       hipStream_t s) {
+hipError_t launch_step(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s) {
+  const int wmode = a.w == nullptr ? kUnitW : (a.intw ? kIntW : kRealW);
   if (dtype == 0) {
-    if (vec == 4) return step_dispatch_l<float, 4>(a, unit, grid, s);
-    if (vec == 1) return step_dispatch_l<float, 1>(a, unit, grid, s);
+    if (vec == 4) return step_dispatch_l<float, 4>(a, wmode, grid, s);
+    if (vec == 1) return step_dispatch_l<float, 1>(a, wmode, grid, s);
   } else {
-    if (vec == 8) return step_dispatch_l<uint16_t, 8>(a, unit, grid, s);
-    if (vec == 1) return step_dispatch_l<uint16_t, 1>(a, unit, grid, s);
+    if (vec == 8) return step_dispatch_l<uint16_t, 8>(a, wmode, grid, s);
+    if (vec == 1) return step_dispatch_l<uint16_t, 1>(a, wmode, grid, s);
   }
   return hipErrorInvalidValue;
 }

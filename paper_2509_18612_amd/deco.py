@@ -13,7 +13,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdeco.so")
+# DECO_LIBRARY may name another build of the same sources (e.g. other compile options).
+LIB_PATH = os.environ.get("DECO_LIBRARY", os.path.join(_HERE, "libdeco.so"))
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_NONFINITE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 GRAD_CUT, GRAD_LAPLACIAN = 0, 1
@@ -52,6 +53,11 @@ class deco_solve_params(ct.Structure):
                 ("target_cut", ct.c_void_p), ("use_graph", ct.c_int32), ("autotune", ct.c_int32)]
 
 
+class deco_schedule(ct.Structure):
+    _fields_ = [("lanes_per_row", ct.c_int32), ("split", ct.c_int32), ("long_row", ct.c_int32),
+                ("xcd_mode", ct.c_int32), ("blocks_per_xcd", ct.c_int32), ("nnz_per_item", ct.c_int32)]
+
+
 class deco_solve_report(ct.Structure):
     _fields_ = [("rounds_done", ct.c_int32), ("steps_done", ct.c_int64), ("edge_updates", ct.c_double),
                 ("seconds", ct.c_double), ("eq_best", ct.c_double), ("el_best", ct.c_double),
@@ -62,7 +68,7 @@ EXPORTS = ["deco_status_string", "deco_workspace_size", "deco_init", "deco_start
            "deco_round_score", "deco_best", "deco_read_x", "deco_set_trace", "deco_current_step",
            "deco_autotune", "deco_schedule_string", "deco_destroy", "deco_solve", "deco_evo_next",
            "deco_philox", "deco_philox_device", "deco_solver_create", "deco_solver_run",
-           "deco_solver_set_target", "deco_solver_destroy"]
+           "deco_solver_set_target", "deco_solver_destroy", "deco_set_schedule"]
 
 _lib = None
 
@@ -93,6 +99,7 @@ def lib():
         L.deco_destroy.argtypes = [P]
         L.deco_destroy.restype = None
         L.deco_solve.argtypes = [P, P, P, P, P, P, P, P]
+        L.deco_set_schedule.argtypes = [P, P]
         L.deco_solver_create.argtypes = [ct.POINTER(P), P, P, P]
         L.deco_solver_run.argtypes = [P, I32, P, P, P, P, P]
         L.deco_solver_set_target.argtypes = [P, P]
@@ -272,6 +279,11 @@ class Handle:
 
     def autotune(self, steps: int = 10):
         _check(lib().deco_autotune(self.h, int(steps)), "deco_autotune")
+
+    def set_schedule(self, lanes_per_row, split=1, long_row=64, xcd_mode=0, blocks_per_xcd=128,
+                     nnz_per_item=2048):
+        q = deco_schedule(lanes_per_row, split, long_row, xcd_mode, blocks_per_xcd, nnz_per_item)
+        _check(lib().deco_set_schedule(self.h, ct.byref(q)), "deco_set_schedule")
 
     def schedule(self) -> str:
         buf = ct.create_string_buffer(512)
