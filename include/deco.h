@@ -184,6 +184,22 @@ typedef struct deco_schedule {
 } deco_schedule;
 deco_status deco_set_schedule(deco_handle *h, const deco_schedule *s);
 
+/* ---------------------------------------------------------------------------------
+ * Dense graphs (same method, Sec. 3.1 eq. (6)-(7) with a dense W): the gradient W X is a
+ * GEMM on the bfloat16 matrix cores with float32 accumulation, and the exact cut comes from
+ * the same GEMM against the sign matrix S = 2Z - 1: cut_b = 1/4 sum_v (d_w(v) - s_v (W s)_v),
+ * exact for integer weights of magnitude <= 1024 (W s is then an exact float32 integer).
+ * W: device bfloat16 n x n, row-major, symmetric, zero diagonal, caller-owned. Requires
+ * n % 128 == 0, B % 128 == 0, l == 1 (unlifted), x_dtype == DECO_BF16; otherwise
+ * DECO_E_UNSUPPORTED. The handle then works with deco_start (USER, UNIFORM and MEAN
+ * starts), deco_set_eta, deco_step, deco_round_score, deco_best, deco_read_x,
+ * deco_set_trace and deco_destroy. deco_dense_init validates W on the device
+ * (symmetry, diagonal, finiteness: DECO_E_INVAL / DECO_E_NONFINITE).
+ * --------------------------------------------------------------------------------- */
+deco_status deco_dense_workspace_size(int64_t n, const deco_params *p, size_t *bytes);
+deco_status deco_dense_init(deco_handle **out, int64_t n, const void *W, const deco_params *p, void *X,
+                            void *workspace, size_t workspace_bytes, void *stream);
+
 /* Describe the schedule in use (NUL-terminated text into buf[cap]). */
 deco_status deco_schedule_string(const deco_handle *h, char *buf, int32_t cap);
 

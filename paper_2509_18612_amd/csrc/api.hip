@@ -118,6 +118,7 @@ struct deco_handle {
   long long n = 0, nnz = 0;
   int G = 1, C = 1, NBY = 1, R = 1, dtype = 0;
   bool unit = true;
+  bool dense = false;  // dense-matrix (MFMA) path
   bool poisoned = false;
   Layout lay{};
   char* ws = nullptr;
@@ -306,7 +307,8 @@ deco_status launch_steps(deco_handle* h, int steps, int do_update, int force) {
   a.do_update = do_update;
   a.force_score = force;
   for (int s = 0; s < steps; ++s) {
-    const hipError_t e = launch_step(a, h->dtype, h->sched.vec, h->sched.grid, h->stream);
+    const hipError_t e = h->dense ? launch_dense_step(a, h->stream)
+                                  : launch_step(a, h->dtype, h->sched.vec, h->sched.grid, h->stream);
     if (e != hipSuccess) return poison(h, e);
   }
   return DECO_OK;
@@ -431,6 +433,9 @@ deco_status deco_init(deco_handle** out, const deco_graph* g, const deco_params*
   a.trace_cap = 1;
   a.ctrl = reinterpret_cast<DevCtrl*>(ws + lay.ctrl);
   a.do_update = 1;
+  a.cut_scale = 0.5;
+  a.dense_w = nullptr;
+  a.n = g->n;
 
   int* goff_dev = reinterpret_cast<int*>(ws + lay.goff);
   int* flags = reinterpret_cast<int*>(ws + lay.flags);
@@ -490,6 +495,7 @@ deco_status deco_start(deco_handle* h, const deco_start_args* s) {
   if (s->kind < DECO_INIT_USER || s->kind > DECO_INIT_MEAN) return DECO_E_INVAL;
   if (s->kind == DECO_INIT_USER && !s->x0) return DECO_E_INVAL;
   if (s->kind == DECO_INIT_MEAN && !s->mean_z) return DECO_E_INVAL;
+  if (h->dense && (s->kind == DECO_INIT_DUI || s->kind == DECO_INIT_IDI)) return DECO_E_UNSUPPORTED;
   if (!(s->scale > 0.0) || !(s->sigma2 >= 0.0) || !std::isfinite(s->scale) || !std::isfinite(s->sigma2))
     return DECO_E_INVAL;
   char* ws = h->ws;
@@ -660,6 +666,7 @@ int64_t deco_current_step(const deco_handle* h) { return h ? h->t_host : -1; }
 deco_status deco_autotune(deco_handle* h, int32_t steps) {
   if (!h || steps < 1) return DECO_E_INVAL;
   if (h->poisoned) return DECO_E_STATE;
+  if (h->dense) return DECO_OK;  // one fixed tiling
   const Schedule base = default_schedule(h);
   std::vector<Schedule> cand;
   const int vec = base.vec;
@@ -729,6 +736,7 @@ deco_status deco_autotune(deco_handle* h, int32_t steps) {
 deco_status deco_set_schedule(deco_handle* h, const deco_schedule* q) {
   if (!h || !q) return DECO_E_INVAL;
   if (h->poisoned) return DECO_E_STATE;
+  if (h->dense) return DECO_E_UNSUPPORTED;
   if (q->lanes_per_row < 1 || (q->lanes_per_row & (q->lanes_per_row - 1)) || q->split < 1 ||
       q->blocks_per_xcd < 1 || q->blocks_per_xcd > 4096 || q->nnz_per_item < 1 || q->nnz_per_item > kEmax ||
       (q->xcd_mode != 0 && q->xcd_mode != 1))
@@ -747,12 +755,120 @@ deco_status deco_set_schedule(deco_handle* h, const deco_schedule* q) {
 
 deco_status deco_schedule_string(const deco_handle* h, char* buf, int32_t cap) {
   if (!h || !buf || cap < 1) return DECO_E_INVAL;
+  if (h->dense) {
+    std::snprintf(buf, (size_t)cap, "dense bf16 MFMA 32x32x16: tiles 128x128x64, grid=%lld, R=%d",
+                  (long long)(h->n / 128) * (2 * h->C / 128), h->R);
+    return DECO_OK;
+  }
   const Schedule& s = h->sched;
   std::snprintf(buf, (size_t)cap,
                 "vec=%d Wc=%d split=%d dlong=%d tile=%d tiles=%d xcd_mode=%d grid=%d items=%d "
                 "rows_per_item=%d nnz_per_item=%d R=%d",
                 s.vec, s.Wc, s.split, s.dlong, s.Wc * s.vec, h->p.B / (s.Wc * s.vec), s.xcd_mode, s.grid, s.nitems,
                 s.rows_per_item, s.nnz_per_item, h->R);
+  return DECO_OK;
+}
+
+
+deco_status deco_dense_workspace_size(int64_t n, const deco_params* p, size_t* bytes) {
+  deco_status st = check_params(p);
+  if (st) return st;
+  if (!bytes || n < 1) return DECO_E_INVAL;
+  if (n % 128 != 0 || p->B % 128 != 0 || p->l != 1 || p->lifted || p->x_dtype != DECO_BF16 || n >= (1LL << 31))
+    return DECO_E_UNSUPPORTED;
+  *bytes = layout_for(n, 0, 1, p).total;
+  return DECO_OK;
+}
+
+deco_status deco_dense_init(deco_handle** out, int64_t n, const void* W, const deco_params* p, void* X,
+                            void* workspace, size_t workspace_bytes, void* stream) {
+  if (!out) return DECO_E_INVAL;
+  *out = nullptr;
+  size_t need = 0;
+  deco_status st = deco_dense_workspace_size(n, p, &need);
+  if (st) return st;
+  if (!W || !X || !workspace) return DECO_E_INVAL;
+  if (((uintptr_t)X % 16) != 0 || ((uintptr_t)W % 16) != 0 || ((uintptr_t)workspace % kAlign) != 0)
+    return DECO_E_INVAL;
+  if (workspace_bytes < need) return DECO_E_NOMEM;
+  const Layout lay = layout_for(n, 0, 1, p);
+  deco_handle* h = new deco_handle();
+  h->dense = true;
+  h->p = *p;
+  h->g.n = n;
+  h->g.nnz = 0;
+  h->g.num_graphs = 1;
+  h->stream = reinterpret_cast<hipStream_t>(stream);
+  h->n = n;
+  h->G = 1;
+  h->C = p->B;
+  h->NBY = nby_of(p->B);
+  h->R = lay.R;
+  h->dtype = DECO_BF16;
+  h->unit = false;
+  h->lay = lay;
+  h->ws = reinterpret_cast<char*>(workspace);
+  h->X = X;
+  h->goff_host = {0, (int)n};
+  char* ws = h->ws;
+  StepArgs& a = h->args;
+  a.dw = reinterpret_cast<float*>(ws + lay.dw);
+  a.x[0] = X;
+  a.x[1] = ws + lay.xalt;
+  a.C = h->C;
+  a.B = p->B;
+  a.L = 1;
+  a.lifted = 0;
+  a.cW = p->grad_form == DECO_GRAD_CUT ? -0.5f : -1.0f;
+  a.cD = p->grad_form == DECO_GRAD_CUT ? 0.0f : 1.0f;
+  a.eta = reinterpret_cast<float*>(ws + lay.eta);
+  a.bits[0] = reinterpret_cast<uint8_t*>(ws + lay.bits0);
+  a.bits[1] = reinterpret_cast<uint8_t*>(ws + lay.bits1);
+  a.best_bits = reinterpret_cast<uint8_t*>(ws + lay.best_bits);
+  a.mask = reinterpret_cast<uint8_t*>(ws + lay.mask);
+  a.NBY = h->NBY;
+  a.acc = reinterpret_cast<double*>(ws + lay.acc);
+  a.R = lay.R;
+  a.G = 1;
+  a.cur_cut = reinterpret_cast<double*>(ws + lay.cur_cut);
+  a.best_cut = reinterpret_cast<double*>(ws + lay.best_cut);
+  a.best_step = reinterpret_cast<int*>(ws + lay.best_step);
+  a.trace = nullptr;
+  a.trace_cap = 1;
+  a.ctrl = reinterpret_cast<DevCtrl*>(ws + lay.ctrl);
+  a.do_update = 1;
+  a.cut_scale = 0.25;
+  a.dense_w = reinterpret_cast<const uint16_t*>(W);
+  a.n = n;
+  int* goff_dev = reinterpret_cast<int*>(ws + lay.goff);
+  int* flags = reinterpret_cast<int*>(ws + lay.flags);
+  int hflags = 0;
+  hipError_t e = hipMemcpyAsync(goff_dev, h->goff_host.data(), sizeof(int) * 2, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(flags, 0, sizeof(int) * 4, h->stream);
+  if (e == hipSuccess) e = launch_dense_validate(a.dense_w, (int)n, const_cast<float*>(a.dw), flags, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    delete h;
+    return DECO_E_DEVICE;
+  }
+  if (hflags & (1 | 2)) {
+    delete h;
+    return DECO_E_INVAL;
+  }
+  if (hflags & 4) {
+    delete h;
+    return DECO_E_NONFINITE;
+  }
+  a.intw = (hflags & 16) ? 0 : 1;
+  e = launch_fill_eta(const_cast<float*>(a.eta), p->B, p->eta, h->stream);
+  if (e == hipSuccess) e = launch_reset(a, a.acc, (long long)lay.R * p->B, p->score_every, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    delete h;
+    return DECO_E_DEVICE;
+  }
+  *out = h;
   return DECO_OK;
 }
 

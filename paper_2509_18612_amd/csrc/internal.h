@@ -55,12 +55,18 @@ struct StepArgs {
   int do_update;    // 0: score-only pass (no new iterate, step counter unchanged)
   int force_score;  // score this launch regardless of score_every
   int intw;         // all weights are integers of magnitude <= 1024 (int32 score partials)
+  double cut_scale; // cut = cut_scale * accumulated sum (1/2 sparse path, 1/4 dense path)
+  const uint16_t* dense_w;  // dense path: bfloat16 n x n weight matrix (row-major)
+  long long n;      // rows
 };
 
 // Kernel launchers (kernels.hip). dtype: 0 float32, 1 bfloat16. vec: elements per lane
 // per load (the native 16-byte width, or 1).
 hipError_t launch_step(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s);
 int native_vec(int dtype);
+// Dense path: n % 128 == 0, C % 128 == 0, bfloat16 X and W, unlifted.
+hipError_t launch_dense_step(const StepArgs& a, hipStream_t s);
+hipError_t launch_dense_validate(const uint16_t* W, int n, float* dw, int* flags, hipStream_t s);
 
 hipError_t launch_validate(long long n, const int* rp, const int* ci, const float* w,
                            const int* goff, int G, float* dw, int* flags, hipStream_t s);

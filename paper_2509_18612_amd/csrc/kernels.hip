@@ -24,8 +24,9 @@
 //    through LDS in sub-group order (deterministic), then sub-group 0 finishes the row.
 // Score partials stay in registers (int32 for integer weights, exact; float otherwise)
 // until the item ends; then a wave reduction and an LDS reduction in double and one double
-// atomic per initialisation into one of R replicated accumulators. Completion uses a two-level ticket (per XCD, then global) so
-// no address takes more than one atomic per workgroup of one XCD. The last workgroup turns
+// atomic per initialisation into one of R replicated accumulators. Completion uses a
+// two-level ticket (per XCD, then global) so no address takes more than one atomic per
+// workgroup of one XCD. The last workgroup turns
 // the sums into cuts, updates best / best step / improvement mask and advances the step
 // counter; the next launch folds the improved cut bits into best_bits row by row, before
 // it overwrites that bit slot.
@@ -115,11 +116,11 @@ struct VecIO<uint16_t, 1> {
 // Side of one initialisation from its l component values (float32, order i = 0..l-1).
 template <int L>
 __device__ __forceinline__ bool side_of(const float (&x)[L], int lifted) {
-  if (!lifted) return x[0] > 0.0f;
   float s = 0.0f;
 #pragma unroll
   for (int i = 0; i < L; ++i) s = s + x[i];
-  return s >= 0.0f;
+  const bool pos = x[0] > 0.0f, nonneg = s >= 0.0f;  // both formed, then selected (no branch)
+  return lifted ? nonneg : pos;
 }
 
 constexpr int kThreads = 256;
@@ -217,18 +218,18 @@ __device__ __forceinline__ void gather_rows(const T* __restrict__ X, const int* 
             else
               acc[r][i][e] = fmaf(wk[r][q], xu[i][e], acc[r][i][e]);
           }
-        if (do_score && u[r][q] >= 0) {
-          const uint32_t d = side_mask<L, VEC>(xu, lifted) ^ zm[r];
+        if (do_score) {
+          // disagreement bits of this edge (padding slots gather zeros and are masked off)
+          const uint32_t d = (side_mask<L, VEC>(xu, lifted) ^ zm[r]) & (u[r][q] >= 0 ? 0xFFu : 0u);
 #pragma unroll
           for (int e = 0; e < VEC; ++e) {
-            if ((d >> e) & 1u) {
-              if (WM == kUnitW)
-                sc[e] += 1;
-              else if (WM == kIntW)
-                sc[e] += (int)wk[r][q];
-              else
-                sc[e] += wk[r][q];
-            }
+            const uint32_t bit = (d >> e) & 1u;  // branch-free accumulation
+            if (WM == kUnitW)
+              sc[e] += (int)bit;
+            else if (WM == kIntW)
+              sc[e] += (int)bit * (int)wk[r][q];
+            else
+              sc[e] += bit ? wk[r][q] : 0.0f;
           }
         }
       }
@@ -271,6 +272,69 @@ __device__ __forceinline__ void finish_row(const StepArgs& a, T* __restrict__ Y,
     const size_t bi = (size_t)row * a.NBY + (bl >> 3);
     if (m) a.best_bits[bi] = (uint8_t)((mb & ~m) | (mo & m));
     if (do_score) bw[bi] = (uint8_t)byte;
+  }
+}
+
+// Completion of one step launch: two-level ticket, then the last workgroup finishes the
+// step. Inside a launch, workgroups exchange data only through device-scope atomics (score
+// accumulators, tickets), so no L2 write-back fence is needed: every lane waits until its
+// own atomics are acknowledged, then one lane takes its XCD's ticket and the last workgroup
+// of each XCD takes the global ticket. Plain stores (iterate, bits) are consumed by the
+// next launch, after the kernel boundary. The last workgroup turns the accumulated sums
+// into cuts (cut = a.cut_scale * sum), updates best / best step / improvement mask and
+// advances the step counter. Every workgroup of the grid must call this exactly once.
+__device__ __forceinline__ void complete_step(const StepArgs& a, long long t, bool do_score, int par, int& s_last) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int xcd = blockIdx.x & 7;
+  const int nbx = ((int)gridDim.x - xcd + 7) >> 3;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (tid == 0) {
+    bool last = false;
+    const unsigned p = atomicAdd(&a.ctrl->xticket[xcd][0], 1u);
+    if (p == (unsigned)nbx - 1u) {
+      const unsigned q = atomicAdd(&a.ctrl->ticket, 1u);
+      last = (q == 7u);
+    }
+    s_last = last;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  const int GB = a.G * a.B;
+  if (do_score) {
+    const int chunk = a.B < 8 ? a.B : 8;
+    for (int base = 0; base < GB; base += (int)blockDim.x) {
+      const int idx = base + tid;
+      const bool in = idx < GB;
+      bool imp = false;
+      if (in) {
+        double s = 0.0;
+        for (int r = 0; r < a.R; ++r) {
+          double* p = a.acc + (size_t)r * GB + idx;
+          s += __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(p, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const double cut = a.cut_scale * s;
+        a.cur_cut[idx] = cut;
+        if (a.trace) a.trace[(size_t)(t % a.trace_cap) * GB + idx] = cut;
+        imp = cut > a.best_cut[idx];
+        if (imp) {
+          a.best_cut[idx] = cut;
+          a.best_step[idx] = (int)t;
+        }
+      }
+      const unsigned long long bal = __ballot(imp);
+      if (in && (idx % chunk) == 0) {
+        const int g = idx / a.B, b = idx % a.B;
+        a.mask[g * a.NBY + (b >> 3)] = (uint8_t)((bal >> lane) & ((1ull << chunk) - 1ull));
+      }
+    }
+  }
+  if (tid < 8) a.ctrl->xticket[tid][0] = 0u;
+  if (tid == 0) {
+    a.ctrl->pending_slot = do_score ? par : -1;
+    if (a.do_update) a.ctrl->t = t + 1;
+    a.ctrl->ticket = 0u;
   }
 }
 
@@ -485,60 +549,231 @@ void k_step(StepArgs a) {
     }
   }
 
-  // ---- completion: two-level ticket, then the last workgroup finishes the step.
-  // Inside a launch, workgroups exchange data only through device-scope atomics (score
-  // accumulators, tickets), so no L2 write-back fence is needed: every lane waits until its
-  // own atomics are acknowledged, then one lane takes the XCD ticket; the last workgroup of
-  // each XCD takes the global ticket. Plain stores (iterate, bits) are consumed by the next
-  // launch, after the kernel boundary.
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  if (tid == 0) {
-    bool last = false;
-    const unsigned p = atomicAdd(&a.ctrl->xticket[xcd][0], 1u);
-    if (p == (unsigned)nbx - 1u) {
-      const unsigned q = atomicAdd(&a.ctrl->ticket, 1u);
-      last = (q == 7u);
+  complete_step(a, t, do_score, par, s_last);
+}
+
+
+// ------------------------------------------------------------------ dense graphs: MFMA path
+// For a dense graph the gradient W X is a true GEMM. One launch computes
+//   P = W [X | S],  S = sign(X) in {-1, +1}   (bfloat16 operands, float32 accumulation)
+// with v_mfma_f32_32x32x16_bf16: 128 x 128 output tiles (4 waves, 64 x 64 each as 2 x 2
+// MFMA blocks), K steps of 64 staged through LDS (double-buffered; X is transposed into LDS
+// in 4-byte pairs so every MFMA operand is one 16-byte LDS read). Gradient tiles finish the
+// projected update; sign tiles score exactly: with s = 2z - 1,
+//   sum_u w_vu 1{z_u != z_v} = (d_w(v) - s_v (W s)_v) / 2,
+// and W s is exact in float32 for integer weights (integer sums below 2^24), so each tile
+// adds sum_v (d_w(v) - s_v (W s)_v) per column and the cut is 1/4 of the total. Sign tiles
+// also write the cut bits and fold the previous step's improvements into best_bits.
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
+
+constexpr int kDBM = 128, kDBN = 128, kDBK = 64, kDLd = kDBK + 8;  // LDS row: 144 bytes
+
+__device__ __forceinline__ uint32_t bf16_sign(uint32_t h) {
+  return ((h & 0x8000u) == 0u && (h & 0x7FFFu) != 0u) ? 0x3F80u : 0xBF80u;  // x > 0 ? +1 : -1
+}
+
+// Global -> register staging of one K step: A = 128 rows x 64 k of W (64 bytes per
+// thread), B = 64 k x 128 columns of X (two k rows x 16 columns per thread).
+__device__ __forceinline__ void dense_gload(const uint16_t* __restrict__ W, const uint16_t* __restrict__ X, int n,
+                                            int C, int row0, int col0, int k0, int tid, uint4 (&ra)[4],
+                                            uint4 (&rb)[2][2]) {
+  const uint4* pa = reinterpret_cast<const uint4*>(W + (size_t)(row0 + (tid >> 1)) * n + k0 + (tid & 1) * 32);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) ra[i] = pa[i];
+  const int kk = k0 + 2 * (tid & 31), nc = col0 + (tid >> 5) * 16;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const uint4* pb = reinterpret_cast<const uint4*>(X + (size_t)(kk + j) * C + nc);
+    rb[j][0] = pb[0];
+    rb[j][1] = pb[1];
+  }
+}
+
+// Register -> LDS: A as is ([m][k]); B transposed to [n][k] in 4-byte (k, k+1) pairs, as
+// signs (+-1) for sign tiles.
+__device__ __forceinline__ void dense_sstore(uint16_t (*As)[kDLd], uint16_t (*Bs)[kDLd], int tid, bool sign_tile,
+                                             const uint4 (&ra)[4], const uint4 (&rb)[2][2]) {
+  uint4* da = reinterpret_cast<uint4*>(&As[tid >> 1][(tid & 1) * 32]);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) da[i] = ra[i];
+  const int kp = tid & 31, nl0 = (tid >> 5) * 16;
+  const uint32_t w0[8] = {rb[0][0].x, rb[0][0].y, rb[0][0].z, rb[0][0].w, rb[0][1].x, rb[0][1].y, rb[0][1].z, rb[0][1].w};
+  const uint32_t w1[8] = {rb[1][0].x, rb[1][0].y, rb[1][0].z, rb[1][0].w, rb[1][1].x, rb[1][1].y, rb[1][1].z, rb[1][1].w};
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    uint32_t lo0 = w0[q] & 0xFFFFu, hi0 = w0[q] >> 16;  // row k: columns 2q, 2q+1
+    uint32_t lo1 = w1[q] & 0xFFFFu, hi1 = w1[q] >> 16;  // row k+1
+    if (sign_tile) {
+      lo0 = bf16_sign(lo0);
+      hi0 = bf16_sign(hi0);
+      lo1 = bf16_sign(lo1);
+      hi1 = bf16_sign(hi1);
     }
-    s_last = last;
+    *reinterpret_cast<uint32_t*>(&Bs[nl0 + 2 * q][2 * kp]) = lo0 | (lo1 << 16);
+    *reinterpret_cast<uint32_t*>(&Bs[nl0 + 2 * q + 1][2 * kp]) = hi0 | (hi1 << 16);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_dense_step(StepArgs a) {
+  __shared__ __align__(16) uint16_t As[2][kDBM][kDLd];
+  __shared__ __align__(16) uint16_t Bs[2][kDBN][kDLd];
+  __shared__ double s_col[2][kDBN];
+  __shared__ int s_last;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const long long t = a.ctrl->t;
+  const bool do_score = a.force_score || (t % a.ctrl->score_every) == 0;
+  const int pend = a.ctrl->pending_slot;
+  const int par = (int)(t & 1);
+  const uint16_t* __restrict__ X = reinterpret_cast<const uint16_t*>(a.x[par]);
+  uint16_t* __restrict__ Y = reinterpret_cast<uint16_t*>(a.x[par ^ 1]);
+  const int n = (int)a.n, C = a.C;
+  const int ctiles = C / kDBN;
+  const int mt = blockIdx.x / (2 * ctiles), nt = blockIdx.x % (2 * ctiles);
+  const bool sign_tile = nt >= ctiles;
+  const int col0 = (nt % ctiles) * kDBN, row0 = mt * kDBM;
+  const bool work = sign_tile ? do_score : (a.do_update != 0);
+
+  if (work) {
+    f32x16_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    uint4 ra[4], rb[2][2];
+    dense_gload(a.dense_w, X, n, C, row0, col0, 0, tid, ra, rb);
+    dense_sstore(As[0], Bs[0], tid, sign_tile, ra, rb);
+    __syncthreads();
+    const int hi = lane >> 5, lo = lane & 31;
+    for (int k0 = 0; k0 < n; k0 += kDBK) {
+      const int cur = (k0 / kDBK) & 1;
+      const bool more = k0 + kDBK < n;
+      if (more) dense_gload(a.dense_w, X, n, C, row0, col0, k0 + kDBK, tid, ra, rb);
+#pragma unroll
+      for (int ks = 0; ks < kDBK / 16; ++ks) {
+        bf16x8_t fa[2], fb[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          fa[i] = *reinterpret_cast<const bf16x8_t*>(&As[cur][wm * 64 + i * 32 + lo][ks * 16 + 8 * hi]);
+          fb[i] = *reinterpret_cast<const bf16x8_t*>(&Bs[cur][wn * 64 + i * 32 + lo][ks * 16 + 8 * hi]);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+      }
+      if (more) dense_sstore(As[cur ^ 1], Bs[cur ^ 1], tid, sign_tile, ra, rb);
+      __syncthreads();
+    }
+    // element (i, j, r) of this lane: row wm*64 + i*32 + 8*(r/4) + 4*hi + r%4, column wn*64 + j*32 + lo
+    if (!sign_tile) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int c = col0 + wn * 64 + j * 32 + lo;
+        const float eta = a.eta[c];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int v = row0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+            const size_t idx = (size_t)v * C + c;
+            const float x = bf2f(X[idx]);
+            float g = a.cW * acc[i][j][r];
+            if (a.cD != 0.0f) g = fmaf(a.cD * a.dw[v], x, g);
+            const float y = fminf(1.0f, fmaxf(-1.0f, fmaf(eta, g, x)));
+            Y[idx] = (uint16_t)f2bf(y);
+          }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int c = col0 + wn * 64 + j * 32 + lo;
+        float colsum = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int v = row0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+            const uint32_t hx = X[(size_t)v * C + c];
+            const bool z = (hx & 0x8000u) == 0u && (hx & 0x7FFFu) != 0u;
+            colsum += a.dw[v] - (z ? acc[i][j][r] : -acc[i][j][r]);
+            // cut bits of X_t and the fold of the previous step's improvements
+            const unsigned long long bal = __ballot(z);
+            if ((lo & 7) == 0) {
+              const size_t bi = (size_t)v * a.NBY + (c >> 3);
+              if (pend >= 0) {
+                const uint32_t m = a.mask[c >> 3];
+                if (m) {
+                  const uint32_t old = a.bits[pend][bi];
+                  const uint32_t bb = a.best_bits[bi];
+                  a.best_bits[bi] = (uint8_t)((bb & ~m) | (old & m));
+                }
+              }
+              a.bits[par][bi] = (uint8_t)((bal >> lane) & 0xFFu);
+            }
+          }
+        double d = (double)colsum;
+        d += __shfl_xor(d, 32);
+        if (hi == 0) s_col[wm][wn * 64 + j * 32 + lo] = d;
+      }
+      __syncthreads();
+      if (tid < kDBN) {
+        const double v = s_col[0][tid] + s_col[1][tid];
+        unsafeAtomicAdd(a.acc + (size_t)(blockIdx.x % a.R) * a.B + col0 + tid, v);
+      }
+    }
+  } else if (sign_tile && pend >= 0) {
+    // a step that does not score still folds the pending improvements of its tile
+    for (int e = tid; e < kDBM * (kDBN / 8); e += 256) {
+      const int v = row0 + e / (kDBN / 8);
+      const int by = (col0 >> 3) + e % (kDBN / 8);
+      const uint32_t m = a.mask[by];
+      if (m) {
+        const size_t bi = (size_t)v * a.NBY + by;
+        a.best_bits[bi] = (uint8_t)((a.best_bits[bi] & ~m) | (a.bits[pend][bi] & m));
+      }
+    }
+  }
+  complete_step(a, t, do_score, par, s_last);
+}
+
+// Dense-matrix checks: symmetric, zero diagonal, finite; row sums into dw.
+__global__ void k_dense_validate(const uint16_t* W, int n, float* dw, int* flags) {
+  const int v = blockIdx.x;
+  float s = 0.0f;
+  int f = 0;
+  for (int u = threadIdx.x; u < n; u += blockDim.x) {
+    const uint32_t h = W[(size_t)v * n + u];
+    const float w = bf2f(h);
+    if (!isfinite(w)) f |= 4;
+    if (u == v && h != 0u && h != 0x8000u) f |= 1;
+    if (W[(size_t)u * n + v] != h) f |= 2;
+    if (w != floorf(w) || fabsf(w) > 1024.0f) f |= 16;
+    s += w;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    s += __shfl_xor(s, o);
+    f |= __shfl_xor(f, o);
+  }
+  __shared__ float ss[16];
+  __shared__ int sf[16];
+  if ((threadIdx.x & 63) == 0) {
+    ss[threadIdx.x >> 6] = s;
+    sf[threadIdx.x >> 6] = f;
   }
   __syncthreads();
-  if (!s_last) return;
-  const int GB = a.G * a.B;
-  if (do_score) {
-    const int chunk = a.B < 8 ? a.B : 8;
-    for (int base = 0; base < GB; base += kThreads) {
-      const int idx = base + tid;
-      const bool in = idx < GB;
-      bool imp = false;
-      if (in) {
-        double s = 0.0;
-        for (int r = 0; r < a.R; ++r) {
-          double* p = a.acc + (size_t)r * GB + idx;
-          s += __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(p, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        const double cut = 0.5 * s;
-        a.cur_cut[idx] = cut;
-        if (a.trace) a.trace[(size_t)(t % a.trace_cap) * GB + idx] = cut;
-        imp = cut > a.best_cut[idx];
-        if (imp) {
-          a.best_cut[idx] = cut;
-          a.best_step[idx] = (int)t;
-        }
-      }
-      const unsigned long long bal = __ballot(imp);
-      if (in && (idx % chunk) == 0) {
-        const int g = idx / a.B, b = idx % a.B;
-        a.mask[g * a.NBY + (b >> 3)] = (uint8_t)((bal >> lane) & ((1ull << chunk) - 1ull));
-      }
+  if (threadIdx.x == 0) {
+    float tot = 0.0f;
+    int ff = 0;
+    for (int i = 0; i < (int)blockDim.x / 64; ++i) {
+      tot += ss[i];
+      ff |= sf[i];
     }
-  }
-  if (tid < 8) a.ctrl->xticket[tid][0] = 0u;
-  if (tid == 0) {
-    a.ctrl->pending_slot = do_score ? par : -1;
-    if (a.do_update) a.ctrl->t = t + 1;
-    a.ctrl->ticket = 0u;
+    dw[v] = tot;
+    if (ff) atomicOr(flags, ff);
   }
 }
 
@@ -801,6 +1036,17 @@ inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1)
 }  // namespace
 
 int native_vec(int dtype) { return dtype == 0 ? 4 : 8; }
+
+hipError_t launch_dense_step(const StepArgs& a, hipStream_t s) {
+  const int grid = (int)(a.n / kDBM) * (2 * a.C / kDBN);
+  hipLaunchKernelGGL(k_dense_step, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_validate(const uint16_t* W, int n, float* dw, int* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_validate, dim3(n), dim3(256), 0, s, W, n, dw, flags);
+  return hipGetLastError();
+}
 
 hipError_t launch_step(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s) {
   const int wmode = a.w == nullptr ? kUnitW : (a.intw ? kIntW : kRealW);

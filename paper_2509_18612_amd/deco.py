@@ -68,7 +68,8 @@ EXPORTS = ["deco_status_string", "deco_workspace_size", "deco_init", "deco_start
            "deco_round_score", "deco_best", "deco_read_x", "deco_set_trace", "deco_current_step",
            "deco_autotune", "deco_schedule_string", "deco_destroy", "deco_solve", "deco_evo_next",
            "deco_philox", "deco_philox_device", "deco_solver_create", "deco_solver_run",
-           "deco_solver_set_target", "deco_solver_destroy", "deco_set_schedule"]
+           "deco_solver_set_target", "deco_solver_destroy", "deco_set_schedule", "deco_dense_workspace_size",
+           "deco_dense_init"]
 
 _lib = None
 
@@ -100,6 +101,8 @@ def lib():
         L.deco_destroy.restype = None
         L.deco_solve.argtypes = [P, P, P, P, P, P, P, P]
         L.deco_set_schedule.argtypes = [P, P]
+        L.deco_dense_workspace_size.argtypes = [I64, P, ct.POINTER(ct.c_size_t)]
+        L.deco_dense_init.argtypes = [ct.POINTER(P), I64, P, P, P, P, ct.c_size_t, P]
         L.deco_solver_create.argtypes = [ct.POINTER(P), P, P, P]
         L.deco_solver_run.argtypes = [P, I32, P, P, P, P, P]
         L.deco_solver_set_target.argtypes = [P, P]
@@ -289,6 +292,35 @@ class Handle:
         buf = ct.create_string_buffer(512)
         _check(lib().deco_schedule_string(self.h, buf, 512), "deco_schedule_string")
         return buf.value.decode()
+
+
+class DenseHandle(Handle):
+    """Dense-matrix batch: W is a device bfloat16 n x n tensor (symmetric, zero diagonal)."""
+
+    def __init__(self, W, B: int, grad_form: int = GRAD_CUT, eta: float = 0.1, score_every: int = 1, seed: int = 0,
+                 stream=None):
+        import torch
+        self.torch = torch
+        n = int(W.shape[0])
+        self.W = W.contiguous()
+        self.graph = type("DenseGraph", (), {"n": n, "num_graphs": 1})()
+        self.B, self.l, self.lifted, self.C = int(B), 1, False, int(B)
+        self.x_dtype = BF16
+        self.params = deco_params(self.B, 1, 0, grad_form, BF16, score_every, eta, seed)
+        nbytes = ct.c_size_t(0)
+        _check(lib().deco_dense_workspace_size(n, ct.byref(self.params), ct.byref(nbytes)), "deco_dense_workspace_size")
+        self.ws_bytes = int(nbytes.value)
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.X = torch.empty((n, self.C), dtype=torch.bfloat16, device="cuda")
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device="cuda")
+        self.nby = (self.B + 7) // 8
+        self.G = 1
+        torch.cuda.synchronize()
+        h = ct.c_void_p()
+        _check(lib().deco_dense_init(ct.byref(h), n, self.W.data_ptr(), ct.byref(self.params), self.X.data_ptr(),
+                                     self.ws.data_ptr(), self.ws_bytes, ct.c_void_p(self.stream.cuda_stream)),
+               "deco_dense_init")
+        self.h = h
 
 
 # ------------------------------------------------------------------------ solve

@@ -1,0 +1,200 @@
+"""GPU parity at the full sizes of the workloads (same launch path as bench.py).
+
+The oracle cannot step a million-row batch quickly, so iterates are checked on sampled
+rows: the oracle steps a star subgraph made of each sampled row and its neighbours, which
+gives exactly that row's result. Cuts are checked on every graph and initialisation (the
+oracle's eq. (1) scorer is fast enough), bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_18612_amd import deco, synth
+
+from gpu_util import bf16_ulp, oracle_cuts, to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+
+def star_rows(g, rows):
+    """Block-diagonal union of stars (row v and its neighbours, edges v-u with w_vu)."""
+    rp = g.row_ptr.astype(np.int64)
+    us, vs, ws, offs = [], [], [], [0]
+    src_rows = []
+    base = 0
+    for v in rows:
+        nb = g.col_idx[rp[v]:rp[v + 1]].astype(np.int64)
+        k = len(nb)
+        us.append(np.full(k, base))
+        vs.append(base + 1 + np.arange(k))
+        if g.w is not None:
+            ws.append(g.w[rp[v]:rp[v + 1]])
+        src_rows.append(np.concatenate([[v], nb]))
+        base += 1 + k
+        offs.append(base)
+    u = np.concatenate(us) if us else np.zeros(0, np.int64)
+    w = np.concatenate(ws) if ws else None
+    mini = synth.from_edges(base, u, np.concatenate(vs), w)
+    return mini, np.concatenate(src_rows), np.array(offs[:-1])
+
+
+def check_rows(g, X_t, X_next, rows, eta, dtype, form=deco.GRAD_CUT):
+    mini, src, centre = star_rows(g, rows)
+    want = oracle.step(mini, X_t[src], eta, form)[centre]
+    got = X_next[rows]
+    if dtype == deco.BF16:
+        emu = oracle.to_bf16(want.astype(np.float32)).astype(np.float64)
+        d = np.abs(got - emu)
+        tol = bf16_ulp(emu) + 1e-5
+    else:
+        d = np.abs(got - want)
+        tol = 1e-5
+    assert np.all(d <= tol), f"max deviation {d.max():.3e}"
+    return float(d.max())
+
+
+def run_steps(G, g, B, l, lifted, dtype, steps, eta, kind=deco.INIT_IDI, seed=1):
+    h = deco.Handle(G, B=B, l=l, lifted=lifted, x_dtype=dtype, eta=eta, seed=seed)
+    h.start(kind, scale=1e4, sigma2=0.8, batch=0)
+    tr = h.set_trace(steps + 1)
+    xs = [to_np(h.read_x()).astype(np.float64)]
+    for _ in range(steps):
+        h.step(1, use_graph=True)
+        xs.append(to_np(h.read_x()).astype(np.float64))
+    return h, xs, tr.cpu().numpy()
+
+
+def test_er800_uniform_start_200_steps():
+    """ER(800, 0.06) seed 0, B = 16 uniform starts in [-1, 1], eta = 0.1, 200 steps, every
+    iterate rounded and scored: teacher-forced float32 parity on the first 50 steps (1e-5),
+    bit-exact cuts on all 201 iterates, running best equal to the oracle's bookkeeping."""
+    g = synth.erdos_renyi(800, 0.06, 0)
+    G = deco.Graph(g)
+    B, T = 16, 200
+    h = deco.Handle(G, B=B, eta=0.1, seed=0)
+    h.start(deco.INIT_UNIFORM, batch=0)
+    x0 = to_np(h.read_x()).astype(np.float64)
+    assert np.array_equal(x0, oracle.init_uniform(g.n, B, 0, 0))
+    tr = h.set_trace(T + 1)
+    xs = [x0]
+    for t in range(T):
+        h.step(1)
+        xs.append(to_np(h.read_x()).astype(np.float64))
+    h.round_score()
+    trn = tr.cpu().numpy()
+    best = np.full(B, -np.inf)
+    step = np.full(B, -1)
+    worst = 0.0
+    for t in range(T + 1):
+        cuts = oracle_cuts(g, xs[t], B, 1, False)[0][0]
+        assert np.array_equal(trn[t][0], cuts)
+        imp = cuts > best
+        best[imp] = cuts[imp]
+        step[imp] = t
+        if t < 50:
+            d = np.abs(xs[t + 1] - oracle.step(g, xs[t], 0.1)).max()
+            worst = max(worst, d)
+            assert d <= 1e-5
+    bc, bs, bb = h.best()
+    assert np.array_equal(bc[0], best) and np.array_equal(bs[0], step)
+    assert np.array_equal(oracle.cut_batch(g, deco.bits_to_z(bb, B))[0], best)
+    print(f"ER800: max per-step error {worst:.2e}, best cut {best.max():.0f}")
+    h.destroy()
+
+
+@pytest.mark.parametrize("dtype,l", [(deco.F32, 1), (deco.BF16, 1), (deco.F32, 4), (deco.BF16, 2)])
+def test_ba10k_B256_full_rows(dtype, l):
+    g = synth.barabasi_albert(10_000, 4, 0)
+    G = deco.Graph(g)
+    h, xs, tr = run_steps(G, g, 256, l, l > 1, dtype, 3, eta=0.05)
+    for t in range(3):
+        cuts = oracle_cuts(g, xs[t], 256, l, l > 1)[0]
+        assert np.array_equal(tr[t], cuts)
+        want = oracle.step(g, xs[t], 0.05)
+        if dtype == deco.BF16:
+            emu = oracle.to_bf16(want.astype(np.float32)).astype(np.float64)
+            assert np.all(np.abs(xs[t + 1] - emu) <= bf16_ulp(emu) + 2e-5)
+        else:
+            # hubs of degree ~400: float32 summation bound above 1e-5 on a few rows
+            assert np.abs(xs[t + 1] - want).max() <= 5e-5
+    h.destroy()
+
+
+def test_uneven_512_graph_batch():
+    """512 graphs (half ER(n~U{200..1200}, 0.15), half BA(n~U{100..2000}, m~U{2..6})) in one
+    persistent launch, B = 64, bfloat16 storage: exact cuts of all 512 x 64 (graph,
+    initialisation) pairs, sampled rows of every graph against the oracle."""
+    g = synth.uneven_batch(512, 7)
+    G = deco.Graph(g)
+    h, xs, tr = run_steps(G, g, 64, 1, False, deco.BF16, 2, eta=0.01)
+    for t in range(3):
+        assert np.array_equal(tr[t], oracle_cuts(g, xs[t], 64, 1, False)[0])
+    rng = np.random.default_rng(0)
+    goff = g.graph_row_offset
+    rows = np.concatenate([rng.integers(goff[i], goff[i + 1], 2) for i in range(512)])
+    for t in range(2):
+        check_rows(g, xs[t], xs[t + 1], rows, 0.01, deco.BF16)
+    bc, bs, bb = h.best()
+    assert np.array_equal(oracle.cut_batch(g, deco.bits_to_z(bb, 64)), bc)
+    print(f"uneven batch: n={g.n} nnz={g.nnz}; schedule {h.schedule()}")
+    h.destroy()
+
+
+def test_regular3_million_pm1_B128():
+    """Random 3-regular n = 1e6 with +-1 weights, B = 128, bfloat16: exact cuts for all 128
+    initialisations and 4000 sampled rows per step."""
+    g = synth.with_rademacher_weights(synth.random_regular3(1_000_000, 0), 3)
+    G = deco.Graph(g)
+    h = deco.Handle(G, B=128, x_dtype=deco.BF16, eta=0.1, seed=1)
+    h.start(deco.INIT_UNIFORM, batch=0)
+    tr = h.set_trace(4)
+    xs = [to_np(h.read_x()).astype(np.float64)]
+    for _ in range(2):
+        h.step(1, use_graph=True)
+        xs.append(to_np(h.read_x()).astype(np.float64))
+    rows = np.random.default_rng(1).integers(0, g.n, 4000)
+    for t in range(2):
+        check_rows(g, xs[t], xs[t + 1], rows, 0.1, deco.BF16)
+    trn = tr.cpu().numpy()
+    for t in range(2):
+        assert np.array_equal(trn[t], oracle_cuts(g, xs[t], 128, 1, False)[0])
+    h.destroy()
+
+
+def test_solve_small_graph_bounded_by_brute_force():
+    g = synth.erdos_renyi(18, 0.4, 3)
+    opt = oracle.brute_force(g)[0]
+    r = deco.solve(deco.Graph(g), B=32, K=8, l_max=4, rounds=3, evo_rounds=2, T_q=100, T_l=50, seed=3)
+    assert r["best_cut"][0] == oracle.cut(g, r["z"]) <= opt
+    assert r["best_cut"][0] >= 0.9 * opt
+    assert np.all(np.diff(r["round_best"][:, 0]) >= 0)
+
+
+@pytest.mark.parametrize("dtype", [deco.F32, deco.BF16])
+def test_solve_ba10k_exact_result_and_beats_greedy(dtype):
+    g = synth.barabasi_albert(10_000, 4, 0)
+    r = deco.solve(deco.Graph(g), B=256, K=8, l_max=4, rounds=3, evo_rounds=2, T_q=300, T_l=150, x_dtype=dtype,
+                   seed=1)
+    assert r["best_cut"][0] == oracle.cut(g, r["z"])  # the reported cut is the exact cut of the vector
+    gb, _ = oracle.greedy(g, orders=2, seed=1)
+    assert r["best_cut"][0] > gb
+    print(f"BA10k solve dtype={dtype}: {r['best_cut'][0]:.0f} (greedy {gb:.0f}) in {r['seconds']:.2f}s, "
+          f"genes {r['eq_best']:.2f} {r['el_best']:.2f} {r['l_best']}")
+
+
+def test_solver_object_continues_and_multi_graph():
+    gs = [synth.erdos_renyi(300, 0.1, i) for i in range(3)] + [synth.barabasi_albert(500, 3, 9)]
+    bd = synth.block_diagonal(gs)
+    s = deco.Solver(deco.Graph(bd), B=64, K=8, l_max=2, evo_rounds=1, T_q=100, T_l=50, seed=4)
+    r1 = s.run(2)
+    r2 = s.run(2)
+    assert r2["steps_done"] == 2 * r1["steps_done"]
+    assert np.all(r2["best_cut"] >= r1["best_cut"])
+    for i, gi in enumerate(gs):
+        o = bd.graph_row_offset
+        assert r2["best_cut"][i] == oracle.cut(gi, r2["z"][o[i]:o[i + 1]])
+    s.destroy()
