@@ -52,6 +52,72 @@ def time_step_kernel(deco, torch, G, B, l, dtype, steps, eta=0.01, seed=1):
     return ms, sched
 
 
+def time_handle(torch, h, steps, kind, **start):
+    """Average per-launch time (us) of h's step kernel, HIP events on its stream."""
+    h.start(kind, **start)
+    h.step(steps, use_graph=True)
+    h.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(h.stream)
+    h.step(steps, use_graph=True)
+    e1.record(h.stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / steps * 1e3
+
+
+def other_workloads(deco, synth, torch, which):
+    """Step-kernel measurements on the other workload shapes (not the benchmark value)."""
+    import numpy as np
+    out = {}
+    if "er800" in which:
+        g = synth.erdos_renyi(800, 0.06, 0)
+        h = deco.Handle(deco.Graph(g), B=16, eta=0.1)
+        us = time_handle(torch, h, 200, deco.INIT_UNIFORM)
+        A = algorithmic_bytes(g.n, g.nnz, 16, 1, 4, 0)
+        out["er800_B16_f32"] = {"us_per_step": round(us, 3), "edge_updates_per_s": g.nnz * 16 / us * 1e6,
+                                "hbm_frac": round(A / us / 1e3 / HBM_PEAK_GBS, 4), "schedule": h.schedule()}
+        h.destroy()
+    if "uneven" in which:
+        g = synth.uneven_batch(512, 7)
+        h = deco.Handle(deco.Graph(g), B=64, x_dtype=deco.BF16, eta=0.01)
+        h.autotune(5)
+        us = time_handle(torch, h, 50, deco.INIT_IDI, scale=1e4, sigma2=0.8)
+        A = algorithmic_bytes(g.n, g.nnz, 64, 512, 2, 0)
+        out["uneven512_B64_bf16"] = {"us_per_step": round(us, 2), "edge_updates_per_s": g.nnz * 64 / us * 1e6,
+                                     "hbm_frac": round(A / us / 1e3 / HBM_PEAK_GBS, 4), "n": g.n, "nnz": g.nnz,
+                                     "schedule": h.schedule()}
+        h.destroy()
+    if "reg3" in which:
+        g = synth.with_rademacher_weights(synth.random_regular3(1_000_000, 0), 3)
+        h = deco.Handle(deco.Graph(g), B=128, x_dtype=deco.BF16, eta=0.01)
+        h.autotune(5)
+        us = time_handle(torch, h, 40, deco.INIT_UNIFORM)
+        A = algorithmic_bytes(g.n, g.nnz, 128, 1, 2, 4)
+        out["reg3_1e6_pm1_B128_bf16"] = {"us_per_step": round(us, 2), "edge_updates_per_s": g.nnz * 128 / us * 1e6,
+                                         "achieved_GBs": round(A / us / 1e3, 1),
+                                         "hbm_frac": round(A / us / 1e3 / HBM_PEAK_GBS, 4),
+                                         "bytes_per_launch": A, "schedule": h.schedule()}
+        h.destroy()
+    if "dense" in which:
+        g = synth.erdos_renyi(8192, 0.5, 0)
+        W = torch.zeros((g.n, g.n), dtype=torch.float32, device="cuda")
+        rows = torch.from_numpy(np.repeat(np.arange(g.n), np.diff(g.row_ptr.astype(np.int64)))).cuda()
+        W[rows, torch.from_numpy(g.col_idx.astype(np.int64)).cuda()] = 1.0
+        Wb = W.to(torch.bfloat16)
+        del W
+        h = deco.DenseHandle(Wb, B=512, eta=0.01)
+        us = time_handle(torch, h, 20, deco.INIT_UNIFORM)
+        flop = 2.0 * 2 * g.n * g.n * 512  # W X and W sign(X)
+        tf = flop / us / 1e6
+        out["dense_er8192_B512_bf16_mfma"] = {"us_per_step": round(us, 2), "tflops": round(tf, 1),
+                                              "mfma_frac_bf16_dense": round(tf / 2500.0, 4),
+                                              "edge_updates_per_s": g.nnz * 512 / us * 1e6,
+                                              "flop_per_launch": flop}
+        h.destroy()
+    return out
+
+
 def cpu_baseline(oracle, csr, B, budget_s):
     """The oracle's batch (step + rounding + exact cut + running best per step, FP64,
     one thread) on the same graph, for as many steps as fit in about budget_s seconds."""
@@ -81,6 +147,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttc", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=200)
+    ap.add_argument("--others", default="er800,uneven,reg3,dense",
+                    help="comma list of other workload shapes to time (empty: none)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -141,6 +209,7 @@ def main():
                "sample": f"{k} oracle steps (FP64 step + rounding + exact cut + running best, unlifted, "
                          f"B={B}) on the same BA graph, {cdt:.1f}s on 1 thread"}
 
+    others = other_workloads(deco, synth, torch, set(filter(None, args.others.split(","))))
     ttc = None
     if not args.no_ttc:
         ttc = time_to_cut(deco, torch, G, B, K, l_max, args)
@@ -160,7 +229,8 @@ def main():
                   "hbm_frac": {"unlifted": round(A_q / (ms_q * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                "lifted": round(A_l / (ms_l * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
                   "schedule": {"unlifted": sched_q, "lifted": sched_l},
-                  "best_cut": float(res["best_cut"][0]), "genes": [res["eq_best"], res["el_best"], res["l_best"]]},
+                  "best_cut": float(res["best_cut"][0]), "genes": [res["eq_best"], res["el_best"], res["l_best"]],
+                  "workloads": others},
     }
     print(json.dumps(line), flush=True)
 

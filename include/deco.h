@@ -71,6 +71,8 @@ typedef int32_t deco_status;
 #define DECO_INIT_DUI 2     /* mean h ~ U[-(1-d_v/Delta), 1-d_v/Delta] per column */
 #define DECO_INIT_IDI 3     /* mean h = importance-based signs per column */
 #define DECO_INIT_MEAN 4    /* mean h = 2 z - 1 from a device byte vector z[n] */
+#define DECO_INIT_LEARNED 5 /* mean h = y_v * IDI sign (y: device float magnitudes[n], e.g. from
+                               deco_mpnn_forward) */
 
 /* Random draws: Philox4x32-10 (Salmon et al., SC'11) with key = (seed low, seed high)
  * and counter = (row, column, purpose, batch); purposes 1 uniform, 2 DUI, 3 IDI sign,
@@ -110,6 +112,7 @@ typedef struct deco_start_args {
   uint32_t batch;          /* batch index in the generator's counter */
   const int32_t *l_active; /* host [B] or NULL: components i >= l_active[b] of
                               initialisation b start at exactly 0 (and stay 0) */
+  const float *magnitude;  /* LEARNED: device [n] per-node magnitudes */
 } deco_start_args;
 
 typedef struct deco_handle deco_handle;
@@ -268,6 +271,35 @@ deco_status deco_solver_run(deco_solver *s, int32_t rounds, double *best_cut, ui
 /* Replace the early-stop targets (host [G]; NULL clears them). */
 deco_status deco_solver_set_target(deco_solver *s, const double *target_cut);
 void deco_solver_destroy(deco_solver *s);
+
+/* ---------------------------------------------------------------------------------
+ * Learned starting magnitudes (an extension; the paper's method is training-free): a
+ * 3-layer message-passing network over [d_v/dbar, m_v/dbar, log(1+d_v) - log(1+dbar)]
+ * (d = degree, m = mean neighbour degree, dbar = the graph's mean degree), hidden width
+ * 64, h <- relu(h Ws + mean_nbr(h) Wn + b), output y = sigmoid(h wo + bo) in (0, 1). The
+ * forward pass uses the parameters rounded to bfloat16 with float32 accumulation. The
+ * parameters are one packed device float32 vector of deco_mpnn_num_params() values in the
+ * order Ws1 (3x64), Wn1 (3x64), b1, Ws2 (64x64), Wn2, b2, Ws3, Wn3, b3, wo (64), bo (1);
+ * matrices row-major [input][output]. Training minimises mean_v (y_v - t_v)^2 against
+ * t_v = cut fraction of v's weight at a best vector (deco_mpnn_labels). All buffers are
+ * device memory owned by the caller; the workspace holds activations for the backward pass.
+ * --------------------------------------------------------------------------------- */
+int32_t deco_mpnn_num_params(void);
+deco_status deco_mpnn_workspace_size(const deco_graph *g, size_t *bytes);
+/* y[n] = network output per node. Asynchronous. */
+deco_status deco_mpnn_forward(const deco_graph *g, const float *params, float *y, void *workspace,
+                              size_t workspace_bytes, void *stream);
+/* Loss (host double, after a synchronisation) and its gradient with respect to the
+ * bfloat16-rounded parameters (device float32, same packing). */
+deco_status deco_mpnn_loss_grad(const deco_graph *g, const float *params, const float *target,
+                                float *grads, double *loss, void *workspace, size_t workspace_bytes,
+                                void *stream);
+/* One Adam step (Kingma and Ba; beta1 0.9, beta2 0.999, eps 1e-8) on the float32 masters;
+ * m, v: device moment buffers of the same size, zero before step 1. */
+deco_status deco_mpnn_adam(float *params, const float *grads, float *m, float *v, int32_t step, float lr,
+                           void *stream);
+/* t[v] = sum_u w_vu 1{z_u != z_v} / d_w(v) for a cut vector z (device bytes), 0 if isolated. */
+deco_status deco_mpnn_labels(const deco_graph *g, const uint8_t *z, float *target, void *stream);
 
 /* Host utility: one evolution step of Sec. 4.3 for the genome (eq, el, l). Members are
  * ranked by fitness (descending; ties to the lower index); the top half is kept in rank

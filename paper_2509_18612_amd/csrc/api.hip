@@ -492,10 +492,12 @@ deco_status deco_init(deco_handle** out, const deco_graph* g, const deco_params*
 deco_status deco_start(deco_handle* h, const deco_start_args* s) {
   if (!h || !s) return DECO_E_INVAL;
   if (h->poisoned) return DECO_E_STATE;
-  if (s->kind < DECO_INIT_USER || s->kind > DECO_INIT_MEAN) return DECO_E_INVAL;
+  if (s->kind < DECO_INIT_USER || s->kind > DECO_INIT_LEARNED) return DECO_E_INVAL;
+  if (s->kind == DECO_INIT_LEARNED && !s->magnitude) return DECO_E_INVAL;
   if (s->kind == DECO_INIT_USER && !s->x0) return DECO_E_INVAL;
   if (s->kind == DECO_INIT_MEAN && !s->mean_z) return DECO_E_INVAL;
-  if (h->dense && (s->kind == DECO_INIT_DUI || s->kind == DECO_INIT_IDI)) return DECO_E_UNSUPPORTED;
+  if (h->dense && (s->kind == DECO_INIT_DUI || s->kind == DECO_INIT_IDI || s->kind == DECO_INIT_LEARNED))
+    return DECO_E_UNSUPPORTED;
   if (!(s->scale > 0.0) || !(s->sigma2 >= 0.0) || !std::isfinite(s->scale) || !std::isfinite(s->sigma2))
     return DECO_E_INVAL;
   char* ws = h->ws;
@@ -539,7 +541,8 @@ deco_status deco_start(deco_handle* h, const deco_start_args* s) {
     ia.X = h->X;
     double* thr = reinterpret_cast<double*>(ws + lay.thr);
     int* delta = reinterpret_cast<int*>(ws + lay.delta);
-    if (s->kind == DECO_INIT_IDI || s->kind == DECO_INIT_DUI) {
+    ia.magnitude = s->magnitude;
+    if (s->kind == DECO_INIT_IDI || s->kind == DECO_INIT_DUI || s->kind == DECO_INIT_LEARNED) {
       // per-graph degree statistics on the host copy of row_ptr (Sec. 4.1)
       std::vector<double> th(h->G);
       std::vector<int> dl(h->G);

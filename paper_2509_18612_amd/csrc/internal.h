@@ -87,6 +87,7 @@ struct InitArgs {
   const int* delta;  // max degree per graph [G]
   const uint8_t* mean_z;
   const int* l_active; // device [B] or NULL
+  const float* magnitude; // learned magnitudes [n] or NULL
   int8_t* scratch;   // n*C bytes (IDI important signs)
   double scale, sd;
   unsigned long long seed;

@@ -293,8 +293,9 @@ __device__ __forceinline__ void complete_step(const StepArgs& a, long long t, bo
     bool last = false;
     const unsigned p = atomicAdd(&a.ctrl->xticket[xcd][0], 1u);
     if (p == (unsigned)nbx - 1u) {
+      const unsigned nx = gridDim.x < 8u ? gridDim.x : 8u;  // XCDs that received workgroups
       const unsigned q = atomicAdd(&a.ctrl->ticket, 1u);
-      last = (q == 7u);
+      last = (q == nx - 1u);
     }
     s_last = last;
   }
@@ -965,7 +966,7 @@ __global__ void k_init(InitArgs a) {
     const double half = dl > 0 ? 1.0 - (double)(a.rp[v + 1] - a.rp[v]) / (double)dl : 1.0;
     draw4(a.seed, (uint32_t)v, (uint32_t)c, kDui, a.batch, r);
     h = (2.0 * u24(r[0]) - 1.0) * half;
-  } else if (a.kind == 3) {  // IDI
+  } else if (a.kind == 3 || a.kind == 5) {  // IDI (kind 5: times a learned magnitude)
     const int8_t p = a.scratch[i];
     if (p != 0) {
       h = (double)p;
@@ -987,6 +988,7 @@ __global__ void k_init(InitArgs a) {
   } else if (a.kind == 4) {  // mean from a cut vector
     h = a.mean_z[v] ? 1.0 : -1.0;
   }
+  if (a.kind == 5) h *= (double)a.magnitude[v];
   double eps = 0.0;
   if (a.sd != 0.0) {
     draw4(a.seed, (uint32_t)v, (uint32_t)c, kGauss, a.batch, r);
@@ -1095,7 +1097,7 @@ hipError_t launch_fill_eta(float* eta, int B, float v, hipStream_t s) {
 hipError_t launch_init(const InitArgs& a, hipStream_t s) {
   const long long m = a.n * a.C;
   if (m <= 0) return hipSuccess;
-  if (a.kind == 3) {
+  if (a.kind == 3 || a.kind == 5) {
     hipLaunchKernelGGL(k_idi_sign, dim3(blocks_for(m, 256)), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

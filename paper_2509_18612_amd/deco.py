@@ -19,7 +19,7 @@ LIB_PATH = os.environ.get("DECO_LIBRARY", os.path.join(_HERE, "libdeco.so"))
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_NONFINITE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 GRAD_CUT, GRAD_LAPLACIAN = 0, 1
 F32, BF16 = 0, 1
-INIT_USER, INIT_UNIFORM, INIT_DUI, INIT_IDI, INIT_MEAN = 0, 1, 2, 3, 4
+INIT_USER, INIT_UNIFORM, INIT_DUI, INIT_IDI, INIT_MEAN, INIT_LEARNED = 0, 1, 2, 3, 4, 5
 
 
 class DecoError(RuntimeError):
@@ -41,7 +41,7 @@ class deco_params(ct.Structure):
 class deco_start_args(ct.Structure):
     _fields_ = [("kind", ct.c_int32), ("x0", ct.c_void_p), ("mean_z", ct.c_void_p), ("scale", ct.c_double),
                 ("sigma2", ct.c_double), ("beta", ct.c_double), ("batch", ct.c_uint32),
-                ("l_active", ct.c_void_p)]
+                ("l_active", ct.c_void_p), ("magnitude", ct.c_void_p)]
 
 
 class deco_solve_params(ct.Structure):
@@ -69,7 +69,8 @@ EXPORTS = ["deco_status_string", "deco_workspace_size", "deco_init", "deco_start
            "deco_autotune", "deco_schedule_string", "deco_destroy", "deco_solve", "deco_evo_next",
            "deco_philox", "deco_philox_device", "deco_solver_create", "deco_solver_run",
            "deco_solver_set_target", "deco_solver_destroy", "deco_set_schedule", "deco_dense_workspace_size",
-           "deco_dense_init"]
+           "deco_dense_init", "deco_mpnn_num_params", "deco_mpnn_workspace_size", "deco_mpnn_forward",
+           "deco_mpnn_loss_grad", "deco_mpnn_adam", "deco_mpnn_labels"]
 
 _lib = None
 
@@ -101,6 +102,12 @@ def lib():
         L.deco_destroy.restype = None
         L.deco_solve.argtypes = [P, P, P, P, P, P, P, P]
         L.deco_set_schedule.argtypes = [P, P]
+        L.deco_mpnn_num_params.argtypes = []
+        L.deco_mpnn_workspace_size.argtypes = [P, ct.POINTER(ct.c_size_t)]
+        L.deco_mpnn_forward.argtypes = [P, P, P, P, ct.c_size_t, P]
+        L.deco_mpnn_loss_grad.argtypes = [P, P, P, P, ct.POINTER(D), P, ct.c_size_t, P]
+        L.deco_mpnn_adam.argtypes = [P, P, P, P, I32, ct.c_float, P]
+        L.deco_mpnn_labels.argtypes = [P, P, P, P]
         L.deco_dense_workspace_size.argtypes = [I64, P, ct.POINTER(ct.c_size_t)]
         L.deco_dense_init.argtypes = [ct.POINTER(P), I64, P, P, P, P, ct.c_size_t, P]
         L.deco_solver_create.argtypes = [ct.POINTER(P), P, P, P]
@@ -219,7 +226,7 @@ class Handle:
 
     # -- API
     def start(self, kind=INIT_UNIFORM, x0=None, mean_z=None, scale=1.0, sigma2=0.0, beta=0.2, batch=0,
-              l_active: Optional[Sequence[int]] = None):
+              l_active: Optional[Sequence[int]] = None, magnitude=None):
         keep = []
         if x0 is not None:
             x0 = x0.contiguous()
@@ -230,8 +237,11 @@ class Handle:
         la = None
         if l_active is not None:
             la = np.ascontiguousarray(l_active, np.int32)
+        if magnitude is not None:
+            magnitude = magnitude.contiguous()
+            keep.append(magnitude)
         a = deco_start_args(kind, _ptr(x0), _ptr(mean_z), float(scale), float(sigma2), float(beta), int(batch),
-                            _ptr(la))
+                            _ptr(la), _ptr(magnitude))
         self.torch.cuda.current_stream().synchronize()
         _check(lib().deco_start(self.h, ct.byref(a)), "deco_start")
         self._keep = keep
@@ -321,6 +331,86 @@ class DenseHandle(Handle):
                                      self.ws.data_ptr(), self.ws_bytes, ct.c_void_p(self.stream.cuda_stream)),
                "deco_dense_init")
         self.h = h
+
+
+class Mpnn:
+    """Learned starting magnitudes: parameters and Adam moments on the device, forward /
+    loss-gradient / Adam / label kernels of the library (deco_mpnn_*)."""
+
+    def __init__(self, params=None, stream=None):
+        import torch
+        self.torch = torch
+        self.count = int(lib().deco_mpnn_num_params())
+        if params is None:
+            params = torch.zeros(self.count, dtype=torch.float32)
+        self.params = torch.as_tensor(params, dtype=torch.float32).reshape(-1).cuda().contiguous()
+        assert self.params.numel() == self.count
+        self.grads = torch.zeros_like(self.params)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = 0
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self._ws = None
+
+    def _workspace(self, graph: Graph):
+        nb = ct.c_size_t(0)
+        _check(lib().deco_mpnn_workspace_size(ct.byref(graph.struct), ct.byref(nb)), "deco_mpnn_workspace_size")
+        if self._ws is None or self._ws.numel() < nb.value:
+            self._ws = self.torch.empty(int(nb.value), dtype=self.torch.uint8, device="cuda")
+        return self._ws
+
+    def forward(self, graph: Graph):
+        ws = self._workspace(graph)
+        y = self.torch.empty(graph.n, dtype=self.torch.float32, device="cuda")
+        self.torch.cuda.current_stream().synchronize()
+        _check(lib().deco_mpnn_forward(ct.byref(graph.struct), self.params.data_ptr(), y.data_ptr(), ws.data_ptr(),
+                                       ws.numel(), ct.c_void_p(self.stream.cuda_stream)), "deco_mpnn_forward")
+        self.stream.synchronize()
+        return y
+
+    def loss_grad(self, graph: Graph, target):
+        ws = self._workspace(graph)
+        target = target.contiguous()
+        loss = ct.c_double(0.0)
+        self.torch.cuda.current_stream().synchronize()
+        _check(lib().deco_mpnn_loss_grad(ct.byref(graph.struct), self.params.data_ptr(), target.data_ptr(),
+                                         self.grads.data_ptr(), ct.byref(loss), ws.data_ptr(), ws.numel(),
+                                         ct.c_void_p(self.stream.cuda_stream)), "deco_mpnn_loss_grad")
+        return float(loss.value)
+
+    def adam(self, lr=1e-3):
+        self.t += 1
+        _check(lib().deco_mpnn_adam(self.params.data_ptr(), self.grads.data_ptr(), self.m.data_ptr(),
+                                    self.v.data_ptr(), self.t, lr, ct.c_void_p(self.stream.cuda_stream)),
+               "deco_mpnn_adam")
+        self.stream.synchronize()
+
+    def labels(self, graph: Graph, z):
+        z = self.torch.as_tensor(np.ascontiguousarray(z, np.uint8)).cuda()
+        t = self.torch.empty(graph.n, dtype=self.torch.float32, device="cuda")
+        self.torch.cuda.current_stream().synchronize()
+        _check(lib().deco_mpnn_labels(ct.byref(graph.struct), z.data_ptr(), t.data_ptr(),
+                                      ct.c_void_p(self.stream.cuda_stream)), "deco_mpnn_labels")
+        self.stream.synchronize()
+        return t
+
+
+def pack_mpnn(params: dict) -> np.ndarray:
+    """Pack a name -> array dict (ws1, wn1, b1, ..., wo, bo) in the library's order."""
+    order = ["ws1", "wn1", "b1", "ws2", "wn2", "b2", "ws3", "wn3", "b3", "wo", "bo"]
+    return np.concatenate([np.asarray(params[k], np.float32).reshape(-1) for k in order])
+
+
+def unpack_mpnn(vec) -> dict:
+    shapes = [("ws1", (3, 64)), ("wn1", (3, 64)), ("b1", (64,)), ("ws2", (64, 64)), ("wn2", (64, 64)),
+              ("b2", (64,)), ("ws3", (64, 64)), ("wn3", (64, 64)), ("b3", (64,)), ("wo", (64,)), ("bo", (1,))]
+    vec = np.asarray(vec, np.float64).reshape(-1)
+    out, o = {}, 0
+    for k, shp in shapes:
+        size = int(np.prod(shp))
+        out[k] = vec[o:o + size].reshape(shp)
+        o += size
+    return out
 
 
 # ------------------------------------------------------------------------ solve

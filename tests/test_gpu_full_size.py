@@ -65,6 +65,7 @@ def run_steps(G, g, B, l, lifted, dtype, steps, eta, kind=deco.INIT_IDI, seed=1)
     for _ in range(steps):
         h.step(1, use_graph=True)
         xs.append(to_np(h.read_x()).astype(np.float64))
+    h.round_score()  # scores X_steps into the trace
     return h, xs, tr.cpu().numpy()
 
 
