@@ -168,22 +168,24 @@ deco_status deco_set_trace(deco_handle *h, double *trace, int32_t capacity);
 /* Index of the current iterate (number of steps taken since deco_start). Host-side. */
 int64_t deco_current_step(const deco_handle *h);
 
-/* Choose the kernel schedule (b-tile width, row split, rows per work item, XCD layout)
+/* Choose the kernel schedule (b-tile width, long-row threshold, work item size, XCD layout)
  * by timing candidates for 'steps' steps each on the device; the winner is kept in the
  * handle and in a per-process cache keyed by the graph and batch shape. It overwrites X
  * and the running best (call deco_start afterwards). Synchronous. */
 deco_status deco_autotune(deco_handle *h, int32_t steps);
 
 /* Set the kernel schedule explicitly (instead of the default or the autotuner's choice).
- * lanes_per_row: lanes holding one row's initialisation tile (power of two <= 64; the tile
- * is lanes_per_row * (16 bytes / element size) columns and must divide B); split: lanes
- * groups sharing one row (power of two, lanes_per_row * split <= 64); long_row: rows with
- * more neighbours get a workgroup of their own (32..256); xcd_mode: 0 = each XCD owns a row
- * range for every tile, 1 = each XCD owns tiles; blocks_per_xcd: persistent workgroups per
- * XCD; nnz_per_item: target edges per work item (<= 2048). DECO_E_INVAL when the values do
- * not fit B or the limits. Synchronous (uploads the work list). */
+ * lanes_per_row: lanes of one row team, which holds one row's initialisation tile (power
+ * of two <= 64; the tile is lanes_per_row * (16 bytes / element size) columns, 8 bytes for
+ * lifted bfloat16; it must divide B, hold at most 256 columns, and at least 64 when 64
+ * divides B); long_row: rows with more neighbours get a work item of their own (>= 16; rows
+ * with more slots than nnz_per_item always do); xcd_mode: 0 = each XCD owns a row range
+ * for every tile, 1 = each XCD owns tiles; blocks_per_xcd: workgroups per XCD (1..4096;
+ * with more items than workgroups a workgroup walks several); nnz_per_item: target slots
+ * (edges plus rows) per work item (128..2048). DECO_E_INVAL when the values do not fit B
+ * or the limits. Synchronous (uploads the work list). */
 typedef struct deco_schedule {
-  int32_t lanes_per_row, split, long_row, xcd_mode, blocks_per_xcd, nnz_per_item;
+  int32_t lanes_per_row, long_row, xcd_mode, blocks_per_xcd, nnz_per_item;
 } deco_schedule;
 deco_status deco_set_schedule(deco_handle *h, const deco_schedule *s);
 

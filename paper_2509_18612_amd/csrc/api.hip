@@ -28,27 +28,28 @@ using namespace deco;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kMinChunkRows = 8;
+constexpr int kMinTile = 64;       // narrowest initialisation tile when B >= 64
+constexpr int kMinItemSlots = 128; // smallest nnz_per_item
+constexpr int kMaxBlocksPerXcd = 4096;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Schedule {
   int vec = 4;
-  int Wc = 1;
-  int split = 1;      // sub-groups sharing a row
-  int dlong = 64;     // rows with more neighbours get a workgroup of their own
+  int Wc = 1;         // lanes per row team
+  int dlong = 64;     // rows with more neighbours get a work item of their own
   int rows_per_item = 256;
   int nnz_per_item = 2048;
   int xcd_mode = 0;   // 0 rows per XCD, 1 initialisation tiles per XCD
   int blocks_per_xcd = 128;
   int grid = 0;
   int nitems = 0;
-  std::vector<int4> items;
+  std::vector<int4> items;  // {first row, end row, graph, tile | long << 16}
   int seg[9] = {0};
 };
 
 struct Layout {
   size_t xalt, bits0, bits1, best_bits, mask, acc, cur_cut, best_cut, best_step, ctrl, dw, eta,
-      items, seg, goff, thr, delta, l_active, flags, total;
+      slots, sw, items, seg, goff, thr, delta, l_active, flags, total;
   long long items_cap;
   int R;
 };
@@ -58,28 +59,30 @@ int nby_of(int B) { return (B + 7) / 8; }
 
 bool supported_B(int B) { return B == 1 || B == 2 || B == 4 || (B > 0 && B % 8 == 0); }
 
-int vec_for(int dtype, int B) { return (B % 8 == 0) ? native_vec(dtype) : 1; }
+int vec_for(int dtype, int B, int L) { return (B % 8 == 0) ? native_vec(dtype, L) : 1; }
 
-// Largest lane count per row (power of two, <= 64) whose tile divides B.
+// Largest lane count per row team (power of two, <= 64) whose tile divides B and holds at
+// most 256 initialisations.
 int max_wc(int vec, int B) {
   int wc = 1;
-  while (wc * 2 <= 64 && B % (wc * 2 * vec) == 0) wc *= 2;
+  while (wc * 2 <= 64 && wc * 2 * vec <= 256 && B % (wc * 2 * vec) == 0) wc *= 2;
   return wc;
 }
 
-Layout layout_for(long long n, long long nnz, int G, const deco_params* p) {
+Layout layout_for(long long n, long long nnz, int G, const deco_params* p, bool weighted) {
   Layout L{};
   const int C = p->l * p->B;
   const int NBY = nby_of(p->B);
-  const int vec = vec_for(p->x_dtype, p->B);
-  // initialisation tiles are at least 8 wide (or the whole of B < 8); row chunks hold at
-  // least kMinChunkRows rows except the last chunk of each graph
-  const long long nbt_max = p->B >= 8 ? p->B / 8 : 1;
+  const int vec = vec_for(p->x_dtype, p->B, p->l);
+  // initialisation tiles are at least kMinTile wide when kMinTile divides B, else at least
+  // 8 wide (or the whole of B < 8). A chunk
+  // and the row after it hold more than nnz_per_item >= kMinItemSlots slots, or the chunk
+  // holds kRmax rows, or ends a graph, or precedes a row isolated by the neighbour limit
+  // (at least 17 neighbours)
+  const long long nbt_max = p->B % kMinTile == 0 ? p->B / kMinTile : (p->B >= 8 ? p->B / 8 : 1);
   (void)vec;
   L.R = G >= 16 ? 1 : 16;
-  // chunks: at most n / kMinChunkRows full ones, plus per long row (at least 33
-  // neighbours) the row itself and one cut-short chunk before it, plus one per graph
-  L.items_cap = nbt_max * (n / kMinChunkRows + 2 * (nnz / 32) + (long long)G + 8);
+  L.items_cap = nbt_max * (2 * (n + nnz) / kMinItemSlots + n / kRmax + 2 * (nnz / 17) + (long long)G + 8);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -98,7 +101,9 @@ Layout layout_for(long long n, long long nnz, int G, const deco_params* p) {
   L.ctrl = take(sizeof(DevCtrl));
   L.dw = take(sizeof(float) * (size_t)n);
   L.eta = take(sizeof(float) * (size_t)p->B);
-  L.items = take(sizeof(int4) * (size_t)L.items_cap);
+  L.slots = take(sizeof(int) * (size_t)(n + nnz));
+  L.sw = take(weighted ? sizeof(float) * (size_t)(n + nnz) : 0);
+  L.items = take(2 * sizeof(int4) * (size_t)L.items_cap);
   L.seg = take(sizeof(int) * 16);
   L.goff = take(sizeof(int) * (size_t)(G + 1));
   L.thr = take(sizeof(double) * (size_t)G);
@@ -147,10 +152,10 @@ deco_status poison(deco_handle* h, hipError_t e) {
     if (e__ != hipSuccess) return poison((h), e__); \
   } while (0)
 
-// Split each graph's rows into work chunks: a row with more than dlong neighbours is a
-// chunk of its own (flag 1 in .w); other rows are grouped into chunks of at most kRmax and
-// rows_per_item rows and kEmax edges, closing a chunk at about nnz_per_item edges once it
-// holds kMinChunkRows rows.
+// Split each graph's rows into work chunks of about nnz_per_item slots (edges plus rows):
+// a chunk closes before the row that would take it past nnz_per_item slots or kRmax /
+// rows_per_item rows. A row of more than nnz_per_item slots or more than dlong neighbours
+// is a chunk of its own, flagged in .w as a long row when its slots exceed kEmax.
 std::vector<int4> row_chunks(const std::vector<int>& rp, const std::vector<int>& goff, int rows_per_item,
                              int nnz_per_item, int dlong) {
   std::vector<int4> ch;
@@ -160,24 +165,21 @@ std::vector<int4> row_chunks(const std::vector<int>& rp, const std::vector<int>&
     int start = -1;
     long long e = 0;
     for (int r = goff[g]; r < goff[g + 1]; ++r) {
-      const int d = rp[r + 1] - rp[r];
-      if (d > dlong) {
+      const int d = rp[r + 1] - rp[r] + 1;  // slots of the row
+      if (d - 1 > dlong || d > nnz_per_item) {
         if (start >= 0) ch.push_back(make_int4(start, r, g, 0));
         start = -1;
-        e = 0;
-        ch.push_back(make_int4(r, r + 1, g, 1 << 16));
+        ch.push_back(make_int4(r, r + 1, g, d > kEmax ? 1 << 16 : 0));
         continue;
       }
-      if (start >= 0) {
-        const int rows = r - start;
-        const bool fits = rows < rmax && e + d <= kEmax && (rows < kMinChunkRows || e + d <= nnz_per_item);
-        if (!fits) {
-          ch.push_back(make_int4(start, r, g, 0));
-          start = -1;
-          e = 0;
-        }
+      if (start >= 0 && (r - start >= rmax || e + d > nnz_per_item)) {
+        ch.push_back(make_int4(start, r, g, 0));
+        start = -1;
       }
-      if (start < 0) start = r;
+      if (start < 0) {
+        start = r;
+        e = 0;
+      }
       e += d;
     }
     if (start >= 0) ch.push_back(make_int4(start, goff[g + 1], g, 0));
@@ -204,9 +206,10 @@ std::vector<int> balance(const std::vector<int4>& ch, const std::vector<int>& rp
 bool build_schedule(deco_handle* h, Schedule& s) {
   const int B = h->p.B;
   const int Bt = s.Wc * s.vec;
-  if (Bt <= 0 || B % Bt != 0 || (B >= 8 && Bt % 8 != 0)) return false;
-  if (s.Wc > 64 || s.split < 1 || s.Wc * s.split > 64 || (s.split & (s.split - 1)) != 0) return false;
-  if (s.dlong < 32 || s.dlong > kEmax / kMinChunkRows) return false;
+  if (Bt <= 0 || Bt > 256 || B % Bt != 0 || (B >= 8 && Bt % 8 != 0)) return false;
+  if (B % kMinTile == 0 && Bt < kMinTile) return false;
+  if (s.Wc > 64) return false;
+  if (s.dlong < 16 || s.nnz_per_item < kMinItemSlots || s.nnz_per_item > kEmax) return false;
   const int nbt = B / Bt;
   auto ch = row_chunks(h->rp_host, h->goff_host, s.rows_per_item, s.nnz_per_item, s.dlong);
   std::vector<int4> items;
@@ -247,12 +250,19 @@ bool build_schedule(deco_handle* h, Schedule& s) {
 
 deco_status upload_schedule(deco_handle* h) {
   char* ws = h->ws;
-  HIP_TRY(h, hipMemcpyAsync(ws + h->lay.items, h->sched.items.data(), sizeof(int4) * h->sched.items.size(),
-                            hipMemcpyHostToDevice, h->stream));
+  // device form: {x, y, first slot, end slot}, {graph, tile, long-row flag, 0}
+  const std::vector<int>& rp = h->rp_host;
+  std::vector<int4> dev(2 * h->sched.items.size());
+  for (size_t i = 0; i < h->sched.items.size(); ++i) {
+    const int4 c = h->sched.items[i];
+    dev[2 * i] = make_int4(c.x, c.y, rp[c.x] + c.x, rp[c.y] + c.y);
+    dev[2 * i + 1] = make_int4(c.z, c.w & 0xFFFF, c.w >> 16, 0);
+  }
+  HIP_TRY(h, hipMemcpyAsync(ws + h->lay.items, dev.data(), sizeof(int4) * dev.size(), hipMemcpyHostToDevice,
+                            h->stream));
   HIP_TRY(h, hipMemcpyAsync(ws + h->lay.seg, h->sched.seg, sizeof(int) * 9, hipMemcpyHostToDevice, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   h->args.Wc = h->sched.Wc;
-  h->args.split = h->sched.split;
   for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
   h->graphs.clear();
   return DECO_OK;
@@ -260,18 +270,16 @@ deco_status upload_schedule(deco_handle* h) {
 
 Schedule default_schedule(deco_handle* h) {
   Schedule s;
-  s.vec = vec_for(h->dtype, h->p.B);
+  s.vec = vec_for(h->dtype, h->p.B, h->p.l);
   s.Wc = max_wc(s.vec, h->p.B);
-  // sub-groups per row: about one per 8 neighbours, within one wave
-  const double deg = h->n > 0 ? (double)h->nnz / (double)h->n : 0.0;
-  s.split = 1;
-  while (s.split * 2 * s.Wc <= 64 && s.split * 8 < deg) s.split *= 2;
-  s.dlong = 64;
+  s.dlong = 1 << 30;  // rows are isolated only by the item size
   s.xcd_mode = 0;
-  s.blocks_per_xcd = 128;
-  // about two items per workgroup of the persistent grid, within the LDS limits
-  const long long per = (h->nnz + 8LL * s.blocks_per_xcd * 2 - 1) / (8LL * s.blocks_per_xcd * 2);
-  s.nnz_per_item = (int)std::max<long long>(256, std::min<long long>(kEmax, per));
+  // one item per workgroup (the dispatcher balances the rest) and about as many items as
+  // workgroups fit on the chip at once (256 CUs x 3)
+  s.blocks_per_xcd = kMaxBlocksPerXcd;
+  const long long slots = h->nnz + h->n;
+  const long long per = (slots + 767) / 768;
+  s.nnz_per_item = (int)std::max<long long>(kMinItemSlots, std::min<long long>(kEmax, per));
   s.rows_per_item = kRmax;
   return s;
 }
@@ -286,7 +294,7 @@ std::tuple<long long, long long, int, int, int, int, int> cache_key(const deco_h
 deco_status check_graph_args(const deco_graph* g) {
   if (!g || g->n < 1 || g->nnz < 0 || !g->row_ptr || (g->nnz > 0 && !g->col_idx)) return DECO_E_INVAL;
   if (g->num_graphs < 1 || (g->num_graphs > 1 && !g->graph_row_offset)) return DECO_E_INVAL;
-  if (g->n >= (1LL << 31) - 1 || g->nnz >= (1LL << 31) - 1) return DECO_E_UNSUPPORTED;
+  if (g->n + g->nnz >= (1LL << 31) - 1) return DECO_E_UNSUPPORTED;  // slot indices are int32
   if (g->num_graphs > g->n) return DECO_E_INVAL;
   return DECO_OK;
 }
@@ -340,7 +348,7 @@ deco_status deco_workspace_size(const deco_graph* g, const deco_params* p, size_
   if (st) return st;
   if ((st = check_params(p))) return st;
   if (!bytes) return DECO_E_INVAL;
-  *bytes = layout_for(g->n, g->nnz, g->num_graphs, p).total;
+  *bytes = layout_for(g->n, g->nnz, g->num_graphs, p, g->w != nullptr).total;
   return DECO_OK;
 }
 
@@ -353,7 +361,7 @@ deco_status deco_init(deco_handle** out, const deco_graph* g, const deco_params*
   if ((st = check_params(p))) return st;
   if (!X || !workspace) return DECO_E_INVAL;
   if (((uintptr_t)X % 16) != 0 || ((uintptr_t)workspace % kAlign) != 0) return DECO_E_INVAL;
-  Layout lay = layout_for(g->n, g->nnz, g->num_graphs, p);
+  Layout lay = layout_for(g->n, g->nnz, g->num_graphs, p, g->w != nullptr);
   if (workspace_bytes < lay.total) return DECO_E_NOMEM;
 
   deco_handle* h = new deco_handle();
@@ -413,6 +421,8 @@ deco_status deco_init(deco_handle** out, const deco_graph* g, const deco_params*
   a.B = p->B;
   a.L = p->l;
   a.lifted = p->lifted;
+  a.slots = reinterpret_cast<int*>(ws + lay.slots);
+  a.sw = g->w ? reinterpret_cast<float*>(ws + lay.sw) : nullptr;
   a.items = reinterpret_cast<int4*>(ws + lay.items);
   a.seg = reinterpret_cast<int*>(ws + lay.seg);
   a.cW = p->grad_form == DECO_GRAD_CUT ? -0.5f : -1.0f;
@@ -460,6 +470,13 @@ deco_status deco_init(deco_handle** out, const deco_graph* g, const deco_params*
     return DECO_E_NONFINITE;
   }
   a.intw = (hflags & 16) ? 0 : 1;
+  e = launch_build_slots(g->n, g->nnz, g->row_ptr, g->col_idx, g->w, a.dw, const_cast<int*>(a.slots),
+                         const_cast<float*>(a.sw), h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    delete h;
+    return DECO_E_DEVICE;
+  }
 
   // schedule: cached winner of an earlier autotune for this shape, else the default
   {
@@ -674,23 +691,18 @@ deco_status deco_autotune(deco_handle* h, int32_t steps) {
   std::vector<Schedule> cand;
   const int vec = base.vec;
   const int wmax = max_wc(vec, h->p.B);
-  const double deg = h->n > 0 ? (double)h->nnz / (double)h->n : 0.0;
-  for (int Wc = wmax; Wc >= 1 && Wc * vec >= std::min(8, h->p.B) && Wc * 4 >= wmax; Wc /= 2) {
-    for (int split = 1; Wc * split <= 64 && (split == 1 || split * 2 <= deg); split *= 2) {
-      for (int dlong : {32, 64, 256}) {
-        for (int mode = 0; mode < 2; ++mode) {
-          if (mode == 1 && h->p.B / (Wc * vec) < 2) continue;
-          for (int bpx : {64, 128, 256}) {
-            Schedule s = base;
-            s.Wc = Wc;
-            s.split = split;
-            s.dlong = dlong;
-            s.xcd_mode = mode;
-            s.blocks_per_xcd = bpx;
-            const long long per = (h->nnz + 8LL * bpx * 2 - 1) / (8LL * bpx * 2);
-            s.nnz_per_item = (int)std::max<long long>(256, std::min<long long>(kEmax, per));
-            cand.push_back(s);
-          }
+  const int min_tile = h->p.B % kMinTile == 0 ? kMinTile : std::min(8, h->p.B);
+  for (int Wc = wmax; Wc >= 1 && Wc * vec >= min_tile && Wc * 4 >= wmax; Wc /= 2) {
+    for (int npi : {128, 256, 512, 1024, 2048}) {
+      for (int mode = 0; mode < 2; ++mode) {
+        if (mode == 1 && h->p.B / (Wc * vec) < 2) continue;
+        for (int bpx : {64, 256, kMaxBlocksPerXcd}) {
+          Schedule s = base;
+          s.Wc = Wc;
+          s.xcd_mode = mode;
+          s.blocks_per_xcd = bpx;
+          s.nnz_per_item = npi;
+          cand.push_back(s);
         }
       }
     }
@@ -740,13 +752,13 @@ deco_status deco_set_schedule(deco_handle* h, const deco_schedule* q) {
   if (!h || !q) return DECO_E_INVAL;
   if (h->poisoned) return DECO_E_STATE;
   if (h->dense) return DECO_E_UNSUPPORTED;
-  if (q->lanes_per_row < 1 || (q->lanes_per_row & (q->lanes_per_row - 1)) || q->split < 1 ||
-      q->blocks_per_xcd < 1 || q->blocks_per_xcd > 4096 || q->nnz_per_item < 1 || q->nnz_per_item > kEmax ||
+  if (q->lanes_per_row < 1 || (q->lanes_per_row & (q->lanes_per_row - 1)) ||
+      q->blocks_per_xcd < 1 || q->blocks_per_xcd > kMaxBlocksPerXcd || q->nnz_per_item < kMinItemSlots ||
+      q->nnz_per_item > kEmax || q->long_row < 16 ||
       (q->xcd_mode != 0 && q->xcd_mode != 1))
     return DECO_E_INVAL;
   Schedule s = default_schedule(h);
   s.Wc = q->lanes_per_row;
-  s.split = q->split;
   s.dlong = q->long_row;
   s.xcd_mode = q->xcd_mode;
   s.blocks_per_xcd = q->blocks_per_xcd;
@@ -765,9 +777,9 @@ deco_status deco_schedule_string(const deco_handle* h, char* buf, int32_t cap) {
   }
   const Schedule& s = h->sched;
   std::snprintf(buf, (size_t)cap,
-                "vec=%d Wc=%d split=%d dlong=%d tile=%d tiles=%d xcd_mode=%d grid=%d items=%d "
+                "vec=%d Wc=%d dlong=%d tile=%d tiles=%d xcd_mode=%d grid=%d items=%d "
                 "rows_per_item=%d nnz_per_item=%d R=%d",
-                s.vec, s.Wc, s.split, s.dlong, s.Wc * s.vec, h->p.B / (s.Wc * s.vec), s.xcd_mode, s.grid, s.nitems,
+                s.vec, s.Wc, s.dlong, s.Wc * s.vec, h->p.B / (s.Wc * s.vec), s.xcd_mode, s.grid, s.nitems,
                 s.rows_per_item, s.nnz_per_item, h->R);
   return DECO_OK;
 }
@@ -779,7 +791,7 @@ deco_status deco_dense_workspace_size(int64_t n, const deco_params* p, size_t* b
   if (!bytes || n < 1) return DECO_E_INVAL;
   if (n % 128 != 0 || p->B % 128 != 0 || p->l != 1 || p->lifted || p->x_dtype != DECO_BF16 || n >= (1LL << 31))
     return DECO_E_UNSUPPORTED;
-  *bytes = layout_for(n, 0, 1, p).total;
+  *bytes = layout_for(n, 0, 1, p, false).total;
   return DECO_OK;
 }
 
@@ -794,7 +806,7 @@ deco_status deco_dense_init(deco_handle** out, int64_t n, const void* W, const d
   if (((uintptr_t)X % 16) != 0 || ((uintptr_t)W % 16) != 0 || ((uintptr_t)workspace % kAlign) != 0)
     return DECO_E_INVAL;
   if (workspace_bytes < need) return DECO_E_NOMEM;
-  const Layout lay = layout_for(n, 0, 1, p);
+  const Layout lay = layout_for(n, 0, 1, p, false);
   deco_handle* h = new deco_handle();
   h->dense = true;
   h->p = *p;

@@ -18,14 +18,18 @@ struct DevCtrl {
   unsigned int xticket[8][64];  // per-XCD completion counters, 256 bytes apart
 };
 
-// Work-item limits of the step kernel (LDS staging of one item's CSR slice).
-constexpr int kEmax = 2048;  // edges staged at a time
+// Work-item limits of the step kernel (LDS staging of one item's slot list).
+constexpr int kEmax = 2048;  // slots staged at a time
 constexpr int kRmax = 512;   // rows of a normal item
 
-// One work item: rows [x, y) of graph z, initialisation tile (w & 0xFFFF); (w >> 16) != 0
-// marks a single long row handled by the whole workgroup.
-// Items are grouped by XCD: items[seg[x] .. seg[x+1]) run on workgroups with
-// blockIdx % 8 == x.
+// Slot list: row v occupies positions [row_ptr[v] + v, row_ptr[v+1] + v + 1): its own
+// index with the top bit set, then its neighbours in CSR order. The slot weights (weighted
+// graphs) hold the weighted degree at the row's own position and w_vu after it.
+//
+// One work item is two int4: {x, y, s0, s1} = rows [x, y) and their slots [s0, s1), then
+// {graph, initialisation tile, long-row flag, 0}; a long-row item is a single row handled
+// by the whole workgroup. Items are grouped by XCD: items[seg[x] .. seg[x+1]) run on
+// workgroups with blockIdx % 8 == x.
 
 struct StepArgs {
   const int* rp;
@@ -34,8 +38,9 @@ struct StepArgs {
   const float* dw;  // weighted degree (Laplacian form), may be NULL for the cut form
   void* x[2];       // ping-pong iterates; x[t & 1] holds X_t
   int C, B, L, lifted;
-  int Wc;           // lanes per row sub-group (power of two, <= 64)
-  int split;        // sub-groups sharing one row of a normal item (power of two, Wc*split <= 64)
+  int Wc;           // lanes per row team (power of two, <= 64; Wc * VEC <= 256)
+  const int* slots; // slot list (n + nnz)
+  const float* sw;  // slot weights (n + nnz), NULL for unit weights
   const int4* items;
   const int* seg;   // [9]
   float cW, cD;     // G = cW * (W X) + cD * (d_w . X)
@@ -61,15 +66,18 @@ struct StepArgs {
 };
 
 // Kernel launchers (kernels.hip). dtype: 0 float32, 1 bfloat16. vec: elements per lane
-// per load (the native 16-byte width, or 1).
+// per load (native_vec, or 1).
 hipError_t launch_step(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s);
-int native_vec(int dtype);
+int native_vec(int dtype, int L);
 // Dense path: n % 128 == 0, C % 128 == 0, bfloat16 X and W, unlifted.
 hipError_t launch_dense_step(const StepArgs& a, hipStream_t s);
 hipError_t launch_dense_validate(const uint16_t* W, int n, float* dw, int* flags, hipStream_t s);
 
 hipError_t launch_validate(long long n, const int* rp, const int* ci, const float* w,
                            const int* goff, int G, float* dw, int* flags, hipStream_t s);
+// Builds the slot list (and slot weights when w != NULL) of a validated graph.
+hipError_t launch_build_slots(long long n, long long nnz, const int* rp, const int* ci, const float* w,
+                              const float* dw, int* slots, float* sw, hipStream_t s);
 hipError_t launch_reset(StepArgs a, double* acc_all, long long acc_count, int score_every,
                         hipStream_t s);
 hipError_t launch_merge(StepArgs a, long long n, const int* goff, hipStream_t s);

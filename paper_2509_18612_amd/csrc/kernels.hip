@@ -9,27 +9,30 @@
 //     X_t+1 = clip(X_t[v] + eta_b (cW acc + cD d_w(v) X_t[v]), -1, 1)
 //     score += w_vu 1{z_t(v) != z_t(u)}                   (double, exact for integer w)
 //
-// Mapping. X is node-major: row v holds its l*B values contiguously. A row of one
-// initialisation tile (Bt = Wc*VEC columns, for every component) is handled by a
-// sub-group of Wc lanes with 16-byte loads; a 256-thread workgroup has NS = 256/Wc
-// sub-groups. Work items are row ranges of one graph and one tile, grouped per XCD
-// (workgroup i runs on XCD i % 8) and walked by a persistent grid:
-//  * a normal item (rows of degree <= the long-row threshold, at most kEmax edges and
-//    kRmax rows) first copies its row_ptr / col_idx / weight slice into LDS with coalesced
-//    loads, so no gather waits on a dependent index load. Sub-group s takes the rows whose
-//    first edge lies in the s-th equal share of the item's edges and walks RB of them at
-//    once, issuing their own-row loads and up to RB*U neighbour gathers together;
-//  * a long-row item holds one row: all sub-groups split its edges in contiguous chunks
-//    (staged through LDS kEmax at a time), and their float32 partial sums are reduced
-//    through LDS in sub-group order (deterministic), then sub-group 0 finishes the row.
+// Mapping. X is node-major: row v holds its l*B values contiguously. One initialisation
+// tile of a row (Bt = Wc*VEC columns, at most 256, for every component) is held by a row
+// team of Wc lanes with 16-byte loads (8-byte for lifted bfloat16 rows); a 256-thread
+// workgroup has NS = 256/Wc teams. The graph is read through its slot list: row v is its
+// own index (top bit set) followed by its neighbours, so a team walks a flat stream of
+// slots and never waits on a row boundary. Work items are row ranges of one graph and one
+// tile, grouped per XCD (workgroup i runs on XCD i % 8) and walked by a persistent grid:
+//  * a normal item (rows of degree <= the long-row threshold, at most kEmax slots and
+//    kRmax rows) copies its slots (and slot weights) into LDS with coalesced loads; team s
+//    takes the rows whose own slot lies in the s-th equal share of the item's slots and
+//    walks them in windows of W slots: all W gathers (own rows and neighbours alike) are
+//    issued before any is used, then folded in order, a self slot closing the previous
+//    row (update, store, cut bits) and opening its own;
+//  * a long-row item holds one row: every team takes a contiguous share of each staged
+//    chunk of its neighbour slots, and the float32 partial sums are reduced in a fixed
+//    order (butterfly inside a wave, then the waves in order through LDS) before team 0
+//    finishes the row.
 // Score partials stay in registers (int32 for integer weights, exact; float otherwise)
 // until the item ends; then a wave reduction and an LDS reduction in double and one double
-// atomic per initialisation into one of R replicated accumulators. Completion uses a
-// two-level ticket (per XCD, then global) so no address takes more than one atomic per
-// workgroup of one XCD. The last workgroup turns
-// the sums into cuts, updates best / best step / improvement mask and advances the step
-// counter; the next launch folds the improved cut bits into best_bits row by row, before
-// it overwrites that bit slot.
+// atomic per initialisation into one of R replicated accumulators. After its rows, an item
+// folds the previous scored step's improved cut bits into best_bits for its rows and tile.
+// Completion uses a two-level ticket (per XCD, then global) so no address takes more than
+// one atomic per workgroup of one XCD. The last workgroup turns the sums into cuts,
+// updates best / best step / improvement mask and advances the step counter.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -103,6 +106,25 @@ struct VecIO<uint16_t, 8> {
 };
 
 template <>
+struct VecIO<uint16_t, 4> {
+  using raw = uint2;
+  static __device__ __forceinline__ raw load_raw(const uint16_t* p) { return *reinterpret_cast<const uint2*>(p); }
+  static __device__ __forceinline__ raw zero() { return make_uint2(0u, 0u); }
+  static __device__ __forceinline__ void unpack(const raw& v, float (&o)[4]) {
+    o[0] = bf2f(v.x & 0xFFFFu);
+    o[1] = bf2f(v.x >> 16);
+    o[2] = bf2f(v.y & 0xFFFFu);
+    o[3] = bf2f(v.y >> 16);
+  }
+  static __device__ __forceinline__ void store(uint16_t* p, const float (&o)[4]) {
+    uint2 v;
+    v.x = f2bf(o[0]) | (f2bf(o[1]) << 16);
+    v.y = f2bf(o[2]) | (f2bf(o[3]) << 16);
+    *reinterpret_cast<uint2*>(p) = v;
+  }
+};
+
+template <>
 struct VecIO<uint16_t, 1> {
   using raw = uint32_t;
   static __device__ __forceinline__ raw load_raw(const uint16_t* p) { return *p; }
@@ -125,14 +147,15 @@ __device__ __forceinline__ bool side_of(const float (&x)[L], int lifted) {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
+constexpr int kSelfBit = (int)0x80000000;  // slot flag: the row's own entry
 
+// Slots gathered together by one row team: 16 loads of 16 bytes in flight per lane for
+// unlifted rows, 8 when the l > 1 components also hold registers (32 for one-element
+// lanes), divided among the l components.
 template <int L, int VEC>
 struct Tune {
-  // rows walked together per sub-group, and gathers issued per row per batch: 16 loads in
-  // flight per lane for float32 / scalar data, 8 for bfloat16 (8 values per load)
-  static constexpr int RB = (L == 1) ? 2 : 1;
-  static constexpr int kLoads = (VEC == 8) ? 8 : 16;
-  static constexpr int U = (kLoads / (L * RB)) < 2 ? 2 : kLoads / (L * RB);
+  static constexpr int kLoads = VEC == 1 ? 32 : (L == 1 ? 16 : 8);
+  static constexpr int W = kLoads / L < 1 ? 1 : kLoads / L;
 };
 
 // Weight modes: unit weights (no weight loads), integer weights of magnitude <= 1024
@@ -161,117 +184,157 @@ __device__ __forceinline__ uint32_t side_mask(const float (&x)[L][VEC], int lift
   return m;
 }
 
-// Accumulate the edges kb[r], kb[r] + S, ... < ke[r] of RB rows (indices and weights
-// from the LDS copy of the item's slice) into acc[r] and, when scoring, sc. Every batch
-// issues the gathers of all RB rows before any of them is used; the sides of the rows
-// themselves (zm) are formed only after the first batch is in flight.
-template <typename T, int VEC, int L, int WM, int RB>
-__device__ __forceinline__ void gather_rows(const T* __restrict__ X, const int* s_ci, const float* s_w,
-                                            const int (&kb)[RB], const int (&ke)[RB], int S, size_t C, size_t B,
-                                            int bl, const float (&xv)[RB][L][VEC], float (&acc)[RB][L][VEC],
-                                            uint32_t (&zm)[RB], typename ScoreType<WM>::type (&sc)[VEC],
-                                            bool do_score, int lifted) {
-  using IO = VecIO<T, VEC>;
-  constexpr int U = Tune<L, VEC>::U;
-  int len = 0;
+// Sides of the VEC initialisations of one lane from its l raw component vectors.
+template <typename T, int VEC, int L>
+__device__ __forceinline__ uint32_t side_mask_raw(const typename VecIO<T, VEC>::raw (&xr)[L], int lifted) {
+  float x[L][VEC];
 #pragma unroll
-  for (int r = 0; r < RB; ++r) len = max(len, ke[r] - kb[r]);
-  bool have_z = false;
-  for (int j = 0; j < len; j += U * S) {
-    int u[RB][U];
-    float wk[RB][U];
+  for (int i = 0; i < L; ++i) VecIO<T, VEC>::unpack(xr[i], x[i]);
+  return side_mask<L, VEC>(x, lifted);
+}
+
+// The open row of a team: its own values (storage format), the running neighbour sums,
+// its sides and its weighted degree (Laplacian form). A 'head' row is the continuation of
+// a row whose own slot lies in an earlier team's share: its sums go to that team.
+template <typename T, int L, int VEC>
+struct RowState {
+  typename VecIO<T, VEC>::raw xv[L];
+  float acc[L][VEC];
+  uint32_t zm;
+  int row;    // -1 while no row is open
+  float dsum;
+  bool head;  // continuation of an earlier team's row
+  bool lazy;  // zm not yet formed from xv
+};
+
+// A team's partial sums of its head row, for the team that owns the row.
+template <int L, int VEC>
+__device__ __forceinline__ void put_part(float* s_part, int idx, const float (&acc)[L][VEC]) {
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
+  for (int i = 0; i < L; ++i)
 #pragma unroll
-      for (int q = 0; q < U; ++q) {
-        const int k = kb[r] + j + q * S;
-        const bool ok = k < ke[r];
-        u[r][q] = ok ? s_ci[k] : -1;
-        wk[r][q] = ok ? (WM == kUnitW ? 1.0f : s_w[k]) : 0.0f;
+    for (int e = 0; e < VEC; ++e) s_part[idx + i * VEC + e] = acc[i][e];
+}
+
+// Projected update of one row and its cut bits for the lanes' initialisations. Every lane
+// of the team calls it (the bit byte is assembled with shuffles inside the team); 'lead'
+// lanes store.
+template <typename T, int VEC, int L>
+__device__ __forceinline__ void finish_row(const StepArgs& a, T* __restrict__ Y, uint8_t* __restrict__ bw,
+                                           bool do_score, bool lead, int bl, int lc, int gb,
+                                           const float (&eta)[VEC], const RowState<T, L, VEC>& st) {
+  if (a.do_update && lead) {
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      float xv[VEC], y[VEC];
+      VecIO<T, VEC>::unpack(st.xv[i], xv);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        float g = a.cW * st.acc[i][e];
+        if (a.cD != 0.0f) g = fmaf(a.cD * st.dsum, xv[e], g);
+        const float v = fmaf(eta[e], g, xv[e]);
+        y[e] = fminf(1.0f, fmaxf(-1.0f, v));
       }
-    typename IO::raw xr[RB][U][L];
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-      for (int q = 0; q < U; ++q)
-#pragma unroll
-        for (int i = 0; i < L; ++i)
-          xr[r][q][i] = u[r][q] >= 0 ? IO::load_raw(X + (size_t)u[r][q] * C + i * B + bl) : IO::zero();
-    if (!have_z) {
-#pragma unroll
-      for (int r = 0; r < RB; ++r) zm[r] = side_mask<L, VEC>(xv[r], lifted);
-      have_z = true;
+      VecIO<T, VEC>::store(Y + (size_t)st.row * a.C + (size_t)i * a.B + bl, y);
     }
+  }
+  // cut bits of X_t: one byte per 8 initialisations, assembled over gb lanes
+  uint32_t byte = (st.zm & ((1u << VEC) - 1u)) << ((lc * VEC) & 7);
+  for (int s = 1; s < gb; s <<= 1) byte |= __shfl_xor(byte, s);
+  if (do_score && lead && (lc % gb) == 0) bw[(size_t)st.row * a.NBY + (bl >> 3)] = (uint8_t)byte;
+}
+
+// One window of the team's slot range: slots [p, min(p + W, pe)) of the staged list. All
+// gathers of the window are issued before any is used; then the slots are folded in list
+// order. A self slot (SELF lists only) finishes the open row and opens its own; a
+// neighbour slot adds w * x_u to the open row's sums and, when scoring, w to the
+// initialisations whose sides differ. Sides follow the rounding rule: x_0 > 0 unlifted,
+// the float32 sum of the components in component order >= 0 lifted.
+template <typename T, int VEC, int L, int WM, bool SELF>
+__device__ __forceinline__ void gather_window(const StepArgs& a, const T* __restrict__ X, T* __restrict__ Y,
+                                              uint8_t* __restrict__ bw, const int* s_slot, const float* s_sw,
+                                              float* s_part, int part_idx, int p, int pe, int bl, int lc, int gb,
+                                              const float (&eta)[VEC], RowState<T, L, VEC>& st,
+                                              typename ScoreType<WM>::type (&sc)[VEC], bool do_score) {
+  using IO = VecIO<T, VEC>;
+  constexpr int W = Tune<L, VEC>::W;
+  const size_t C = (size_t)a.C, B = (size_t)a.B;
+  int sl[W];
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
+  for (int q = 0; q < W; ++q) sl[q] = (p + q < pe) ? s_slot[p + q] : 0;
+  typename IO::raw xr[W][L];
 #pragma unroll
-      for (int q = 0; q < U; ++q) {
-        float xu[L][VEC];
+  for (int q = 0; q < W; ++q) {
+    const bool ok = p + q < pe;
+    const size_t node = (size_t)(sl[q] & 0x7FFFFFFF);
 #pragma unroll
-        for (int i = 0; i < L; ++i) IO::unpack(xr[r][q][i], xu[i]);
+    for (int i = 0; i < L; ++i) xr[q][i] = ok ? IO::load_raw(X + node * C + i * B + bl) : IO::zero();
+  }
+  if (st.lazy) {
+    st.zm = side_mask_raw<T, VEC, L>(st.xv, a.lifted);
+    st.lazy = false;
+  }
 #pragma unroll
-        for (int i = 0; i < L; ++i)
+  for (int q = 0; q < W; ++q) {
+    if (p + q < pe) {
+      const bool self = SELF && sl[q] < 0;
+      const float wq = WM == kUnitW ? 1.0f : s_sw[p + q];
+      if (self && st.row >= 0) {
+        if (st.head)
+          put_part<L, VEC>(s_part, part_idx, st.acc);
+        else
+          finish_row<T, VEC, L>(a, Y, bw, do_score, true, bl, lc, gb, eta, st);
+      }
+      float ssum[VEC], x0[VEC];
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) {
-            if (WM == kUnitW)
-              acc[r][i][e] += xu[i][e];
-            else
-              acc[r][i][e] = fmaf(wk[r][q], xu[i][e], acc[r][i][e]);
+      for (int i = 0; i < L; ++i) {
+        float xu[VEC];
+        IO::unpack(xr[q][i], xu);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          if (i == 0) {
+            x0[e] = xu[e];
+            ssum[e] = 0.0f + xu[e];
+          } else {
+            ssum[e] = ssum[e] + xu[e];
           }
+          if (self)
+            st.acc[i][e] = 0.0f;
+          else if (WM == kUnitW)
+            st.acc[i][e] += xu[e];
+          else
+            st.acc[i][e] = fmaf(wq, xu[e], st.acc[i][e]);
+        }
+        if (self) st.xv[i] = xr[q][i];
+      }
+      uint32_t sm = 0;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const bool pos = x0[e] > 0.0f, nonneg = ssum[e] >= 0.0f;
+        sm |= ((a.lifted ? nonneg : pos) ? 1u : 0u) << e;
+      }
+      if (self) {
+        st.row = sl[q] & 0x7FFFFFFF;
+        st.zm = sm;
+        st.dsum = WM == kUnitW ? 0.0f : wq;
+        st.head = false;
+      } else {
+        if (SELF && WM == kUnitW) st.dsum += 1.0f;
         if (do_score) {
-          // disagreement bits of this edge (padding slots gather zeros and are masked off)
-          const uint32_t d = (side_mask<L, VEC>(xu, lifted) ^ zm[r]) & (u[r][q] >= 0 ? 0xFFu : 0u);
+          const uint32_t d = sm ^ st.zm;
 #pragma unroll
           for (int e = 0; e < VEC; ++e) {
             const uint32_t bit = (d >> e) & 1u;  // branch-free accumulation
             if (WM == kUnitW)
               sc[e] += (int)bit;
             else if (WM == kIntW)
-              sc[e] += (int)bit * (int)wk[r][q];
+              sc[e] += (int)bit * (int)wq;
             else
-              sc[e] += bit ? wk[r][q] : 0.0f;
+              sc[e] += bit ? wq : 0.0f;
           }
         }
       }
-  }
-  if (!have_z) {
-#pragma unroll
-    for (int r = 0; r < RB; ++r) zm[r] = side_mask<L, VEC>(xv[r], lifted);
-  }
-}
-
-// Projected update of one row (team leader lanes), its cut bits, and the fold of the
-// previous scored step's improvements into best_bits (inputs prefetched by the caller).
-template <typename T, int VEC, int L>
-__device__ __forceinline__ void finish_row(const StepArgs& a, T* __restrict__ Y, uint8_t* __restrict__ bw,
-                                           bool do_score, int row, bool active, int bl, int lc, int gb,
-                                           const float (&xv)[L][VEC], const float (&acc)[L][VEC], uint32_t zm,
-                                           uint32_t m, uint32_t mo, uint32_t mb) {
-  if (a.do_update && active) {
-    const float dwv = (a.cD != 0.0f) ? a.dw[row] : 0.0f;
-    float eta[VEC];
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) eta[e] = a.eta[bl + e];
-#pragma unroll
-    for (int i = 0; i < L; ++i) {
-      float y[VEC];
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        float g = a.cW * acc[i][e];
-        if (a.cD != 0.0f) g = fmaf(a.cD * dwv, xv[i][e], g);
-        const float v = fmaf(eta[e], g, xv[i][e]);
-        y[e] = fminf(1.0f, fmaxf(-1.0f, v));
-      }
-      VecIO<T, VEC>::store(Y + (size_t)row * a.C + (size_t)i * a.B + bl, y);
     }
-  }
-  // cut bits of X_t: one byte per 8 initialisations, assembled over gb lanes
-  uint32_t byte = (zm & ((1u << VEC) - 1u)) << ((lc * VEC) & 7);
-  for (int s = 1; s < gb; s <<= 1) byte |= __shfl_xor(byte, s);
-  if (active && (lc % gb) == 0) {
-    const size_t bi = (size_t)row * a.NBY + (bl >> 3);
-    if (m) a.best_bits[bi] = (uint8_t)((mb & ~m) | (mo & m));
-    if (do_score) bw[bi] = (uint8_t)byte;
   }
 }
 
@@ -281,8 +344,10 @@ __device__ __forceinline__ void finish_row(const StepArgs& a, T* __restrict__ Y,
 // own atomics are acknowledged, then one lane takes its XCD's ticket and the last workgroup
 // of each XCD takes the global ticket. Plain stores (iterate, bits) are consumed by the
 // next launch, after the kernel boundary. The last workgroup turns the accumulated sums
-// into cuts (cut = a.cut_scale * sum), updates best / best step / improvement mask and
-// advances the step counter. Every workgroup of the grid must call this exactly once.
+// into cuts (cut = a.cut_scale * sum, replicas added in replica order), updates best /
+// best step / improvement mask and advances the step counter. Every workgroup of the grid
+// must call this exactly once.
+constexpr int kMaxReplicas = 16;
 __device__ __forceinline__ void complete_step(const StepArgs& a, long long t, bool do_score, int par, int& s_last) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int xcd = blockIdx.x & 7;
@@ -309,12 +374,20 @@ __device__ __forceinline__ void complete_step(const StepArgs& a, long long t, bo
       const bool in = idx < GB;
       bool imp = false;
       if (in) {
+        // all replica loads in flight together, summed in replica order
+        double v[kMaxReplicas];
+#pragma unroll
+        for (int r = 0; r < kMaxReplicas; ++r)
+          v[r] = r < a.R ? __hip_atomic_load(a.acc + (size_t)r * GB + idx, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT)
+                         : 0.0;
         double s = 0.0;
-        for (int r = 0; r < a.R; ++r) {
-          double* p = a.acc + (size_t)r * GB + idx;
-          s += __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(p, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+#pragma unroll
+        for (int r = 0; r < kMaxReplicas; ++r) s += v[r];
+#pragma unroll
+        for (int r = 0; r < kMaxReplicas; ++r)
+          if (r < a.R)
+            __hip_atomic_store(a.acc + (size_t)r * GB + idx, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const double cut = a.cut_scale * s;
         a.cur_cut[idx] = cut;
         if (a.trace) a.trace[(size_t)(t % a.trace_cap) * GB + idx] = cut;
@@ -340,21 +413,23 @@ __device__ __forceinline__ void complete_step(const StepArgs& a, long long t, bo
 }
 
 #ifndef DECO_STEP_WAVES_PER_EU
-#define DECO_STEP_WAVES_PER_EU 1
+#define DECO_STEP_WAVES_PER_EU 3
 #endif
 
 template <typename T, int VEC, int L, int WM>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(DECO_STEP_WAVES_PER_EU)))
 void k_step(StepArgs a) {
-  constexpr int RB = Tune<L, VEC>::RB;
+  constexpr int W = Tune<L, VEC>::W;
   using ST = typename ScoreType<WM>::type;
   using IO = VecIO<T, VEC>;
-  __shared__ int s_ci[kEmax];
-  __shared__ float s_w[WM == kUnitW ? 1 : kEmax];
+  __shared__ int s_slot[kEmax];
+  __shared__ float s_sw[WM == kUnitW ? 1 : kEmax];
   __shared__ int s_rp[kRmax + 1];
-  // score flush (double per initialisation per wave) / long-row reduction (float per lane)
-  constexpr int kRedBytes = (kWaves * 64 * VEC * 8 > kThreads * L * VEC * 4) ? kWaves * 64 * VEC * 8
-                                                                              : kThreads * L * VEC * 4;
+  // score flush (double per initialisation of the tile per wave) / partial sums of the
+  // teams (float per lane, component and initialisation) / long-row reduction (float per
+  // component and initialisation of the tile per wave)
+  constexpr int kRedBytes = kWaves * (L * 256 * 4 > 256 * 8 ? L * 256 * 4 : 256 * 8);
+  static_assert(kThreads * L * VEC * 4 <= kRedBytes, "partial sums of the teams");
   __shared__ __align__(16) unsigned char s_red_raw[kRedBytes];
   __shared__ int s_last;
   double* s_red = reinterpret_cast<double*>(s_red_raw);
@@ -364,12 +439,9 @@ void k_step(StepArgs a) {
   const int lane = tid & 63;
   const int wv = tid >> 6;
   const int Wc = a.Wc;
-  const int S = a.split;        // sub-groups per row (a team) in normal items
-  const int NS = kThreads / Wc;
-  const int NT = NS / S;
+  const int NS = kThreads / Wc;  // row teams (sub-groups of Wc lanes) per workgroup
   const int lc = tid & (Wc - 1);
   const int sgi = tid / Wc;
-  const int team = sgi / S, mem = sgi % S;
 
   const long long t = a.ctrl->t;
   const bool do_score = a.force_score || (t % a.ctrl->score_every) == 0;
@@ -379,7 +451,6 @@ void k_step(StepArgs a) {
   T* __restrict__ Y = reinterpret_cast<T*>(a.x[par ^ 1]);
   uint8_t* __restrict__ bw = a.bits[par];
   const uint8_t* bm = pend >= 0 ? a.bits[pend] : nullptr;
-  const size_t C = (size_t)a.C, B = (size_t)a.B;
   const int Bt = Wc * VEC;
   const int gb = VEC >= 8 ? 1 : (8 / VEC < Wc ? 8 / VEC : Wc);
 
@@ -395,8 +466,11 @@ void k_step(StepArgs a) {
 
   for (int it = it0 + kb;; it += nbx) {
     const bool have = it < it1;
-    int4 item = make_int4(0, 0, -1, -1);
-    if (have) item = a.items[it];
+    int4 hd = make_int4(0, 0, 0, 0), tl = make_int4(0, 0, 0, 0);
+    if (have) {
+      hd = a.items[2 * it];
+      tl = a.items[2 * it + 1];
+    }
     if (do_score && cg >= 0) {
       // flush the previous item's score partials: wave, then workgroup, then one atomic
       double d[VEC];
@@ -408,15 +482,15 @@ void k_step(StepArgs a) {
       __syncthreads();
       if (lane < Wc) {
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) s_red[wv * 64 * VEC + lane * VEC + e] = d[e];
+        for (int e = 0; e < VEC; ++e) s_red[wv * 256 + lane * VEC + e] = d[e];
       }
       __syncthreads();
       for (int j = tid; j < Bt; j += kThreads) {
         double v = s_red[j];
 #pragma unroll
-        for (int q = 1; q < kWaves; ++q) v += s_red[q * 64 * VEC + j];
+        for (int q = 1; q < kWaves; ++q) v += s_red[q * 256 + j];
         if (v != 0.0) {
-          double* dst = a.acc + ((size_t)(blockIdx.x % a.R) * a.G + cg) * B + (size_t)cbt * Bt + j;
+          double* dst = a.acc + ((size_t)(blockIdx.x % a.R) * a.G + cg) * a.B + (size_t)cbt * Bt + j;
           unsafeAtomicAdd(dst, v);
         }
       }
@@ -424,129 +498,159 @@ void k_step(StepArgs a) {
       for (int e = 0; e < VEC; ++e) sc[e] = 0;
     }
     if (!have) break;
-    const bool longrow = (item.w >> 16) != 0;
-    cg = item.z;
-    cbt = item.w & 0xFFFF;
+    const int x = hd.x, y = hd.y, s0 = hd.z, s1 = hd.w;
+    const bool longrow = tl.z != 0;
+    cg = tl.x;
+    cbt = tl.y;
     const int bl = cbt * Bt + lc * VEC;  // first initialisation of this lane
-    const int e0 = a.rp[item.x], e1 = a.rp[item.y];
-    // improvement mask of the previous scored step for this lane's cut-bit byte
-    const bool owner = (lc % gb) == 0;
-    const uint32_t mlane = (pend >= 0 && owner) ? a.mask[cg * a.NBY + (bl >> 3)] : 0u;
+    float eta[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) eta[e] = a.eta[bl + e];
     __syncthreads();  // LDS of the previous item is free
 
     if (!longrow) {
-      const int E = e1 - e0, R = item.y - item.x;
+      const int E = s1 - s0, R = y - x;
       for (int k = tid; k < E; k += kThreads) {
-        s_ci[k] = a.ci[e0 + k];
-        if (WM != kUnitW) s_w[k] = a.w[e0 + k];
+        s_slot[k] = a.slots[s0 + k];
+        if (WM != kUnitW) s_sw[k] = a.sw[s0 + k];
       }
-      for (int i = tid; i <= R; i += kThreads) s_rp[i] = a.rp[item.x + i] - e0;
+      for (int i = tid; i <= R; i += kThreads) s_rp[i] = a.rp[x + i] + x + i - s0;
       __syncthreads();
-      // rows whose first edge lies in this team's share [c0, c1) of the edges
-      const int c0 = (int)(((long long)E * team) / NT);
-      const int c1 = (int)(((long long)E * (team + 1)) / NT);
-      int lo = 0, hi = R;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (s_rp[mid] < c0) lo = mid + 1; else hi = mid;
-      }
-      const int i0 = lo;
-      int i1 = R;
-      if (team != NT - 1) {
-        lo = i0;
-        hi = R;
+      // merge-path split: the team takes exactly the slots [c0, c1); a row cut by a share
+      // boundary is finished by the team holding its own slot, which adds the partial sums
+      // of the following teams in team order after a barrier
+      const int c0 = (int)(((long long)E * sgi) / NS);
+      const int c1 = (int)(((long long)E * (sgi + 1)) / NS);
+      const int part_idx = (sgi * Wc + lc) * (L * VEC);
+      RowState<T, L, VEC> st;
+      st.row = -1;
+      st.zm = 0u;
+      st.dsum = 0.0f;
+      st.head = false;
+      st.lazy = false;
+      if (c0 < c1) {
+        int lo = 0, hi = R;  // first row starting after c0
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
-          if (s_rp[mid] < c1) lo = mid + 1; else hi = mid;
+          if (s_rp[mid] <= c0) lo = mid + 1; else hi = mid;
         }
-        i1 = lo;
+        if (s_rp[lo - 1] < c0) {
+          // the share starts inside row x + lo - 1: its values give the sides for scoring
+          st.row = x + lo - 1;
+          st.head = true;
+          st.lazy = true;
+#pragma unroll
+          for (int i = 0; i < L; ++i) {
+            st.xv[i] = IO::load_raw(X + (size_t)st.row * a.C + (size_t)i * a.B + bl);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) st.acc[i][e] = 0.0f;
+          }
+        }
       }
-      for (int i = i0; i < i1; i += RB) {
-        float xv[RB][L][VEC];
-        float acc[RB][L][VEC];
-        uint32_t zm[RB], mo[RB], mb[RB];
-        int kb2[RB], ke2[RB];
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-          const bool ok = i + r < i1;
-          const int row = item.x + i + r;
-#pragma unroll
-          for (int ii = 0; ii < L; ++ii) {
-            IO::unpack(ok ? IO::load_raw(X + (size_t)row * C + ii * B + bl) : IO::zero(), xv[r][ii]);
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) acc[r][ii][e] = 0.0f;
+      for (int p = c0; p < c1; p += W)
+        gather_window<T, VEC, L, WM, true>(a, X, Y, bw, s_slot, s_sw, s_acc, part_idx, p, c1, bl, lc, gb, eta, st,
+                                           sc, do_score);
+      bool tail = false;
+      int next = 0;
+      if (st.row >= 0) {
+        if (st.head) {
+          put_part<L, VEC>(s_acc, part_idx, st.acc);
+        } else {
+          const int i = st.row - x;
+          next = s_rp[i + 1];
+          if (next <= c1) {
+            finish_row<T, VEC, L>(a, Y, bw, do_score, true, bl, lc, gb, eta, st);
+          } else {
+            tail = true;
+            if (WM == kUnitW) st.dsum = (float)(next - s_rp[i] - 1);
           }
-          mo[r] = mb[r] = 0u;
-          if (ok && mlane && mem == 0) {
-            const size_t bi = (size_t)row * a.NBY + (bl >> 3);
-            mo[r] = bm[bi];
-            mb[r] = a.best_bits[bi];
+        }
+      }
+      __syncthreads();
+      if (tail) {
+        for (int k = sgi + 1; k < NS; ++k) {
+          const int k0 = (int)(((long long)E * k) / NS), k1 = (int)(((long long)E * (k + 1)) / NS);
+          if (k0 >= next) break;
+          if (k0 < k1) {
+            const int idx = (k * Wc + lc) * (L * VEC);
+#pragma unroll
+            for (int i = 0; i < L; ++i)
+#pragma unroll
+              for (int e = 0; e < VEC; ++e) st.acc[i][e] += s_acc[idx + i * VEC + e];
           }
-          kb2[r] = ok ? s_rp[i + r] + mem : 0;
-          ke2[r] = ok ? s_rp[i + r + 1] : 0;
         }
-        gather_rows<T, VEC, L, WM, RB>(X, s_ci, s_w, kb2, ke2, S, C, B, bl, xv, acc, zm, sc, do_score, a.lifted);
-        // combine the team members that split these rows' neighbours
-        for (int s = Wc; s < Wc * S; s <<= 1) {
-#pragma unroll
-          for (int r = 0; r < RB; ++r)
-#pragma unroll
-            for (int ii = 0; ii < L; ++ii)
-#pragma unroll
-              for (int e = 0; e < VEC; ++e) acc[r][ii][e] += __shfl_xor(acc[r][ii][e], s);
-        }
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-          const bool ok = i + r < i1;
-          finish_row<T, VEC, L>(a, Y, bw, do_score, item.x + i + r, ok && mem == 0, bl, lc, gb, xv[r], acc[r],
-                                zm[r], mlane, mo[r], mb[r]);
-        }
+        finish_row<T, VEC, L>(a, Y, bw, do_score, true, bl, lc, gb, eta, st);
       }
     } else {
-      // one long row: every sub-group takes a contiguous share of each staged chunk
-      const int row = item.x;
-      float xv[1][L][VEC];
-      float acc[1][L][VEC];
-      uint32_t zm[1];
+      // one long row: every team takes a contiguous share of each staged chunk of its
+      // neighbour slots; the partial sums are reduced in a fixed order
+      RowState<T, L, VEC> st;
+      st.row = x;
 #pragma unroll
-      for (int ii = 0; ii < L; ++ii) {
-        IO::unpack(IO::load_raw(X + (size_t)row * C + ii * B + bl), xv[0][ii]);
+      for (int i = 0; i < L; ++i) {
+        st.xv[i] = IO::load_raw(X + (size_t)x * a.C + (size_t)i * a.B + bl);
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[0][ii][e] = 0.0f;
+        for (int e = 0; e < VEC; ++e) st.acc[i][e] = 0.0f;
       }
-      uint32_t mo = 0u, mb = 0u;
-      if (mlane && sgi == 0) {
-        const size_t bi = (size_t)row * a.NBY + (bl >> 3);
-        mo = bm[bi];
-        mb = a.best_bits[bi];
-      }
-      for (int sb = e0; sb < e1; sb += kEmax) {
-        const int E = (e1 - sb) < kEmax ? (e1 - sb) : kEmax;
-        __syncthreads();
+      st.dsum = WM == kUnitW ? (float)(s1 - s0 - 1) : a.sw[s0];
+      st.zm = 0u;
+      st.head = false;
+      st.lazy = false;
+      for (int sb = s0 + 1; sb < s1; sb += kEmax) {
+        const int E = (s1 - sb) < kEmax ? (s1 - sb) : kEmax;
+        if (sb != s0 + 1) __syncthreads();
         for (int k = tid; k < E; k += kThreads) {
-          s_ci[k] = a.ci[sb + k];
-          if (WM != kUnitW) s_w[k] = a.w[sb + k];
+          s_slot[k] = a.slots[sb + k];
+          if (WM != kUnitW) s_sw[k] = a.sw[sb + k];
         }
         __syncthreads();
-        const int c0[1] = {(int)(((long long)E * sgi) / NS)};
-        const int c1[1] = {(int)(((long long)E * (sgi + 1)) / NS)};
-        gather_rows<T, VEC, L, WM, 1>(X, s_ci, s_w, c0, c1, 1, C, B, bl, xv, acc, zm, sc, do_score, a.lifted);
+        st.zm = side_mask_raw<T, VEC, L>(st.xv, a.lifted);
+        const int c0 = (int)(((long long)E * sgi) / NS);
+        const int c1 = (int)(((long long)E * (sgi + 1)) / NS);
+        for (int p = c0; p < c1; p += W)
+          gather_window<T, VEC, L, WM, false>(a, X, Y, bw, s_slot, s_sw, s_acc, 0, p, c1, bl, lc, gb, eta, st, sc,
+                                              do_score);
       }
-      if (e1 == e0) zm[0] = side_mask<L, VEC>(xv[0], a.lifted);
+      st.zm = side_mask_raw<T, VEC, L>(st.xv, a.lifted);
+      // teams of one wave first (butterfly), then the waves in order through LDS
+#pragma unroll
+      for (int i = 0; i < L; ++i)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          for (int s = Wc; s < 64; s <<= 1) st.acc[i][e] += __shfl_xor(st.acc[i][e], s);
       __syncthreads();
+      if (lane < Wc) {
 #pragma unroll
-      for (int ii = 0; ii < L; ++ii)
+        for (int i = 0; i < L; ++i)
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) s_acc[(sgi * Wc + lc) * (L * VEC) + ii * VEC + e] = acc[0][ii][e];
-      __syncthreads();
-      if (sgi == 0) {
-        for (int q = 1; q < NS; ++q)
-#pragma unroll
-          for (int ii = 0; ii < L; ++ii)
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) acc[0][ii][e] += s_acc[(q * Wc + lc) * (L * VEC) + ii * VEC + e];
+          for (int e = 0; e < VEC; ++e) s_acc[wv * (L * 256) + (lane * L + i) * VEC + e] = st.acc[i][e];
       }
-      finish_row<T, VEC, L>(a, Y, bw, do_score, row, sgi == 0, bl, lc, gb, xv[0], acc[0], zm[0], mlane, mo, mb);
+      __syncthreads();
+      if (wv == 0) {
+#pragma unroll
+        for (int q = 1; q < kWaves; ++q)
+#pragma unroll
+          for (int i = 0; i < L; ++i)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) st.acc[i][e] += s_acc[q * (L * 256) + (lc * L + i) * VEC + e];
+      }
+      finish_row<T, VEC, L>(a, Y, bw, do_score, sgi == 0, bl, lc, gb, eta, st);
+    }
+
+    // fold the previous scored step's improvements into best_bits for this item's rows and
+    // tile (the bit slot bm is rewritten only by the launch after this one)
+    if (pend >= 0) {
+      const int TB = Bt >= 8 ? (Bt >> 3) : 1;
+      const int b0 = (cbt * Bt) >> 3;
+      const int R = y - x;
+      for (int k = tid; k < R * TB; k += kThreads) {
+        const int r = k / TB, bb = b0 + k % TB;
+        const uint32_t m = a.mask[cg * a.NBY + bb];
+        if (m) {
+          const size_t bi = (size_t)(x + r) * a.NBY + bb;
+          a.best_bits[bi] = (uint8_t)((a.best_bits[bi] & ~m) | (bm[bi] & m));
+        }
+      }
     }
   }
 
@@ -778,25 +882,35 @@ __global__ void k_dense_validate(const uint16_t* W, int n, float* dw, int* flags
   }
 }
 
+template <typename T, int VEC, int LL>
+hipError_t step_dispatch(const StepArgs& a, int wmode, int grid, hipStream_t s) {
+  const dim3 g(grid), b(kThreads);
+  if (wmode == kUnitW)
+    hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW>), g, b, 0, s, a);
+  else if (wmode == kIntW)
+    hipLaunchKernelGGL((k_step<T, VEC, LL, kIntW>), g, b, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW>), g, b, 0, s, a);
+  return hipGetLastError();
+}
+
+// All component counts for float32 and one-element lanes; bfloat16 runs unlifted rows 8
+// values per lane and lifted rows (l > 1) 4 values per lane.
 template <typename T, int VEC>
 hipError_t step_dispatch_l(const StepArgs& a, int wmode, int grid, hipStream_t s) {
-  dim3 g(grid), b(kThreads);
-#define DECO_LAUNCH(LL)                                                              \
-  if (wmode == kUnitW)                                                               \
-    hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW>), g, b, 0, s, a);                 \
-  else if (wmode == kIntW)                                                           \
-    hipLaunchKernelGGL((k_step<T, VEC, LL, kIntW>), g, b, 0, s, a);                  \
-  else                                                                               \
-    hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW>), g, b, 0, s, a);
-  switch (a.L) {
-    case 1: DECO_LAUNCH(1); break;
-    case 2: DECO_LAUNCH(2); break;
-    case 3: DECO_LAUNCH(3); break;
-    case 4: DECO_LAUNCH(4); break;
-    default: return hipErrorInvalidValue;
+  constexpr bool bf_wide = sizeof(T) == 2 && VEC == 8, bf_lift = sizeof(T) == 2 && VEC == 4;
+  if constexpr (!bf_lift) {
+    if (a.L == 1) return step_dispatch<T, VEC, 1>(a, wmode, grid, s);
   }
-#undef DECO_LAUNCH
-  return hipGetLastError();
+  if constexpr (!bf_wide) {
+    switch (a.L) {
+      case 2: return step_dispatch<T, VEC, 2>(a, wmode, grid, s);
+      case 3: return step_dispatch<T, VEC, 3>(a, wmode, grid, s);
+      case 4: return step_dispatch<T, VEC, 4>(a, wmode, grid, s);
+      default: break;
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------------------------ graph validation
@@ -844,6 +958,33 @@ __global__ void k_validate(long long n, const int* rp, const int* ci, const floa
   }
   if (dw) dw[v] = s;
   if (f) atomicOr(flags, f);
+}
+
+// ------------------------------------------------------------------ slot list
+// Row v's own slot at row_ptr[v] + v (index with the top bit set; weighted degree as its
+// weight), one thread per row.
+__global__ void k_slots_self(long long n, const int* rp, const float* dw, int* slots, float* sw) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const long long p = (long long)rp[v] + v;
+  slots[p] = (int)((unsigned)v | 0x80000000u);
+  if (sw) sw[p] = dw[v];
+}
+
+// Edge e of row v (the last row with row_ptr[v] <= e) goes to slot e + v + 1, one thread
+// per edge.
+__global__ void k_slots_edges(long long n, long long nnz, const int* rp, const int* ci, const float* w, int* slots,
+                              float* sw) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  long long lo = 0, hi = n;  // rp[lo] <= e < rp[hi]
+  while (hi - lo > 1) {
+    const long long mid = (lo + hi) >> 1;
+    if (rp[mid] <= e) lo = mid; else hi = mid;
+  }
+  const long long p = e + lo + 1;
+  slots[p] = ci[e];
+  if (sw) sw[p] = w[e];
 }
 
 // ------------------------------------------------------------------ state reset
@@ -1037,7 +1178,7 @@ inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1)
 
 }  // namespace
 
-int native_vec(int dtype) { return dtype == 0 ? 4 : 8; }
+int native_vec(int dtype, int L) { return dtype == 0 ? 4 : (L == 1 ? 8 : 4); }
 
 hipError_t launch_dense_step(const StepArgs& a, hipStream_t s) {
   const int grid = (int)(a.n / kDBM) * (2 * a.C / kDBN);
@@ -1057,6 +1198,7 @@ hipError_t launch_step(const StepArgs& a, int dtype, int vec, int grid, hipStrea
     if (vec == 1) return step_dispatch_l<float, 1>(a, wmode, grid, s);
   } else {
     if (vec == 8) return step_dispatch_l<uint16_t, 8>(a, wmode, grid, s);
+    if (vec == 4) return step_dispatch_l<uint16_t, 4>(a, wmode, grid, s);
     if (vec == 1) return step_dispatch_l<uint16_t, 1>(a, wmode, grid, s);
   }
   return hipErrorInvalidValue;
@@ -1067,6 +1209,15 @@ hipError_t launch_validate(long long n, const int* rp, const int* ci, const floa
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_validate, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, ci, w, goff, G,
                      dw, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_slots(long long n, long long nnz, const int* rp, const int* ci, const float* w,
+                              const float* dw, int* slots, float* sw, hipStream_t s) {
+  hipLaunchKernelGGL(k_slots_self, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, dw, slots, w ? sw : nullptr);
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_slots_edges, dim3(blocks_for(nnz, 256)), dim3(256), 0, s, n, nnz, rp, ci, w, slots,
+                       w ? sw : nullptr);
   return hipGetLastError();
 }
 
