@@ -243,7 +243,8 @@ typedef struct deco_solve_params {
   const int32_t *l0;    /* host [K]: initial lift dimensions, or NULL */
   const double *target_cut; /* host [G] or NULL */
   int32_t use_graph;    /* capture the step loops in hipGraphs */
-  int32_t autotune;     /* run deco_autotune on both handles first */
+  int32_t autotune;     /* run deco_autotune on both handles first (a shape already tuned in
+                           this process reuses its cached winner) */
 } deco_solve_params;
 
 typedef struct deco_solve_report {

@@ -268,27 +268,47 @@ deco_status upload_schedule(deco_handle* h) {
   return DECO_OK;
 }
 
+// Slots one row team gathers per window (the kernel's window for this lane width and l).
+int window_slots(int vec, int L) {
+  const int loads = vec == 1 ? 32 : (L == 1 ? 16 : 8);
+  return std::max(1, loads / L);
+}
+
 Schedule default_schedule(deco_handle* h) {
   Schedule s;
   s.vec = vec_for(h->dtype, h->p.B, h->p.l);
   s.Wc = max_wc(s.vec, h->p.B);
+  // lifted rows: half-width tiles (twice the teams) when the tile stays wide enough
+  if (h->p.l > 1 && s.Wc > 1) {
+    const int bt = (s.Wc / 2) * s.vec;
+    if (bt >= (h->p.B % kMinTile == 0 ? kMinTile : 8) && bt % 8 == 0) s.Wc /= 2;
+  }
   s.dlong = 1 << 30;  // rows are isolated only by the item size
   s.xcd_mode = 0;
-  // one item per workgroup (the dispatcher balances the rest) and about as many items as
-  // workgroups fit on the chip at once (256 CUs x 3)
+  // one item per workgroup (the dispatcher balances the rest); items large enough to give
+  // every team of a workgroup a window, and about as many as workgroups fit on the chip at
+  // once (256 CUs x 3)
   s.blocks_per_xcd = kMaxBlocksPerXcd;
   const long long slots = h->nnz + h->n;
-  const long long per = (slots + 767) / 768;
+  const long long teams = 256 / s.Wc;
+  const long long per = std::max<long long>(teams * window_slots(s.vec, h->p.l), (slots + 767) / 768);
   s.nnz_per_item = (int)std::max<long long>(kMinItemSlots, std::min<long long>(kEmax, per));
   s.rows_per_item = kRmax;
   return s;
 }
+
+bool schedule_cached(const deco_handle* h);
 
 std::mutex g_cache_mu;
 std::map<std::tuple<long long, long long, int, int, int, int, int>, Schedule> g_cache;
 
 std::tuple<long long, long long, int, int, int, int, int> cache_key(const deco_handle* h) {
   return std::make_tuple(h->n, h->nnz, h->G, h->p.B, h->p.l, h->dtype, h->unit ? 1 : 0);
+}
+
+bool schedule_cached(const deco_handle* h) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  return g_cache.count(cache_key(h)) != 0;
 }
 
 deco_status check_graph_args(const deco_graph* g) {
@@ -1078,7 +1098,9 @@ deco_status deco_solver_create(deco_solver** out, const deco_graph* g, const dec
     return st;
   }
   if (sp->autotune) {
-    if ((st = deco_autotune(v->hq, 10)) || (st = deco_autotune(v->hl, 10))) {
+    // shapes tuned earlier in this process already run their cached winner
+    if ((!schedule_cached(v->hq) && (st = deco_autotune(v->hq, 10))) ||
+        (!schedule_cached(v->hl) && (st = deco_autotune(v->hl, 10)))) {
       solver_free(v);
       return st;
     }

@@ -42,14 +42,17 @@ def bf16_ulp(x):
 
 
 def run_teacher_forced(g, B, steps, l=1, lifted=False, form=deco.GRAD_CUT, dtype=deco.F32, eta=0.1, x0=None,
-                       seed=3, schedule_tune=False, eta_per_init=None):
+                       seed=3, schedule_tune=False, eta_per_init=None, schedule=None):
     """Returns per-step records: list of (X_t, X_{t+1}) as float64 arrays (GPU values),
-    plus the handle's trace of cuts and its final best state."""
+    plus the handle's trace of cuts and its final best state. schedule: optional
+    set_schedule arguments."""
     import torch
     G = deco.Graph(g)
     h = deco.Handle(G, B=B, l=l, lifted=lifted, grad_form=form, x_dtype=dtype, eta=eta, seed=seed)
     if schedule_tune:
         h.autotune(3)
+    if schedule is not None:
+        h.set_schedule(*schedule)
     if eta_per_init is not None:
         h.set_eta(eta_per_init)
     C = l * B
