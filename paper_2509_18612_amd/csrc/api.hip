@@ -490,6 +490,7 @@ deco_status deco_init(deco_handle** out, const deco_graph* g, const deco_params*
     return DECO_E_NONFINITE;
   }
   a.intw = (hflags & 16) ? 0 : 1;
+  a.pm1 = (g->w != nullptr && !(hflags & 32)) ? 1 : 0;
   e = launch_build_slots(g->n, g->nnz, g->row_ptr, g->col_idx, g->w, a.dw, const_cast<int*>(a.slots),
                          const_cast<float*>(a.sw), h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);

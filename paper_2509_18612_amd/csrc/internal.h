@@ -60,6 +60,7 @@ struct StepArgs {
   int do_update;    // 0: score-only pass (no new iterate, step counter unchanged)
   int force_score;  // score this launch regardless of score_every
   int intw;         // all weights are integers of magnitude <= 1024 (int32 score partials)
+  int pm1;          // all weights are +-1
   double cut_scale; // cut = cut_scale * accumulated sum (1/2 sparse path, 1/4 dense path)
   const uint16_t* dense_w;  // dense path: bfloat16 n x n weight matrix (row-major)
   long long n;      // rows

@@ -80,6 +80,14 @@ struct VecIO<float, 1> {
   static __device__ __forceinline__ void store(float* p, const float (&o)[1]) { *p = o[0]; }
 };
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two float32 -> a packed pair of bfloat16 (hardware conversion, round to nearest even).
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2{lo, hi}), bf16x2));
+}
+
 template <>
 struct VecIO<uint16_t, 8> {
   using raw = uint4;
@@ -97,10 +105,10 @@ struct VecIO<uint16_t, 8> {
   }
   static __device__ __forceinline__ void store(uint16_t* p, const float (&o)[8]) {
     uint4 v;
-    v.x = f2bf(o[0]) | (f2bf(o[1]) << 16);
-    v.y = f2bf(o[2]) | (f2bf(o[3]) << 16);
-    v.z = f2bf(o[4]) | (f2bf(o[5]) << 16);
-    v.w = f2bf(o[6]) | (f2bf(o[7]) << 16);
+    v.x = pack_bf16(o[0], o[1]);
+    v.y = pack_bf16(o[2], o[3]);
+    v.z = pack_bf16(o[4], o[5]);
+    v.w = pack_bf16(o[6], o[7]);
     *reinterpret_cast<uint4*>(p) = v;
   }
 };
@@ -118,8 +126,8 @@ struct VecIO<uint16_t, 4> {
   }
   static __device__ __forceinline__ void store(uint16_t* p, const float (&o)[4]) {
     uint2 v;
-    v.x = f2bf(o[0]) | (f2bf(o[1]) << 16);
-    v.y = f2bf(o[2]) | (f2bf(o[3]) << 16);
+    v.x = pack_bf16(o[0], o[1]);
+    v.y = pack_bf16(o[2], o[3]);
     *reinterpret_cast<uint2*>(p) = v;
   }
 };
@@ -131,7 +139,7 @@ struct VecIO<uint16_t, 1> {
   static __device__ __forceinline__ raw zero() { return 0u; }
   static __device__ __forceinline__ void unpack(const raw& v, float (&o)[1]) { o[0] = bf2f(v); }
   static __device__ __forceinline__ void store(uint16_t* p, const float (&o)[1]) {
-    *p = (uint16_t)f2bf(o[0]);
+    *p = (uint16_t)(pack_bf16(o[0], 0.0f) & 0xFFFFu);
   }
 };
 
@@ -141,8 +149,12 @@ __device__ __forceinline__ bool side_of(const float (&x)[L], int lifted) {
   float s = 0.0f;
 #pragma unroll
   for (int i = 0; i < L; ++i) s = s + x[i];
-  const bool pos = x[0] > 0.0f, nonneg = s >= 0.0f;  // both formed, then selected (no branch)
-  return lifted ? nonneg : pos;
+  if constexpr (L > 1) {
+    return s >= 0.0f;  // l > 1 only exists lifted
+  } else {
+    const bool pos = x[0] > 0.0f, nonneg = s >= 0.0f;  // both formed, then selected (no branch)
+    return lifted ? nonneg : pos;
+  }
 }
 
 constexpr int kThreads = 256;
@@ -158,9 +170,9 @@ struct Tune {
   static constexpr int W = kLoads / L < 1 ? 1 : kLoads / L;
 };
 
-// Weight modes: unit weights (no weight loads), integer weights of magnitude <= 1024
-// (int32 score partials, exact), real weights (float32 score partials).
-enum : int { kUnitW = 0, kIntW = 1, kRealW = 2 };
+// Weight modes: unit weights (no weight loads), weights of +-1, integer weights of
+// magnitude <= 1024 (int32 score partials, exact), real weights (float32 score partials).
+enum : int { kUnitW = 0, kIntW = 1, kRealW = 2, kPm1W = 3 };
 template <int WM>
 struct ScoreType {
   using type = int;
@@ -169,6 +181,25 @@ template <>
 struct ScoreType<kRealW> {
   using type = float;
 };
+
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// Per 16-bit lane of a word of two bfloat16: 1 where the value is <= 0 (+0, -0 and
+// negatives), else 0. The saturating decrement leaves the sign bit set exactly for those
+// raw values (-0 = 0x8000 saturates at itself).
+__device__ __forceinline__ i16x2 nonpos_pair(uint32_t word) {
+  const i16x2 d = __builtin_elementwise_sub_sat(__builtin_bit_cast(i16x2, word), (i16x2){1, 1});
+  return __builtin_bit_cast(i16x2, __builtin_bit_cast(u16x2, d) >> (u16x2){15, 15});
+}
+
+// acc + (the low or high bfloat16 of word) * (the matching half of wpair), in float32.
+// wpair must be a register value: the compiler may encode a constant pair as an inline
+// float constant, which this instruction does not read as a bfloat16 pair.
+__device__ __forceinline__ float dot2_bf16(uint32_t word, uint32_t wpair, float acc) {
+  return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, word), __builtin_bit_cast(bf16x2, wpair), acc,
+                                         false);
+}
 
 // Sides of the VEC initialisations of one lane as a bit mask.
 template <int L, int VEC>
@@ -193,19 +224,98 @@ __device__ __forceinline__ uint32_t side_mask_raw(const typename VecIO<T, VEC>::
   return side_mask<L, VEC>(x, lifted);
 }
 
-// The open row of a team: its own values (storage format), the running neighbour sums,
-// its sides and its weighted degree (Laplacian form). A 'head' row is the continuation of
-// a row whose own slot lies in an earlier team's share: its sums go to that team.
-template <typename T, int L, int VEC>
+// Score counters of unlifted bfloat16 rows with unit or +-1 weights stay in packed 16-bit
+// pairs (one pair per 32-bit word of the row).
+template <typename T, int L, int VEC, int WM>
+struct Packed {
+  static constexpr bool value = sizeof(T) == 2 && L == 1 && VEC >= 2 && (WM == kUnitW || WM == kPm1W);
+};
+
+// The open row of a team: its own values (storage format), the running neighbour sums, its
+// sides, and the score counters of the neighbours taken so far: wsum = sum of w and
+// zs = sum of w z_u per initialisation (z_u the neighbour's side), from which the cut
+// contribution sum_u w 1{z_u != z_v} = z_v ? wsum - zs : zs follows when the row closes. A
+// 'head' row is the continuation of a row whose own slot lies in an earlier team's share:
+// its sums go to that team.
+template <typename T, int L, int VEC, int WM>
 struct RowState {
+  using ST = typename ScoreType<WM>::type;
+  static constexpr bool kPacked = Packed<T, L, VEC, WM>::value;
   typename VecIO<T, VEC>::raw xv[L];
   float acc[L][VEC];
+  i16x2 zp[kPacked ? VEC / 2 : 1];
+  ST zs[kPacked ? 1 : VEC];
+  ST wsum;
   uint32_t zm;
   int row;    // -1 while no row is open
-  float dsum;
+  float dsum; // weighted degree (Laplacian form)
   bool head;  // continuation of an earlier team's row
   bool lazy;  // zm not yet formed from xv
 };
+
+// Score partials of a workgroup's current item per initialisation of the lane: packed 16-bit
+// pairs for the packed rows (at most kEmax slots, each adding at most 1 in magnitude, are
+// taken before a flush), int32 (integer weights) or float32 (real weights) otherwise.
+template <typename T, int L, int VEC, int WM>
+struct ScoreAcc {
+  using ST = typename ScoreType<WM>::type;
+  static constexpr bool kPacked = Packed<T, L, VEC, WM>::value;
+  i16x2 p[kPacked ? VEC / 2 : 1];
+  ST s[kPacked ? 1 : VEC];
+  __device__ __forceinline__ void clear() {
+    if constexpr (kPacked) {
+#pragma unroll
+      for (int k = 0; k < VEC / 2; ++k) p[k] = i16x2{0, 0};
+    } else {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) s[e] = 0;
+    }
+  }
+  __device__ __forceinline__ double get(int e) const {
+    if constexpr (kPacked)
+      return (double)((e & 1) ? p[e >> 1].y : p[e >> 1].x);
+    else
+      return (double)s[e];
+  }
+};
+
+template <typename T, int L, int VEC, int WM>
+__device__ __forceinline__ void reset_counters(RowState<T, L, VEC, WM>& st) {
+  if constexpr (RowState<T, L, VEC, WM>::kPacked) {
+#pragma unroll
+    for (int k = 0; k < VEC / 2; ++k) st.zp[k] = i16x2{0, 0};
+  } else {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) st.zs[e] = 0;
+  }
+  st.wsum = 0;
+}
+
+// Adds the cut contribution of the neighbours counted in st to sc and clears the counters.
+// Packed counters hold sum w 1{x' <= 0} with x' = x_u unlifted (so sum w z_u = wsum minus
+// the counter) and x' = -x_u lifted (the counter itself, see take_slot); then
+// d = z + z_v (wsum - 2 z) per 16-bit lane.
+template <typename T, int L, int VEC, int WM>
+__device__ __forceinline__ void close_score(RowState<T, L, VEC, WM>& st, ScoreAcc<T, L, VEC, WM>& sc, int lifted) {
+  using ST = typename ScoreType<WM>::type;
+  if constexpr (RowState<T, L, VEC, WM>::kPacked) {
+    const i16x2 w2 = {(short)st.wsum, (short)st.wsum};
+    const i16x2 zz = __builtin_bit_cast(i16x2, st.zm | (st.zm << 16));
+#pragma unroll
+    for (int k = 0; k < VEC / 2; ++k) {
+      const i16x2 zv = (zz >> i16x2{(short)(2 * k), (short)(2 * k + 1)}) & i16x2{1, 1};
+      const i16x2 z = lifted ? st.zp[k] : w2 - st.zp[k];
+      sc.p[k] += z + zv * (w2 - z - z);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const ST z = st.zs[e];
+      sc.s[e] += ((st.zm >> e) & 1u) ? st.wsum - z : z;
+    }
+  }
+  reset_counters(st);
+}
 
 // A team's partial sums of its head row, for the team that owns the row.
 template <int L, int VEC>
@@ -219,10 +329,13 @@ __device__ __forceinline__ void put_part(float* s_part, int idx, const float (&a
 // Projected update of one row and its cut bits for the lanes' initialisations. Every lane
 // of the team calls it (the bit byte is assembled with shuffles inside the team); 'lead'
 // lanes store.
-template <typename T, int VEC, int L>
+// eta points at the tile's step sizes in LDS: eta[e] = eta_b, eta[256 + e] = eta_b * cW. In
+// the cut form x + eta (cW acc) is formed as one fused multiply-add with the exact product
+// (eta cW) acc (cW is -1/2 or -1).
+template <typename T, int VEC, int L, int WM>
 __device__ __forceinline__ void finish_row(const StepArgs& a, T* __restrict__ Y, uint8_t* __restrict__ bw,
                                            bool do_score, bool lead, int bl, int lc, int gb,
-                                           const float (&eta)[VEC], const RowState<T, L, VEC>& st) {
+                                           const float* __restrict__ eta, const RowState<T, L, VEC, WM>& st) {
   if (a.do_update && lead) {
 #pragma unroll
     for (int i = 0; i < L; ++i) {
@@ -230,10 +343,12 @@ __device__ __forceinline__ void finish_row(const StepArgs& a, T* __restrict__ Y,
       VecIO<T, VEC>::unpack(st.xv[i], xv);
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
-        float g = a.cW * st.acc[i][e];
-        if (a.cD != 0.0f) g = fmaf(a.cD * st.dsum, xv[e], g);
-        const float v = fmaf(eta[e], g, xv[e]);
-        y[e] = fminf(1.0f, fmaxf(-1.0f, v));
+        float v;
+        if (a.cD != 0.0f)
+          v = fmaf(eta[e], fmaf(a.cD * st.dsum, xv[e], a.cW * st.acc[i][e]), xv[e]);
+        else
+          v = fmaf(eta[256 + e], st.acc[i][e], xv[e]);
+        y[e] = __builtin_amdgcn_fmed3f(v, -1.0f, 1.0f);
       }
       VecIO<T, VEC>::store(Y + (size_t)st.row * a.C + (size_t)i * a.B + bl, y);
     }
@@ -244,18 +359,141 @@ __device__ __forceinline__ void finish_row(const StepArgs& a, T* __restrict__ Y,
   if (do_score && lead && (lc % gb) == 0) bw[(size_t)st.row * a.NBY + (bl >> 3)] = (uint8_t)byte;
 }
 
+// Closes the open row of a team inside its share: score contribution, then the row's
+// partial sums to their owner (head row) or the update of the complete row.
+template <typename T, int VEC, int L, int WM>
+__device__ __forceinline__ void close_row(const StepArgs& a, T* __restrict__ Y, uint8_t* __restrict__ bw,
+                                          float* s_part, int part_idx, bool do_score, int bl, int lc, int gb,
+                                          const float* __restrict__ eta, RowState<T, L, VEC, WM>& st,
+                                          ScoreAcc<T, L, VEC, WM>& sc) {
+  if (WM == kUnitW && !st.head) st.dsum = (float)st.wsum;  // degree: the row's slots were all taken here
+  if (do_score) close_score(st, sc, a.lifted);
+  if (st.head)
+    put_part<L, VEC>(s_part, part_idx, st.acc);
+  else
+    finish_row<T, VEC, L, WM>(a, Y, bw, do_score, true, bl, lc, gb, eta, st);
+}
+
+// Opens the row whose own slot was just read.
+template <typename T, int L, int VEC, int WM>
+__device__ __forceinline__ void open_row(RowState<T, L, VEC, WM>& st, int row,
+                                         const typename VecIO<T, VEC>::raw (&xr)[L], float wself, int lifted) {
+  st.row = row;
+  st.head = false;
+  st.dsum = WM == kUnitW ? 0.0f : wself;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    st.xv[i] = xr[i];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) st.acc[i][e] = 0.0f;
+  }
+  if constexpr (RowState<T, L, VEC, WM>::kPacked) {
+    // z = 1{x > 0} = 1 - 1{x <= 0} unlifted; z = 1{x >= 0} = 1{-x <= 0} lifted
+    const uint32_t flip = lifted ? 0x80008000u : 0u, inv = lifted ? 0u : 0x00010001u;
+    uint32_t wd[VEC / 2];
+    if constexpr (VEC == 8) {
+      wd[0] = xr[0].x;
+      wd[1] = xr[0].y;
+      wd[2] = xr[0].z;
+      wd[3] = xr[0].w;
+    } else {
+      wd[0] = xr[0].x;
+      wd[1] = xr[0].y;
+    }
+    uint32_t zm = 0;
+#pragma unroll
+    for (int k = 0; k < VEC / 2; ++k) {
+      const uint32_t z = __builtin_bit_cast(uint32_t, nonpos_pair(wd[k] ^ flip)) ^ inv;
+      zm |= ((z & 1u) | ((z >> 15) & 2u)) << (2 * k);
+    }
+    st.zm = zm;
+  } else {
+    st.zm = side_mask_raw<T, VEC, L>(xr, lifted);
+  }
+  reset_counters(st);
+}
+
+// Takes one neighbour slot: w * x_u into the sums and, when scoring, w and w z_u into the
+// counters. Unlifted bfloat16 rows with unit or +-1 weights stay packed: the sums use the
+// bfloat16 dot instruction against (w, 0) / (0, w), and the counters add w 1{x_u <= 0}
+// per 16-bit lane (z_u = 1{x_u > 0} is its complement). Lifted rows with l = 1 have
+// z_u = 1{x_u >= 0} = 1{-x_u <= 0}: the same count taken on -x_u (sign bits flipped).
+template <typename T, int VEC, int L, int WM>
+__device__ __forceinline__ void take_slot(RowState<T, L, VEC, WM>& st, const typename VecIO<T, VEC>::raw (&xr)[L],
+                                          float wq, bool do_score, int lifted) {
+  using ST = typename ScoreType<WM>::type;
+  if constexpr (RowState<T, L, VEC, WM>::kPacked) {
+    uint32_t wd[VEC / 2];
+    if constexpr (VEC == 8) {
+      wd[0] = xr[0].x;
+      wd[1] = xr[0].y;
+      wd[2] = xr[0].z;
+      wd[3] = xr[0].w;
+    } else {
+      wd[0] = xr[0].x;
+      wd[1] = xr[0].y;
+    }
+    uint32_t wlo = WM == kUnitW ? 0x00003F80u : (__float_as_uint(wq) >> 16);
+    if (WM == kUnitW) asm volatile("" : "+v"(wlo));  // keep the pair in a register
+    uint32_t whi = wlo << 16;
+    if (WM == kUnitW) asm volatile("" : "+v"(whi));
+#pragma unroll
+    for (int k = 0; k < VEC / 2; ++k) {
+      st.acc[0][2 * k] = dot2_bf16(wd[k], wlo, st.acc[0][2 * k]);
+      st.acc[0][2 * k + 1] = dot2_bf16(wd[k], whi, st.acc[0][2 * k + 1]);
+    }
+    if (do_score) {
+      const uint32_t flip = lifted ? 0x80008000u : 0u;
+      const short ws = (short)(WM == kUnitW ? 1 : (wq < 0.0f ? -1 : 1));
+#pragma unroll
+      for (int k = 0; k < VEC / 2; ++k) {
+        const i16x2 z = nonpos_pair(wd[k] ^ flip);
+        if (WM == kUnitW)
+          st.zp[k] += z;
+        else
+          st.zp[k] += z * i16x2{ws, ws};
+      }
+    }
+  } else {
+    float xu[L][VEC];
+#pragma unroll
+    for (int i = 0; i < L; ++i) VecIO<T, VEC>::unpack(xr[i], xu[i]);
+#pragma unroll
+    for (int i = 0; i < L; ++i)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        if (WM == kUnitW)
+          st.acc[i][e] += xu[i][e];
+        else
+          st.acc[i][e] = fmaf(wq, xu[i][e], st.acc[i][e]);
+      }
+    if (do_score) {
+      const uint32_t sm = side_mask<L, VEC>(xu, lifted);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const uint32_t bit = (sm >> e) & 1u;
+        if (WM == kUnitW)
+          st.zs[e] += (int)bit;
+        else if (WM == kRealW)
+          st.zs[e] += bit ? wq : 0.0f;
+        else
+          st.zs[e] += (int)bit * (int)wq;
+      }
+    }
+  }
+  st.wsum += WM == kUnitW ? (ST)1 : (ST)wq;
+}
+
 // One window of the team's slot range: slots [p, min(p + W, pe)) of the staged list. All
 // gathers of the window are issued before any is used; then the slots are folded in list
-// order. A self slot (SELF lists only) finishes the open row and opens its own; a
-// neighbour slot adds w * x_u to the open row's sums and, when scoring, w to the
-// initialisations whose sides differ. Sides follow the rounding rule: x_0 > 0 unlifted,
-// the float32 sum of the components in component order >= 0 lifted.
+// order: a self slot (SELF lists only) closes the open row and opens its own, a neighbour
+// slot is taken into the open row.
 template <typename T, int VEC, int L, int WM, bool SELF>
 __device__ __forceinline__ void gather_window(const StepArgs& a, const T* __restrict__ X, T* __restrict__ Y,
                                               uint8_t* __restrict__ bw, const int* s_slot, const float* s_sw,
                                               float* s_part, int part_idx, int p, int pe, int bl, int lc, int gb,
-                                              const float (&eta)[VEC], RowState<T, L, VEC>& st,
-                                              typename ScoreType<WM>::type (&sc)[VEC], bool do_score) {
+                                              const float* __restrict__ eta, RowState<T, L, VEC, WM>& st,
+                                              ScoreAcc<T, L, VEC, WM>& sc, bool do_score) {
   using IO = VecIO<T, VEC>;
   constexpr int W = Tune<L, VEC>::W;
   const size_t C = (size_t)a.C, B = (size_t)a.B;
@@ -277,62 +515,12 @@ __device__ __forceinline__ void gather_window(const StepArgs& a, const T* __rest
 #pragma unroll
   for (int q = 0; q < W; ++q) {
     if (p + q < pe) {
-      const bool self = SELF && sl[q] < 0;
       const float wq = WM == kUnitW ? 1.0f : s_sw[p + q];
-      if (self && st.row >= 0) {
-        if (st.head)
-          put_part<L, VEC>(s_part, part_idx, st.acc);
-        else
-          finish_row<T, VEC, L>(a, Y, bw, do_score, true, bl, lc, gb, eta, st);
-      }
-      float ssum[VEC], x0[VEC];
-#pragma unroll
-      for (int i = 0; i < L; ++i) {
-        float xu[VEC];
-        IO::unpack(xr[q][i], xu);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-          if (i == 0) {
-            x0[e] = xu[e];
-            ssum[e] = 0.0f + xu[e];
-          } else {
-            ssum[e] = ssum[e] + xu[e];
-          }
-          if (self)
-            st.acc[i][e] = 0.0f;
-          else if (WM == kUnitW)
-            st.acc[i][e] += xu[e];
-          else
-            st.acc[i][e] = fmaf(wq, xu[e], st.acc[i][e]);
-        }
-        if (self) st.xv[i] = xr[q][i];
-      }
-      uint32_t sm = 0;
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        const bool pos = x0[e] > 0.0f, nonneg = ssum[e] >= 0.0f;
-        sm |= ((a.lifted ? nonneg : pos) ? 1u : 0u) << e;
-      }
-      if (self) {
-        st.row = sl[q] & 0x7FFFFFFF;
-        st.zm = sm;
-        st.dsum = WM == kUnitW ? 0.0f : wq;
-        st.head = false;
+      if (SELF && sl[q] < 0) {
+        if (st.row >= 0) close_row<T, VEC, L, WM>(a, Y, bw, s_part, part_idx, do_score, bl, lc, gb, eta, st, sc);
+        open_row<T, L, VEC, WM>(st, sl[q] & 0x7FFFFFFF, xr[q], wq, a.lifted);
       } else {
-        if (SELF && WM == kUnitW) st.dsum += 1.0f;
-        if (do_score) {
-          const uint32_t d = sm ^ st.zm;
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) {
-            const uint32_t bit = (d >> e) & 1u;  // branch-free accumulation
-            if (WM == kUnitW)
-              sc[e] += (int)bit;
-            else if (WM == kIntW)
-              sc[e] += (int)bit * (int)wq;
-            else
-              sc[e] += bit ? wq : 0.0f;
-          }
-        }
+        take_slot<T, VEC, L, WM>(st, xr[q], wq, do_score, a.lifted);
       }
     }
   }
@@ -425,6 +613,7 @@ void k_step(StepArgs a) {
   __shared__ int s_slot[kEmax];
   __shared__ float s_sw[WM == kUnitW ? 1 : kEmax];
   __shared__ int s_rp[kRmax + 1];
+  __shared__ __align__(16) float s_eta[512];
   // score flush (double per initialisation of the tile per wave) / partial sums of the
   // teams (float per lane, component and initialisation) / long-row reduction (float per
   // component and initialisation of the tile per wave)
@@ -459,10 +648,36 @@ void k_step(StepArgs a) {
   const int nbx = ((int)gridDim.x - xcd + 7) >> 3;
   const int it0 = a.seg[xcd], it1 = a.seg[xcd + 1];
 
-  ST sc[VEC];
-#pragma unroll
-  for (int e = 0; e < VEC; ++e) sc[e] = 0;
+  ScoreAcc<T, L, VEC, WM> sc;
+  sc.clear();
   int cg = -1, cbt = -1;
+
+  // score partials of the current (graph, tile): wave, then workgroup, then one atomic per
+  // initialisation into replica blockIdx % R. Every thread of the workgroup calls it.
+  auto flush = [&]() {
+    double d[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      d[e] = sc.get(e);
+      for (int s = Wc; s < 64; s <<= 1) d[e] += __shfl_xor(d[e], s);
+    }
+    __syncthreads();
+    if (lane < Wc) {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) s_red[wv * 256 + lane * VEC + e] = d[e];
+    }
+    __syncthreads();
+    for (int j = tid; j < Bt; j += kThreads) {
+      double v = s_red[j];
+#pragma unroll
+      for (int q = 1; q < kWaves; ++q) v += s_red[q * 256 + j];
+      if (v != 0.0) {
+        double* dst = a.acc + ((size_t)(blockIdx.x % a.R) * a.G + cg) * a.B + (size_t)cbt * Bt + j;
+        unsafeAtomicAdd(dst, v);
+      }
+    }
+    sc.clear();
+  };
 
   for (int it = it0 + kb;; it += nbx) {
     const bool have = it < it1;
@@ -471,42 +686,21 @@ void k_step(StepArgs a) {
       hd = a.items[2 * it];
       tl = a.items[2 * it + 1];
     }
-    if (do_score && cg >= 0) {
-      // flush the previous item's score partials: wave, then workgroup, then one atomic
-      double d[VEC];
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        d[e] = (double)sc[e];
-        for (int s = Wc; s < 64; s <<= 1) d[e] += __shfl_xor(d[e], s);
-      }
-      __syncthreads();
-      if (lane < Wc) {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) s_red[wv * 256 + lane * VEC + e] = d[e];
-      }
-      __syncthreads();
-      for (int j = tid; j < Bt; j += kThreads) {
-        double v = s_red[j];
-#pragma unroll
-        for (int q = 1; q < kWaves; ++q) v += s_red[q * 256 + j];
-        if (v != 0.0) {
-          double* dst = a.acc + ((size_t)(blockIdx.x % a.R) * a.G + cg) * a.B + (size_t)cbt * Bt + j;
-          unsafeAtomicAdd(dst, v);
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) sc[e] = 0;
-    }
+    if (do_score && cg >= 0) flush();
     if (!have) break;
     const int x = hd.x, y = hd.y, s0 = hd.z, s1 = hd.w;
     const bool longrow = tl.z != 0;
     cg = tl.x;
     cbt = tl.y;
     const int bl = cbt * Bt + lc * VEC;  // first initialisation of this lane
-    float eta[VEC];
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) eta[e] = a.eta[bl + e];
     __syncthreads();  // LDS of the previous item is free
+    // step sizes of the tile (read by the row updates after the staging barrier)
+    for (int j = tid; j < Bt; j += kThreads) {
+      const float et = a.eta[cbt * Bt + j];
+      s_eta[j] = et;
+      s_eta[256 + j] = et * a.cW;
+    }
+    const float* eta = s_eta + lc * VEC;
 
     if (!longrow) {
       const int E = s1 - s0, R = y - x;
@@ -522,12 +716,13 @@ void k_step(StepArgs a) {
       const int c0 = (int)(((long long)E * sgi) / NS);
       const int c1 = (int)(((long long)E * (sgi + 1)) / NS);
       const int part_idx = (sgi * Wc + lc) * (L * VEC);
-      RowState<T, L, VEC> st;
+      RowState<T, L, VEC, WM> st;
       st.row = -1;
       st.zm = 0u;
       st.dsum = 0.0f;
       st.head = false;
       st.lazy = false;
+      reset_counters(st);
       if (c0 < c1) {
         int lo = 0, hi = R;  // first row starting after c0
         while (lo < hi) {
@@ -554,14 +749,16 @@ void k_step(StepArgs a) {
       int next = 0;
       if (st.row >= 0) {
         if (st.head) {
-          put_part<L, VEC>(s_acc, part_idx, st.acc);
+          close_row<T, VEC, L, WM>(a, Y, bw, s_acc, part_idx, do_score, bl, lc, gb, eta, st, sc);
         } else {
           const int i = st.row - x;
           next = s_rp[i + 1];
           if (next <= c1) {
-            finish_row<T, VEC, L>(a, Y, bw, do_score, true, bl, lc, gb, eta, st);
+            close_row<T, VEC, L, WM>(a, Y, bw, s_acc, part_idx, do_score, bl, lc, gb, eta, st, sc);
           } else {
+            // the row continues in later shares: score this share now, update after them
             tail = true;
+            if (do_score) close_score(st, sc, a.lifted);
             if (WM == kUnitW) st.dsum = (float)(next - s_rp[i] - 1);
           }
         }
@@ -579,12 +776,12 @@ void k_step(StepArgs a) {
               for (int e = 0; e < VEC; ++e) st.acc[i][e] += s_acc[idx + i * VEC + e];
           }
         }
-        finish_row<T, VEC, L>(a, Y, bw, do_score, true, bl, lc, gb, eta, st);
+        finish_row<T, VEC, L, WM>(a, Y, bw, do_score, true, bl, lc, gb, eta, st);
       }
     } else {
       // one long row: every team takes a contiguous share of each staged chunk of its
       // neighbour slots; the partial sums are reduced in a fixed order
-      RowState<T, L, VEC> st;
+      RowState<T, L, VEC, WM> st;
       st.row = x;
 #pragma unroll
       for (int i = 0; i < L; ++i) {
@@ -596,6 +793,7 @@ void k_step(StepArgs a) {
       st.zm = 0u;
       st.head = false;
       st.lazy = false;
+      reset_counters(st);
       for (int sb = s0 + 1; sb < s1; sb += kEmax) {
         const int E = (s1 - sb) < kEmax ? (s1 - sb) : kEmax;
         if (sb != s0 + 1) __syncthreads();
@@ -610,6 +808,11 @@ void k_step(StepArgs a) {
         for (int p = c0; p < c1; p += W)
           gather_window<T, VEC, L, WM, false>(a, X, Y, bw, s_slot, s_sw, s_acc, 0, p, c1, bl, lc, gb, eta, st, sc,
                                               do_score);
+        // score of this chunk's share; the 16-bit partials hold at most one chunk
+        if (do_score) {
+          close_score(st, sc, a.lifted);
+          flush();
+        }
       }
       st.zm = side_mask_raw<T, VEC, L>(st.xv, a.lifted);
       // teams of one wave first (butterfly), then the waves in order through LDS
@@ -634,21 +837,49 @@ void k_step(StepArgs a) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) st.acc[i][e] += s_acc[q * (L * 256) + (lc * L + i) * VEC + e];
       }
-      finish_row<T, VEC, L>(a, Y, bw, do_score, sgi == 0, bl, lc, gb, eta, st);
+      finish_row<T, VEC, L, WM>(a, Y, bw, do_score, sgi == 0, bl, lc, gb, eta, st);
     }
 
     // fold the previous scored step's improvements into best_bits for this item's rows and
-    // tile (the bit slot bm is rewritten only by the launch after this one)
+    // tile (the bit slot bm is rewritten only by the launch after this one): 4-byte words
+    // when rows and tiles are word aligned, all loads of a batch in flight together
     if (pend >= 0) {
       const int TB = Bt >= 8 ? (Bt >> 3) : 1;
       const int b0 = (cbt * Bt) >> 3;
       const int R = y - x;
-      for (int k = tid; k < R * TB; k += kThreads) {
-        const int r = k / TB, bb = b0 + k % TB;
-        const uint32_t m = a.mask[cg * a.NBY + bb];
-        if (m) {
-          const size_t bi = (size_t)(x + r) * a.NBY + bb;
-          a.best_bits[bi] = (uint8_t)((a.best_bits[bi] & ~m) | (bm[bi] & m));
+      if ((a.NBY & 3) == 0 && (TB & 3) == 0) {
+        constexpr int kU = 8;
+        const int TW = TB >> 2, NW = a.NBY >> 2;
+        const uint32_t* mask32 = reinterpret_cast<const uint32_t*>(a.mask) + (size_t)cg * NW + (b0 >> 2);
+        const uint32_t* bm32 = reinterpret_cast<const uint32_t*>(bm);
+        uint32_t* best32 = reinterpret_cast<uint32_t*>(a.best_bits);
+        for (int base = 0; base < R * TW; base += kThreads * kU) {
+          uint32_t m[kU], mo[kU], mb[kU];
+          size_t wi[kU];
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            const int k = base + u * kThreads + tid;
+            const int r = k / TW, c = k - r * TW;
+            m[u] = k < R * TW ? mask32[c] : 0u;
+            wi[u] = (size_t)(x + r) * NW + (b0 >> 2) + c;
+          }
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            mo[u] = m[u] ? bm32[wi[u]] : 0u;
+            mb[u] = m[u] ? best32[wi[u]] : 0u;
+          }
+#pragma unroll
+          for (int u = 0; u < kU; ++u)
+            if (m[u]) best32[wi[u]] = (mb[u] & ~m[u]) | (mo[u] & m[u]);
+        }
+      } else {
+        for (int k = tid; k < R * TB; k += kThreads) {
+          const int r = k / TB, bb = b0 + k % TB;
+          const uint32_t m = a.mask[cg * a.NBY + bb];
+          if (m) {
+            const size_t bi = (size_t)(x + r) * a.NBY + bb;
+            a.best_bits[bi] = (uint8_t)((a.best_bits[bi] & ~m) | (bm[bi] & m));
+          }
         }
       }
     }
@@ -887,6 +1118,8 @@ hipError_t step_dispatch(const StepArgs& a, int wmode, int grid, hipStream_t s) 
   const dim3 g(grid), b(kThreads);
   if (wmode == kUnitW)
     hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW>), g, b, 0, s, a);
+  else if (wmode == kPm1W)
+    hipLaunchKernelGGL((k_step<T, VEC, LL, kPm1W>), g, b, 0, s, a);
   else if (wmode == kIntW)
     hipLaunchKernelGGL((k_step<T, VEC, LL, kIntW>), g, b, 0, s, a);
   else
@@ -941,6 +1174,7 @@ __global__ void k_validate(long long n, const int* rp, const int* ci, const floa
     if (u < g0 || u >= g1) f |= 8;
     if (!isfinite(wk)) f |= 4;
     if (wk != floorf(wk) || fabsf(wk) > 1024.0f) f |= 16;
+    if (fabsf(wk) != 1.0f) f |= 32;
     s += wk;
     // mirror entry: binary search v in row u
     int a0 = rp[u], a1 = rp[u + 1] - 1;
@@ -1192,7 +1426,7 @@ hipError_t launch_dense_validate(const uint16_t* W, int n, float* dw, int* flags
 }
 
 hipError_t launch_step(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s) {
-  const int wmode = a.w == nullptr ? kUnitW : (a.intw ? kIntW : kRealW);
+  const int wmode = a.w == nullptr ? kUnitW : (a.pm1 ? kPm1W : (a.intw ? kIntW : kRealW));
   if (dtype == 0) {
     if (vec == 4) return step_dispatch_l<float, 4>(a, wmode, grid, s);
     if (vec == 1) return step_dispatch_l<float, 1>(a, wmode, grid, s);
