@@ -25,6 +25,29 @@ sys.path.insert(0, ROOT)
 
 METRIC = "edge-updates/s (nnz·B·steps/s); time-to-cut within 0.5% of best, plain vs chosen"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_ba10k_B256_bf16_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2509_18612_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic(which):
+    """Fabric bytes per launch of a step-kernel shape from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the factor a copy of known size gives), or
+    None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        lines = open(TRAFFIC_SUMMARY).read().splitlines()
+    except OSError:
+        return None
+    vals = {}
+    for ln in lines:
+        if ":" in ln and ln.startswith("- "):
+            k, v = ln[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if vals.get("kernels.hip sha256") != sha:
+        return None
+    v = vals.get(f"traffic bytes per launch ({which})")
+    return int(v) if v else None
 
 
 def algorithmic_bytes(n, nnz, C, G, s_x, s_w):
@@ -118,6 +141,28 @@ def other_workloads(deco, synth, torch, which):
     return out
 
 
+def kernel_only(deco, torch, G, B, l_max, dtype, args):
+    """Counter runs: the step kernel of one bench shape with its autotuned schedule, or a
+    plain 256 MiB device-to-device copy (the calibration of the traffic counters)."""
+    if args.kernel_only == "copy":
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(args.kernel_steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"# copied {a.numel() * 4} bytes x {args.kernel_steps}", flush=True)
+        return
+    l = 1 if args.kernel_only == "unlifted" else l_max
+    h = deco.Handle(G, B=B, l=l, lifted=l > 1, x_dtype=dtype, eta=0.01, seed=1)
+    h.autotune(10)
+    h.start(deco.INIT_IDI, scale=1e4, sigma2=0.8, batch=0)
+    h.synchronize()
+    h.step(args.kernel_steps)
+    h.synchronize()
+    print(f"# {args.kernel_only}: {args.kernel_steps} launches, schedule {h.schedule()}", flush=True)
+    h.destroy()
+
+
 def cpu_baseline(oracle, csr, B, budget_s):
     """The oracle's batch (step + rounding + exact cut + running best per step, FP64,
     one thread) on the same graph, for as many steps as fit in about budget_s seconds."""
@@ -150,6 +195,9 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=200)
     ap.add_argument("--others", default="er800,uneven,reg3,dense",
                     help="comma list of other workload shapes to time (empty: none)")
+    ap.add_argument("--kernel-only", choices=["unlifted", "lifted", "copy"], default=None,
+                    help="run only the step kernel of that shape (autotuned as in the bench) for "
+                         "--kernel-steps launches, or a 256 MiB device copy, for counter runs")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -169,6 +217,9 @@ def main():
     G = deco.Graph(csr)
     dtype = deco.BF16 if args.storage == "bf16" else deco.F32
     K, l_max = 8, 4
+    if args.kernel_only:
+        kernel_only(deco, torch, G, B, l_max, dtype, args)
+        return
     print(f"# graph BA({n},{m}) nnz={csr.nnz}; B={B}; storage={args.storage}", file=sys.stderr, flush=True)
 
     # the first solver of a shape autotunes both step kernels; later handles of the same
@@ -201,7 +252,8 @@ def main():
         (ms_q, A_q, "k_step unlifted")
     achieved = dom_A / (dom_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic("lifted" if dom_name.startswith("k_step lifted") else "unlifted"),
                 "kernel": dom_name, "bytes_per_launch": dom_A, "us_per_launch": round(dom_ms * 1e3, 3)}
 
     cpu = None

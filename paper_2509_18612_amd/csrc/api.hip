@@ -731,6 +731,9 @@ deco_status deco_autotune(deco_handle* h, int32_t steps) {
   hipEvent_t e0, e1;
   HIP_TRY(h, hipEventCreate(&e0));
   HIP_TRY(h, hipEventCreate(&e1));
+  // the default comes first; each candidate is timed twice (the faster run counts) and
+  // replaces the best only when more than 3% faster, so near-ties keep the earlier choice
+  cand.insert(cand.begin(), base);
   float best_ms = 1e30f;
   Schedule best = h->sched;
   deco_start_args sa{};
@@ -743,13 +746,17 @@ deco_status deco_autotune(deco_handle* h, int32_t steps) {
     deco_status st = deco_start(h, &sa);
     if (st) return st;
     if ((st = launch_steps(h, 2, 1, 0))) return st;  // warm caches
-    HIP_TRY(h, hipEventRecord(e0, h->stream));
-    if ((st = launch_steps(h, steps, 1, 0))) return st;
-    HIP_TRY(h, hipEventRecord(e1, h->stream));
-    HIP_TRY(h, hipEventSynchronize(e1));
-    float ms = 0.0f;
-    HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best_ms) {
+    float ms = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      HIP_TRY(h, hipEventRecord(e0, h->stream));
+      if ((st = launch_steps(h, steps, 1, 0))) return st;
+      HIP_TRY(h, hipEventRecord(e1, h->stream));
+      HIP_TRY(h, hipEventSynchronize(e1));
+      float r = 0.0f;
+      HIP_TRY(h, hipEventElapsedTime(&r, e0, e1));
+      ms = std::min(ms, r);
+    }
+    if (ms < 0.97f * best_ms) {
       best_ms = ms;
       best = s;
     }

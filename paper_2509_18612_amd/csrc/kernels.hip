@@ -628,9 +628,12 @@ void k_step(StepArgs a) {
   const int lane = tid & 63;
   const int wv = tid >> 6;
   const int Wc = a.Wc;
-  const int NS = kThreads / Wc;  // row teams (sub-groups of Wc lanes) per workgroup
+  // Wc, the team count NS and the replica count R are powers of two: shifts and masks
+  const int wl = __builtin_ctz((unsigned)Wc);
+  const int nsl = 8 - wl;        // log2 of the team count (kThreads = 256)
+  const int NS = kThreads >> wl; // row teams (sub-groups of Wc lanes) per workgroup
   const int lc = tid & (Wc - 1);
-  const int sgi = tid / Wc;
+  const int sgi = tid >> wl;
 
   const long long t = a.ctrl->t;
   const bool do_score = a.force_score || (t % a.ctrl->score_every) == 0;
@@ -672,7 +675,7 @@ void k_step(StepArgs a) {
 #pragma unroll
       for (int q = 1; q < kWaves; ++q) v += s_red[q * 256 + j];
       if (v != 0.0) {
-        double* dst = a.acc + ((size_t)(blockIdx.x % a.R) * a.G + cg) * a.B + (size_t)cbt * Bt + j;
+        double* dst = a.acc + ((size_t)(blockIdx.x & (a.R - 1)) * a.G + cg) * a.B + (size_t)cbt * Bt + j;
         unsafeAtomicAdd(dst, v);
       }
     }
@@ -713,8 +716,8 @@ void k_step(StepArgs a) {
       // merge-path split: the team takes exactly the slots [c0, c1); a row cut by a share
       // boundary is finished by the team holding its own slot, which adds the partial sums
       // of the following teams in team order after a barrier
-      const int c0 = (int)(((long long)E * sgi) / NS);
-      const int c1 = (int)(((long long)E * (sgi + 1)) / NS);
+      const int c0 = (E * sgi) >> nsl;
+      const int c1 = (E * (sgi + 1)) >> nsl;
       const int part_idx = (sgi * Wc + lc) * (L * VEC);
       RowState<T, L, VEC, WM> st;
       st.row = -1;
@@ -766,7 +769,7 @@ void k_step(StepArgs a) {
       __syncthreads();
       if (tail) {
         for (int k = sgi + 1; k < NS; ++k) {
-          const int k0 = (int)(((long long)E * k) / NS), k1 = (int)(((long long)E * (k + 1)) / NS);
+          const int k0 = (E * k) >> nsl, k1 = (E * (k + 1)) >> nsl;
           if (k0 >= next) break;
           if (k0 < k1) {
             const int idx = (k * Wc + lc) * (L * VEC);
@@ -803,8 +806,8 @@ void k_step(StepArgs a) {
         }
         __syncthreads();
         st.zm = side_mask_raw<T, VEC, L>(st.xv, a.lifted);
-        const int c0 = (int)(((long long)E * sgi) / NS);
-        const int c1 = (int)(((long long)E * (sgi + 1)) / NS);
+        const int c0 = (E * sgi) >> nsl;
+        const int c1 = (E * (sgi + 1)) >> nsl;
         for (int p = c0; p < c1; p += W)
           gather_window<T, VEC, L, WM, false>(a, X, Y, bw, s_slot, s_sw, s_acc, 0, p, c1, bl, lc, gb, eta, st, sc,
                                               do_score);
@@ -849,7 +852,7 @@ void k_step(StepArgs a) {
       const int R = y - x;
       if ((a.NBY & 3) == 0 && (TB & 3) == 0) {
         constexpr int kU = 8;
-        const int TW = TB >> 2, NW = a.NBY >> 2;
+        const int TW = TB >> 2, NW = a.NBY >> 2, twl = __builtin_ctz((unsigned)TW);  // TW: a power of two
         const uint32_t* mask32 = reinterpret_cast<const uint32_t*>(a.mask) + (size_t)cg * NW + (b0 >> 2);
         const uint32_t* bm32 = reinterpret_cast<const uint32_t*>(bm);
         uint32_t* best32 = reinterpret_cast<uint32_t*>(a.best_bits);
@@ -859,7 +862,7 @@ void k_step(StepArgs a) {
 #pragma unroll
           for (int u = 0; u < kU; ++u) {
             const int k = base + u * kThreads + tid;
-            const int r = k / TW, c = k - r * TW;
+            const int r = k >> twl, c = k & (TW - 1);
             m[u] = k < R * TW ? mask32[c] : 0u;
             wi[u] = (size_t)(x + r) * NW + (b0 >> 2) + c;
           }
