@@ -49,7 +49,7 @@ struct Schedule {
 
 struct Layout {
   size_t xalt, bits0, bits1, best_bits, mask, acc, cur_cut, best_cut, best_step, ctrl, dw, eta,
-      slots, sw, items, seg, goff, thr, delta, l_active, flags, total;
+      slots, sw, items, seg, goff, thr, delta, l_active, flags, xt0, xt1, total;
   long long items_cap;
   int R;
 };
@@ -69,7 +69,7 @@ int max_wc(int vec, int B) {
   return wc;
 }
 
-Layout layout_for(long long n, long long nnz, int G, const deco_params* p, bool weighted) {
+Layout layout_for(long long n, long long nnz, int G, const deco_params* p, bool weighted, bool dense = false) {
   Layout L{};
   const int C = p->l * p->B;
   const int NBY = nby_of(p->B);
@@ -110,6 +110,9 @@ Layout layout_for(long long n, long long nnz, int G, const deco_params* p, bool 
   L.delta = take(sizeof(int) * (size_t)G);
   L.l_active = take(sizeof(int) * (size_t)p->B);
   L.flags = take(sizeof(int) * 4);
+  // dense path: transposed ping-pong iterates
+  L.xt0 = take(dense ? (size_t)n * C * elem_size(p->x_dtype) : 0);
+  L.xt1 = take(dense ? (size_t)n * C * elem_size(p->x_dtype) : 0);
   L.total = off;
   return L;
 }
@@ -611,6 +614,7 @@ deco_status deco_start(deco_handle* h, const deco_start_args* s) {
     ia.delta = delta;
     HIP_TRY(h, launch_init(ia, h->stream));
   }
+  if (h->dense) HIP_TRY(h, launch_dense_transpose(h->X, h->args.xT[0], h->n, h->C, h->stream));
   HIP_TRY(h, launch_reset(h->args, h->args.acc, (long long)h->R * h->G * h->p.B, h->p.score_every, h->stream));
   h->t_host = 0;
   return DECO_OK;
@@ -819,7 +823,7 @@ deco_status deco_dense_workspace_size(int64_t n, const deco_params* p, size_t* b
   if (!bytes || n < 1) return DECO_E_INVAL;
   if (n % 128 != 0 || p->B % 128 != 0 || p->l != 1 || p->lifted || p->x_dtype != DECO_BF16 || n >= (1LL << 31))
     return DECO_E_UNSUPPORTED;
-  *bytes = layout_for(n, 0, 1, p, false).total;
+  *bytes = layout_for(n, 0, 1, p, false, true).total;
   return DECO_OK;
 }
 
@@ -834,7 +838,7 @@ deco_status deco_dense_init(deco_handle** out, int64_t n, const void* W, const d
   if (((uintptr_t)X % 16) != 0 || ((uintptr_t)W % 16) != 0 || ((uintptr_t)workspace % kAlign) != 0)
     return DECO_E_INVAL;
   if (workspace_bytes < need) return DECO_E_NOMEM;
-  const Layout lay = layout_for(n, 0, 1, p, false);
+  const Layout lay = layout_for(n, 0, 1, p, false, true);
   deco_handle* h = new deco_handle();
   h->dense = true;
   h->p = *p;
@@ -882,6 +886,8 @@ deco_status deco_dense_init(deco_handle** out, int64_t n, const void* W, const d
   a.do_update = 1;
   a.cut_scale = 0.25;
   a.dense_w = reinterpret_cast<const uint16_t*>(W);
+  a.xT[0] = ws + lay.xt0;
+  a.xT[1] = ws + lay.xt1;
   a.n = n;
   int* goff_dev = reinterpret_cast<int*>(ws + lay.goff);
   int* flags = reinterpret_cast<int*>(ws + lay.flags);

@@ -63,6 +63,7 @@ struct StepArgs {
   int pm1;          // all weights are +-1
   double cut_scale; // cut = cut_scale * accumulated sum (1/2 sparse path, 1/4 dense path)
   const uint16_t* dense_w;  // dense path: bfloat16 n x n weight matrix (row-major)
+  void* xT[2];              // dense path: transposed iterates (C x n); xT[t & 1] holds X_t^T
   long long n;      // rows
 };
 
@@ -72,6 +73,8 @@ hipError_t launch_step(const StepArgs& a, int dtype, int vec, int grid, hipStrea
 int native_vec(int dtype, int L);
 // Dense path: n % 128 == 0, C % 128 == 0, bfloat16 X and W, unlifted.
 hipError_t launch_dense_step(const StepArgs& a, hipStream_t s);
+// XT = X^T (bfloat16 n x C -> C x n); n % 64 == 0, C % 64 == 0.
+hipError_t launch_dense_transpose(const void* X, void* XT, long long n, int C, hipStream_t s);
 hipError_t launch_dense_validate(const uint16_t* W, int n, float* dw, int* flags, hipStream_t s);
 
 hipError_t launch_validate(long long n, const int* rp, const int* ci, const float* w,

@@ -893,179 +893,209 @@ void k_step(StepArgs a) {
 
 
 // ------------------------------------------------------------------ dense graphs: MFMA path
-// For a dense graph the gradient W X is a true GEMM. One launch computes
-//   P = W [X | S],  S = sign(X) in {-1, +1}   (bfloat16 operands, float32 accumulation)
-// with v_mfma_f32_32x32x16_bf16: 128 x 128 output tiles (4 waves, 64 x 64 each as 2 x 2
-// MFMA blocks), K steps of 64 staged through LDS (double-buffered; X is transposed into LDS
-// in 4-byte pairs so every MFMA operand is one 16-byte LDS read). Gradient tiles finish the
-// projected update; sign tiles score exactly: with s = 2z - 1,
+// For a dense graph the gradient W X is a true GEMM. One launch computes, for a 128-row by
+// 128-column tile of X,
+//   P = W X  and  Q = W S,  S = sign(X) in {-1, +1}   (bfloat16 operands, float32 accumulation)
+// with v_mfma_f32_32x32x16_bf16 (4 waves, each 64 x 64 of P and of Q as 2 x 2 MFMA blocks).
+// Both operands stream with k contiguous: W's rows, and the rows of a transposed copy XT of X
+// (C x n) that every step writes next to X; K steps of 64 are double-buffered through LDS and
+// the sign fragments are formed in registers from the X fragments. Workgroups of one XCD take
+// consecutive tiles, so the tiles sharing a W row panel meet in that XCD's L2. P finishes the
+// projected update; Q scores exactly: with s = 2z - 1,
 //   sum_u w_vu 1{z_u != z_v} = (d_w(v) - s_v (W s)_v) / 2,
 // and W s is exact in float32 for integer weights (integer sums below 2^24), so each tile
-// adds sum_v (d_w(v) - s_v (W s)_v) per column and the cut is 1/4 of the total. Sign tiles
-// also write the cut bits and fold the previous step's improvements into best_bits.
+// adds sum_v (d_w(v) - s_v (W s)_v) per column and the cut is 1/4 of the total. The epilogue
+// stages the tile in LDS and writes X_t+1 and its transpose with 16-byte stores, the cut bits
+// and the fold of the previous step's improvements into best_bits.
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
 
 constexpr int kDBM = 128, kDBN = 128, kDBK = 64, kDLd = kDBK + 8;  // LDS row: 144 bytes
+constexpr int kDEp = kDBN + 8;                                      // epilogue row: 272 bytes
 
-__device__ __forceinline__ uint32_t bf16_sign(uint32_t h) {
-  return ((h & 0x8000u) == 0u && (h & 0x7FFFu) != 0u) ? 0x3F80u : 0xBF80u;  // x > 0 ? +1 : -1
+// Signs (+1 / -1 as bfloat16, x > 0 ? +1 : -1) of the 8 bfloat16 of an MFMA fragment.
+__device__ __forceinline__ bf16x8_t sign_frag(const bf16x8_t& f) {
+  const uint4 w = __builtin_bit_cast(uint4, f);
+  uint4 s;
+  s.x = 0x3F803F80u | (__builtin_bit_cast(uint32_t, nonpos_pair(w.x)) << 15);
+  s.y = 0x3F803F80u | (__builtin_bit_cast(uint32_t, nonpos_pair(w.y)) << 15);
+  s.z = 0x3F803F80u | (__builtin_bit_cast(uint32_t, nonpos_pair(w.z)) << 15);
+  s.w = 0x3F803F80u | (__builtin_bit_cast(uint32_t, nonpos_pair(w.w)) << 15);
+  return __builtin_bit_cast(bf16x8_t, s);
 }
 
-// Global -> register staging of one K step: A = 128 rows x 64 k of W (64 bytes per
-// thread), B = 64 k x 128 columns of X (two k rows x 16 columns per thread).
-__device__ __forceinline__ void dense_gload(const uint16_t* __restrict__ W, const uint16_t* __restrict__ X, int n,
-                                            int C, int row0, int col0, int k0, int tid, uint4 (&ra)[4],
-                                            uint4 (&rb)[2][2]) {
+// Global -> registers for one K step: 128 rows x 64 k of W and of XT (64 bytes per thread each).
+__device__ __forceinline__ void dense_gload(const uint16_t* __restrict__ W, const uint16_t* __restrict__ XT, int n,
+                                            int row0, int col0, int k0, int tid, uint4 (&ra)[4], uint4 (&rb)[4]) {
   const uint4* pa = reinterpret_cast<const uint4*>(W + (size_t)(row0 + (tid >> 1)) * n + k0 + (tid & 1) * 32);
+  const uint4* pb = reinterpret_cast<const uint4*>(XT + (size_t)(col0 + (tid >> 1)) * n + k0 + (tid & 1) * 32);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) ra[i] = pa[i];
-  const int kk = k0 + 2 * (tid & 31), nc = col0 + (tid >> 5) * 16;
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const uint4* pb = reinterpret_cast<const uint4*>(X + (size_t)(kk + j) * C + nc);
-    rb[j][0] = pb[0];
-    rb[j][1] = pb[1];
+  for (int i = 0; i < 4; ++i) {
+    ra[i] = pa[i];
+    rb[i] = pb[i];
   }
 }
 
-// Register -> LDS: A as is ([m][k]); B transposed to [n][k] in 4-byte (k, k+1) pairs, as
-// signs (+-1) for sign tiles.
-__device__ __forceinline__ void dense_sstore(uint16_t (*As)[kDLd], uint16_t (*Bs)[kDLd], int tid, bool sign_tile,
-                                             const uint4 (&ra)[4], const uint4 (&rb)[2][2]) {
+__device__ __forceinline__ void dense_sstore(uint16_t (*As)[kDLd], uint16_t (*Bs)[kDLd], int tid, const uint4 (&ra)[4],
+                                             const uint4 (&rb)[4]) {
   uint4* da = reinterpret_cast<uint4*>(&As[tid >> 1][(tid & 1) * 32]);
+  uint4* db = reinterpret_cast<uint4*>(&Bs[tid >> 1][(tid & 1) * 32]);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) da[i] = ra[i];
-  const int kp = tid & 31, nl0 = (tid >> 5) * 16;
-  const uint32_t w0[8] = {rb[0][0].x, rb[0][0].y, rb[0][0].z, rb[0][0].w, rb[0][1].x, rb[0][1].y, rb[0][1].z, rb[0][1].w};
-  const uint32_t w1[8] = {rb[1][0].x, rb[1][0].y, rb[1][0].z, rb[1][0].w, rb[1][1].x, rb[1][1].y, rb[1][1].z, rb[1][1].w};
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    uint32_t lo0 = w0[q] & 0xFFFFu, hi0 = w0[q] >> 16;  // row k: columns 2q, 2q+1
-    uint32_t lo1 = w1[q] & 0xFFFFu, hi1 = w1[q] >> 16;  // row k+1
-    if (sign_tile) {
-      lo0 = bf16_sign(lo0);
-      hi0 = bf16_sign(hi0);
-      lo1 = bf16_sign(lo1);
-      hi1 = bf16_sign(hi1);
-    }
-    *reinterpret_cast<uint32_t*>(&Bs[nl0 + 2 * q][2 * kp]) = lo0 | (lo1 << 16);
-    *reinterpret_cast<uint32_t*>(&Bs[nl0 + 2 * q + 1][2 * kp]) = hi0 | (hi1 << 16);
+  for (int i = 0; i < 4; ++i) {
+    da[i] = ra[i];
+    db[i] = rb[i];
   }
 }
 
 __global__ __launch_bounds__(256) void k_dense_step(StepArgs a) {
-  __shared__ __align__(16) uint16_t As[2][kDBM][kDLd];
-  __shared__ __align__(16) uint16_t Bs[2][kDBN][kDLd];
+  __shared__ __align__(16) uint16_t smem[2 * 2 * kDBM * kDLd];  // A and B stages; the epilogue's tiles
+  __shared__ float s_dw[kDBM];
   __shared__ double s_col[2][kDBN];
   __shared__ int s_last;
+  uint16_t (*As)[kDBM][kDLd] = reinterpret_cast<uint16_t (*)[kDBM][kDLd]>(smem);
+  uint16_t (*Bs)[kDBM][kDLd] = reinterpret_cast<uint16_t (*)[kDBM][kDLd]>(smem + 2 * kDBM * kDLd);
+  uint16_t (*Xs)[kDEp] = reinterpret_cast<uint16_t (*)[kDEp]>(smem);              // X_t tile
+  uint16_t (*Ys)[kDEp] = reinterpret_cast<uint16_t (*)[kDEp]>(smem + kDBM * kDEp);  // X_t+1 tile
+
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wm = wv >> 1, wn = wv & 1;
+  const int wm = wv >> 1, wn = wv & 1, hi = lane >> 5, lo = lane & 31;
   const long long t = a.ctrl->t;
   const bool do_score = a.force_score || (t % a.ctrl->score_every) == 0;
   const int pend = a.ctrl->pending_slot;
   const int par = (int)(t & 1);
   const uint16_t* __restrict__ X = reinterpret_cast<const uint16_t*>(a.x[par]);
   uint16_t* __restrict__ Y = reinterpret_cast<uint16_t*>(a.x[par ^ 1]);
+  const uint16_t* __restrict__ XT = reinterpret_cast<const uint16_t*>(a.xT[par]);
+  uint16_t* __restrict__ YT = reinterpret_cast<uint16_t*>(a.xT[par ^ 1]);
   const int n = (int)a.n, C = a.C;
-  const int ctiles = C / kDBN;
-  const int mt = blockIdx.x / (2 * ctiles), nt = blockIdx.x % (2 * ctiles);
-  const bool sign_tile = nt >= ctiles;
-  const int col0 = (nt % ctiles) * kDBN, row0 = mt * kDBM;
-  const bool work = sign_tile ? do_score : (a.do_update != 0);
+  const int ctiles = C / kDBN, tiles = (n / kDBM) * ctiles;
+  const int per = (tiles + 7) >> 3;                       // tiles per XCD
+  const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  const bool have = tile < tiles;
+  const int mt = have ? tile / ctiles : 0, nt = have ? tile % ctiles : 0;
+  const int row0 = mt * kDBM, col0 = nt * kDBN;
+  const bool work = have && (do_score || a.do_update != 0);
 
   if (work) {
-    f32x16_t acc[2][2];
+    f32x16_t P[2][2], Q[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-    uint4 ra[4], rb[2][2];
-    dense_gload(a.dense_w, X, n, C, row0, col0, 0, tid, ra, rb);
-    dense_sstore(As[0], Bs[0], tid, sign_tile, ra, rb);
+        for (int r = 0; r < 16; ++r) P[i][j][r] = Q[i][j][r] = 0.0f;
+    uint4 ra[4], rb[4];
+    dense_gload(a.dense_w, XT, n, row0, col0, 0, tid, ra, rb);
+    dense_sstore(As[0], Bs[0], tid, ra, rb);
     __syncthreads();
-    const int hi = lane >> 5, lo = lane & 31;
     for (int k0 = 0; k0 < n; k0 += kDBK) {
       const int cur = (k0 / kDBK) & 1;
-      const bool more = k0 + kDBK < n;
-      if (more) dense_gload(a.dense_w, X, n, C, row0, col0, k0 + kDBK, tid, ra, rb);
+      // the next stage; the last iteration reloads its own stage into the idle buffer, which
+      // keeps the prefetch registers unconditional
+      dense_gload(a.dense_w, XT, n, row0, col0, k0 + kDBK < n ? k0 + kDBK : k0, tid, ra, rb);
 #pragma unroll
       for (int ks = 0; ks < kDBK / 16; ++ks) {
-        bf16x8_t fa[2], fb[2];
+        bf16x8_t fa[2], fb[2], fs[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
           fa[i] = *reinterpret_cast<const bf16x8_t*>(&As[cur][wm * 64 + i * 32 + lo][ks * 16 + 8 * hi]);
           fb[i] = *reinterpret_cast<const bf16x8_t*>(&Bs[cur][wn * 64 + i * 32 + lo][ks * 16 + 8 * hi]);
+          fs[i] = sign_frag(fb[i]);
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < 2; ++j) {
+            P[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], P[i][j], 0, 0, 0);
+            Q[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fs[j], Q[i][j], 0, 0, 0);
+          }
       }
-      if (more) dense_sstore(As[cur ^ 1], Bs[cur ^ 1], tid, sign_tile, ra, rb);
+      dense_sstore(As[cur ^ 1], Bs[cur ^ 1], tid, ra, rb);
       __syncthreads();
     }
+
+    // X_t tile (rows row0.., columns col0..) into LDS with 16-byte loads; row degrees
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = u * 256 + tid, r = e >> 4, c16 = e & 15;
+      *reinterpret_cast<uint4*>(&Xs[r][c16 * 8]) =
+          *reinterpret_cast<const uint4*>(X + (size_t)(row0 + r) * C + col0 + c16 * 8);
+    }
+    if (tid < kDBM) s_dw[tid] = a.dw[row0 + tid];
+    __syncthreads();
     // element (i, j, r) of this lane: row wm*64 + i*32 + 8*(r/4) + 4*hi + r%4, column wn*64 + j*32 + lo
-    if (!sign_tile) {
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int c = col0 + wn * 64 + j * 32 + lo;
-        const float eta = a.eta[c];
+    for (int j = 0; j < 2; ++j) {
+      const int cl = wn * 64 + j * 32 + lo;
+      const float eta = a.eta[col0 + cl];
+      float colsum = 0.0f;
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int v = row0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
-            const size_t idx = (size_t)v * C + c;
-            const float x = bf2f(X[idx]);
-            float g = a.cW * acc[i][j][r];
-            if (a.cD != 0.0f) g = fmaf(a.cD * a.dw[v], x, g);
-            const float y = fminf(1.0f, fmaxf(-1.0f, fmaf(eta, g, x)));
-            Y[idx] = (uint16_t)f2bf(y);
+        for (int r = 0; r < 16; ++r) {
+          const int vl = wm * 64 + i * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+          const uint32_t hx = Xs[vl][cl];
+          const float x = bf2f(hx);
+          if (a.do_update) {
+            float g = a.cW * P[i][j][r];
+            if (a.cD != 0.0f) g = fmaf(a.cD * s_dw[vl], x, g);
+            const float y = __builtin_amdgcn_fmed3f(fmaf(eta, g, x), -1.0f, 1.0f);
+            Ys[vl][cl] = (uint16_t)(pack_bf16(y, 0.0f) & 0xFFFFu);
           }
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int c = col0 + wn * 64 + j * 32 + lo;
-        float colsum = 0.0f;
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int v = row0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
-            const uint32_t hx = X[(size_t)v * C + c];
-            const bool z = (hx & 0x8000u) == 0u && (hx & 0x7FFFu) != 0u;
-            colsum += a.dw[v] - (z ? acc[i][j][r] : -acc[i][j][r]);
-            // cut bits of X_t and the fold of the previous step's improvements
-            const unsigned long long bal = __ballot(z);
-            if ((lo & 7) == 0) {
-              const size_t bi = (size_t)v * a.NBY + (c >> 3);
-              if (pend >= 0) {
-                const uint32_t m = a.mask[c >> 3];
-                if (m) {
-                  const uint32_t old = a.bits[pend][bi];
-                  const uint32_t bb = a.best_bits[bi];
-                  a.best_bits[bi] = (uint8_t)((bb & ~m) | (old & m));
-                }
-              }
-              a.bits[par][bi] = (uint8_t)((bal >> lane) & 0xFFu);
-            }
-          }
+          const bool z = (hx & 0x8000u) == 0u && (hx & 0x7FFFu) != 0u;
+          colsum += s_dw[vl] - (z ? Q[i][j][r] : -Q[i][j][r]);
+        }
+      if (do_score) {
         double d = (double)colsum;
         d += __shfl_xor(d, 32);
-        if (hi == 0) s_col[wm][wn * 64 + j * 32 + lo] = d;
-      }
-      __syncthreads();
-      if (tid < kDBN) {
-        const double v = s_col[0][tid] + s_col[1][tid];
-        unsafeAtomicAdd(a.acc + (size_t)(blockIdx.x % a.R) * a.B + col0 + tid, v);
+        if (hi == 0) s_col[wm][cl] = d;
       }
     }
-  } else if (sign_tile && pend >= 0) {
-    // a step that does not score still folds the pending improvements of its tile
+    __syncthreads();
+    if (do_score && tid < kDBN) {
+      const double v = s_col[0][tid] + s_col[1][tid];
+      unsafeAtomicAdd(a.acc + (size_t)(blockIdx.x & (a.R - 1)) * a.B + col0 + tid, v);
+    }
+    if (a.do_update) {
+      // X_t+1 rows and XT_t+1 rows (columns of the tile), 16 bytes per store
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = u * 256 + tid, r = e >> 4, c16 = e & 15;
+        *reinterpret_cast<uint4*>(Y + (size_t)(row0 + r) * C + col0 + c16 * 8) =
+            *reinterpret_cast<const uint4*>(&Ys[r][c16 * 8]);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = u * 256 + tid, c = e >> 4, v8 = (e & 15) * 8;
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] = (uint32_t)Ys[v8 + 2 * q][c] | ((uint32_t)Ys[v8 + 2 * q + 1][c] << 16);
+        *reinterpret_cast<uint4*>(YT + (size_t)(col0 + c) * n + row0 + v8) = make_uint4(w[0], w[1], w[2], w[3]);
+      }
+    }
+    if (do_score) {
+      // cut bits of X_t, one byte per 8 columns, and the fold of the previous step's improvements
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = u * 256 + tid, r = e >> 4, b = e & 15;
+        const uint4 w = *reinterpret_cast<const uint4*>(&Xs[r][b * 8]);
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+        uint32_t byte = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t np = __builtin_bit_cast(uint32_t, nonpos_pair(ws[q]));  // 1 where x <= 0
+          byte |= (((np & 1u) ^ 1u) | ((((np >> 16) & 1u) ^ 1u) << 1)) << (2 * q);
+        }
+        const size_t bi = (size_t)(row0 + r) * a.NBY + (col0 >> 3) + b;
+        if (pend >= 0) {
+          const uint32_t m = a.mask[(col0 >> 3) + b];
+          if (m) a.best_bits[bi] = (uint8_t)((a.best_bits[bi] & ~m) | (a.bits[pend][bi] & m));
+        }
+        a.bits[par][bi] = (uint8_t)byte;
+      }
+    }
+  } else if (have && pend >= 0) {
+    // a launch that does not score still folds the pending improvements of its tile
     for (int e = tid; e < kDBM * (kDBN / 8); e += 256) {
       const int v = row0 + e / (kDBN / 8);
       const int by = (col0 >> 3) + e % (kDBN / 8);
@@ -1079,7 +1109,15 @@ __global__ __launch_bounds__(256) void k_dense_step(StepArgs a) {
   complete_step(a, t, do_score, par, s_last);
 }
 
-// Dense-matrix checks: symmetric, zero diagonal, finite; row sums into dw.
+// XT = X^T for the dense path (bfloat16, n x C -> C x n), 64 x 64 tiles through LDS.
+__global__ void k_transpose_bf16(const uint16_t* __restrict__ X, uint16_t* __restrict__ XT, int n, int C) {
+  __shared__ uint16_t T[64][66];
+  const int v0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) T[i >> 6][i & 63] = X[(size_t)(v0 + (i >> 6)) * C + c0 + (i & 63)];
+  __syncthreads();
+  for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) XT[(size_t)(c0 + (i >> 6)) * n + v0 + (i & 63)] = T[i & 63][i >> 6];
+}
+
 __global__ void k_dense_validate(const uint16_t* W, int n, float* dw, int* flags) {
   const int v = blockIdx.x;
   float s = 0.0f;
@@ -1417,8 +1455,15 @@ inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1)
 
 int native_vec(int dtype, int L) { return dtype == 0 ? 4 : (L == 1 ? 8 : 4); }
 
+hipError_t launch_dense_transpose(const void* X, void* XT, long long n, int C, hipStream_t s) {
+  hipLaunchKernelGGL(k_transpose_bf16, dim3((unsigned)(n / 64), (unsigned)(C / 64)), dim3(256), 0, s,
+                     reinterpret_cast<const uint16_t*>(X), reinterpret_cast<uint16_t*>(XT), (int)n, C);
+  return hipGetLastError();
+}
+
 hipError_t launch_dense_step(const StepArgs& a, hipStream_t s) {
-  const int grid = (int)(a.n / kDBM) * (2 * a.C / kDBN);
+  const int tiles = (int)(a.n / kDBM) * (a.C / kDBN);
+  const int grid = 8 * ((tiles + 7) / 8);
   hipLaunchKernelGGL(k_dense_step, dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
