@@ -924,26 +924,59 @@ __device__ __forceinline__ bf16x8_t sign_frag(const bf16x8_t& f) {
   return __builtin_bit_cast(bf16x8_t, s);
 }
 
-// Global -> registers for one K step: 128 rows x 64 k of W and of XT (64 bytes per thread each).
-__device__ __forceinline__ void dense_gload(const uint16_t* __restrict__ W, const uint16_t* __restrict__ XT, int n,
-                                            int row0, int col0, int k0, int tid, uint4 (&ra)[4], uint4 (&rb)[4]) {
+struct DStage {
+  uint4 a0, a1, a2, a3, b0, b1, b2, b3;
+};
+
+// One K step of W rows and XT rows (64 bytes per thread each), as values.
+__device__ __forceinline__ DStage dense_gload2(const uint16_t* __restrict__ W, const uint16_t* __restrict__ XT, int n,
+                                               int row0, int col0, int k0, int tid) {
   const uint4* pa = reinterpret_cast<const uint4*>(W + (size_t)(row0 + (tid >> 1)) * n + k0 + (tid & 1) * 32);
   const uint4* pb = reinterpret_cast<const uint4*>(XT + (size_t)(col0 + (tid >> 1)) * n + k0 + (tid & 1) * 32);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    ra[i] = pa[i];
-    rb[i] = pb[i];
-  }
+  DStage d;
+  d.a0 = pa[0];
+  d.a1 = pa[1];
+  d.a2 = pa[2];
+  d.a3 = pa[3];
+  d.b0 = pb[0];
+  d.b1 = pb[1];
+  d.b2 = pb[2];
+  d.b3 = pb[3];
+  return d;
 }
 
-__device__ __forceinline__ void dense_sstore(uint16_t (*As)[kDLd], uint16_t (*Bs)[kDLd], int tid, const uint4 (&ra)[4],
-                                             const uint4 (&rb)[4]) {
+__device__ __forceinline__ void dense_sstore2(uint16_t (*As)[kDLd], uint16_t (*Bs)[kDLd], int tid, const DStage& d) {
   uint4* da = reinterpret_cast<uint4*>(&As[tid >> 1][(tid & 1) * 32]);
   uint4* db = reinterpret_cast<uint4*>(&Bs[tid >> 1][(tid & 1) * 32]);
+  da[0] = d.a0;
+  da[1] = d.a1;
+  da[2] = d.a2;
+  da[3] = d.a3;
+  db[0] = d.b0;
+  db[1] = d.b1;
+  db[2] = d.b2;
+  db[3] = d.b3;
+}
+
+// The 4 k16 sub-steps of one staged K step: P += A B, Q += A sign(B) for this wave's 64 x 64.
+__device__ __forceinline__ void dense_mma_stage(const uint16_t (*As)[kDLd], const uint16_t (*Bs)[kDLd], int wm, int wn,
+                                                int lo, int hi, f32x16_t (&P)[2][2], f32x16_t (&Q)[2][2]) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    da[i] = ra[i];
-    db[i] = rb[i];
+  for (int ks = 0; ks < kDBK / 16; ++ks) {
+    bf16x8_t fa[2], fb[2], fs[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      fa[i] = *reinterpret_cast<const bf16x8_t*>(&As[wm * 64 + i * 32 + lo][ks * 16 + 8 * hi]);
+      fb[i] = *reinterpret_cast<const bf16x8_t*>(&Bs[wn * 64 + i * 32 + lo][ks * 16 + 8 * hi]);
+      fs[i] = sign_frag(fb[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        P[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], P[i][j], 0, 0, 0);
+        Q[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fs[j], Q[i][j], 0, 0, 0);
+      }
   }
 }
 
@@ -984,33 +1017,23 @@ __global__ __launch_bounds__(256) void k_dense_step(StepArgs a) {
       for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int r = 0; r < 16; ++r) P[i][j][r] = Q[i][j][r] = 0.0f;
-    uint4 ra[4], rb[4];
-    dense_gload(a.dense_w, XT, n, row0, col0, 0, tid, ra, rb);
-    dense_sstore(As[0], Bs[0], tid, ra, rb);
+    // two K stages in flight: stage k+1 waits in registers while stage k+2 is loading; the
+    // loop is unrolled by two so the two register sets alternate without copies
+    DStage r0 = dense_gload2(a.dense_w, XT, n, row0, col0, 0, tid);
+    dense_sstore2(As[0], Bs[0], tid, r0);
+    r0 = dense_gload2(a.dense_w, XT, n, row0, col0, kDBK, tid);  // n >= 128
+    DStage r1;
     __syncthreads();
-    for (int k0 = 0; k0 < n; k0 += kDBK) {
-      const int cur = (k0 / kDBK) & 1;
-      // the next stage; the last iteration reloads its own stage into the idle buffer, which
-      // keeps the prefetch registers unconditional
-      dense_gload(a.dense_w, XT, n, row0, col0, k0 + kDBK < n ? k0 + kDBK : k0, tid, ra, rb);
-#pragma unroll
-      for (int ks = 0; ks < kDBK / 16; ++ks) {
-        bf16x8_t fa[2], fb[2], fs[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          fa[i] = *reinterpret_cast<const bf16x8_t*>(&As[cur][wm * 64 + i * 32 + lo][ks * 16 + 8 * hi]);
-          fb[i] = *reinterpret_cast<const bf16x8_t*>(&Bs[cur][wn * 64 + i * 32 + lo][ks * 16 + 8 * hi]);
-          fs[i] = sign_frag(fb[i]);
-        }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            P[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[j], P[i][j], 0, 0, 0);
-            Q[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fs[j], Q[i][j], 0, 0, 0);
-          }
-      }
-      dense_sstore(As[cur ^ 1], Bs[cur ^ 1], tid, ra, rb);
+    for (int k0 = 0; k0 < n; k0 += 2 * kDBK) {  // n % 128 == 0
+      // stage k0 from buffer 0; load k0 + 128 (clamped: the last iterations reload a stage into
+      // the idle buffer, which keeps the prefetch unconditional); store stage k0 + 64
+      r1 = dense_gload2(a.dense_w, XT, n, row0, col0, k0 + 2 * kDBK < n ? k0 + 2 * kDBK : n - kDBK, tid);
+      dense_mma_stage(As[0], Bs[0], wm, wn, lo, hi, P, Q);
+      dense_sstore2(As[1], Bs[1], tid, r0);
+      __syncthreads();
+      r0 = dense_gload2(a.dense_w, XT, n, row0, col0, k0 + 3 * kDBK < n ? k0 + 3 * kDBK : n - kDBK, tid);
+      dense_mma_stage(As[1], Bs[1], wm, wn, lo, hi, P, Q);
+      dense_sstore2(As[0], Bs[0], tid, r1);
       __syncthreads();
     }
 
