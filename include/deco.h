@@ -182,10 +182,12 @@ deco_status deco_autotune(deco_handle *h, int32_t steps);
  * with more slots than nnz_per_item always do); xcd_mode: 0 = each XCD owns a row range
  * for every tile, 1 = each XCD owns tiles; blocks_per_xcd: workgroups per XCD (1..4096;
  * with more items than workgroups a workgroup walks several); nnz_per_item: target slots
- * (edges plus rows) per work item (128..2048). DECO_E_INVAL when the values do not fit B
- * or the limits. Synchronous (uploads the work list). */
+ * (edges plus rows) per work item (128..2048); lane_elems: 0 = the native lane width
+ * (16-byte loads), or 4 = four bfloat16 per lane for unlifted bfloat16 rows (8-byte loads,
+ * twice the lanes per tile). DECO_E_INVAL when the values do not fit B or the limits.
+ * Synchronous (uploads the work list). */
 typedef struct deco_schedule {
-  int32_t lanes_per_row, long_row, xcd_mode, blocks_per_xcd, nnz_per_item;
+  int32_t lanes_per_row, long_row, xcd_mode, blocks_per_xcd, nnz_per_item, lane_elems;
 } deco_schedule;
 deco_status deco_set_schedule(deco_handle *h, const deco_schedule *s);
 

@@ -715,19 +715,26 @@ deco_status deco_autotune(deco_handle* h, int32_t steps) {
   const Schedule base = default_schedule(h);
   std::vector<Schedule> cand;
   const int vec = base.vec;
-  const int wmax = max_wc(vec, h->p.B);
   const int min_tile = h->p.B % kMinTile == 0 ? kMinTile : std::min(8, h->p.B);
-  for (int Wc = wmax; Wc >= 1 && Wc * vec >= min_tile && Wc * 4 >= wmax; Wc /= 2) {
-    for (int npi : {128, 256, 512, 1024, 2048}) {
-      for (int mode = 0; mode < 2; ++mode) {
-        if (mode == 1 && h->p.B / (Wc * vec) < 2) continue;
-        for (int bpx : {64, 256, kMaxBlocksPerXcd}) {
-          Schedule s = base;
-          s.Wc = Wc;
-          s.xcd_mode = mode;
-          s.blocks_per_xcd = bpx;
-          s.nnz_per_item = npi;
-          cand.push_back(s);
+  // lane widths: the native one, and 4 bfloat16 per lane for unlifted bfloat16 rows (twice the
+  // lanes per tile: one row team per wave at B = 256)
+  std::vector<int> vecs{vec};
+  if (h->dtype == DECO_BF16 && vec == 8) vecs.push_back(4);
+  for (int vw : vecs) {
+    const int wmax_v = max_wc(vw, h->p.B);
+    for (int Wc = wmax_v; Wc >= 1 && Wc * vw >= min_tile && Wc * 4 >= wmax_v; Wc /= 2) {
+      for (int npi : {128, 256, 512, 1024, 2048}) {
+        for (int mode = 0; mode < 2; ++mode) {
+          if (mode == 1 && h->p.B / (Wc * vw) < 2) continue;
+          for (int bpx : {64, 256, kMaxBlocksPerXcd}) {
+            Schedule s = base;
+            s.vec = vw;
+            s.Wc = Wc;
+            s.xcd_mode = mode;
+            s.blocks_per_xcd = bpx;
+            s.nnz_per_item = npi;
+            cand.push_back(s);
+          }
         }
       }
     }
@@ -790,6 +797,11 @@ deco_status deco_set_schedule(deco_handle* h, const deco_schedule* q) {
       (q->xcd_mode != 0 && q->xcd_mode != 1))
     return DECO_E_INVAL;
   Schedule s = default_schedule(h);
+  if (q->lane_elems != 0) {
+    // 4 bfloat16 per lane is the one alternative width (unlifted bfloat16 rows)
+    if (q->lane_elems != 4 || h->dtype != DECO_BF16 || s.vec != 8) return DECO_E_INVAL;
+    s.vec = 4;
+  }
   s.Wc = q->lanes_per_row;
   s.dlong = q->long_row;
   s.xcd_mode = q->xcd_mode;

@@ -696,6 +696,14 @@ void k_step(StepArgs a) {
     cg = tl.x;
     cbt = tl.y;
     const int bl = cbt * Bt + lc * VEC;  // first initialisation of this lane
+    // the improvement mask word this thread folds at the end of the item (word-aligned rows
+    // and tiles: a thread's words all lie in one tile column, since TW divides kThreads)
+    const int fTB = Bt >= 8 ? (Bt >> 3) : 1, fb0 = (cbt * Bt) >> 3;
+    const bool fwords = (a.NBY & 3) == 0 && (fTB & 3) == 0;
+    const int fTW = fTB >> 2;
+    uint32_t fold_m = 0u;
+    if (pend >= 0 && fwords)
+      fold_m = reinterpret_cast<const uint32_t*>(a.mask)[(size_t)cg * (a.NBY >> 2) + (fb0 >> 2) + (tid & (fTW - 1))];
     __syncthreads();  // LDS of the previous item is free
     // step sizes of the tile (read by the row updates after the staging barrier)
     for (int j = tid; j < Bt; j += kThreads) {
@@ -847,33 +855,33 @@ void k_step(StepArgs a) {
     // tile (the bit slot bm is rewritten only by the launch after this one): 4-byte words
     // when rows and tiles are word aligned, all loads of a batch in flight together
     if (pend >= 0) {
-      const int TB = Bt >= 8 ? (Bt >> 3) : 1;
-      const int b0 = (cbt * Bt) >> 3;
+      const int TB = fTB;
+      const int b0 = fb0;
       const int R = y - x;
-      if ((a.NBY & 3) == 0 && (TB & 3) == 0) {
+      if (fwords) {
         constexpr int kU = 8;
-        const int TW = TB >> 2, NW = a.NBY >> 2, twl = __builtin_ctz((unsigned)TW);  // TW: a power of two
-        const uint32_t* mask32 = reinterpret_cast<const uint32_t*>(a.mask) + (size_t)cg * NW + (b0 >> 2);
+        const int TW = fTW, NW = a.NBY >> 2, twl = __builtin_ctz((unsigned)TW);  // TW: a power of two
         const uint32_t* bm32 = reinterpret_cast<const uint32_t*>(bm);
         uint32_t* best32 = reinterpret_cast<uint32_t*>(a.best_bits);
-        for (int base = 0; base < R * TW; base += kThreads * kU) {
-          uint32_t m[kU], mo[kU], mb[kU];
+        for (int base = 0; fold_m != 0u && base < R * TW; base += kThreads * kU) {
+          uint32_t mo[kU], mb[kU];
           size_t wi[kU];
+          bool in[kU];
 #pragma unroll
           for (int u = 0; u < kU; ++u) {
             const int k = base + u * kThreads + tid;
             const int r = k >> twl, c = k & (TW - 1);
-            m[u] = k < R * TW ? mask32[c] : 0u;
+            in[u] = k < R * TW;
             wi[u] = (size_t)(x + r) * NW + (b0 >> 2) + c;
           }
 #pragma unroll
           for (int u = 0; u < kU; ++u) {
-            mo[u] = m[u] ? bm32[wi[u]] : 0u;
-            mb[u] = m[u] ? best32[wi[u]] : 0u;
+            mo[u] = in[u] ? bm32[wi[u]] : 0u;
+            mb[u] = in[u] ? best32[wi[u]] : 0u;
           }
 #pragma unroll
           for (int u = 0; u < kU; ++u)
-            if (m[u]) best32[wi[u]] = (mb[u] & ~m[u]) | (mo[u] & m[u]);
+            if (in[u]) best32[wi[u]] = (mb[u] & ~fold_m) | (mo[u] & fold_m);
         }
       } else {
         for (int k = tid; k < R * TB; k += kThreads) {
@@ -1191,14 +1199,12 @@ hipError_t step_dispatch(const StepArgs& a, int wmode, int grid, hipStream_t s) 
   return hipGetLastError();
 }
 
-// All component counts for float32 and one-element lanes; bfloat16 runs unlifted rows 8
-// values per lane and lifted rows (l > 1) 4 values per lane.
+// All component counts for float32 and one-element lanes; bfloat16 runs unlifted rows 8 or
+// 4 values per lane and lifted rows (l > 1) 4 values per lane.
 template <typename T, int VEC>
 hipError_t step_dispatch_l(const StepArgs& a, int wmode, int grid, hipStream_t s) {
-  constexpr bool bf_wide = sizeof(T) == 2 && VEC == 8, bf_lift = sizeof(T) == 2 && VEC == 4;
-  if constexpr (!bf_lift) {
-    if (a.L == 1) return step_dispatch<T, VEC, 1>(a, wmode, grid, s);
-  }
+  constexpr bool bf_wide = sizeof(T) == 2 && VEC == 8;
+  if (a.L == 1) return step_dispatch<T, VEC, 1>(a, wmode, grid, s);
   if constexpr (!bf_wide) {
     switch (a.L) {
       case 2: return step_dispatch<T, VEC, 2>(a, wmode, grid, s);

@@ -28,8 +28,9 @@ def cw_of(form):
 
 
 def check_run(g, B, steps, l=1, lifted=False, form=deco.GRAD_CUT, dtype=deco.F32, eta=0.1, x0=None, seed=3,
-              schedule_tune=False, eta_per_init=None):
-    r = run_teacher_forced(g, B, steps, l, lifted, form, dtype, eta, x0, seed, schedule_tune, eta_per_init)
+              schedule_tune=False, eta_per_init=None, schedule=None):
+    r = run_teacher_forced(g, B, steps, l, lifted, form, dtype, eta, x0, seed, schedule_tune, eta_per_init,
+                           schedule=schedule)
     xs = r["xs"]
     C = l * B
     eta_cols = (np.full(C, eta) if eta_per_init is None
@@ -121,6 +122,28 @@ def test_bf16_teacher_forced_parity(name):
     g = make()
     worst, _, sched = check_run(g, B, 20, dtype=deco.BF16, **kw)
     print(f"{name} bf16: max |dX| = {worst:.2e}, schedule: {sched}")
+
+
+LANES4 = {
+    "ba_B256": (lambda: synth.barabasi_albert(600, 3, 2), 256, (64, 1 << 30, 0, 4096, 256, 4), {}),
+    "er_pm1_B64": (lambda: synth.with_rademacher_weights(synth.erdos_renyi(400, 0.1, 3), 4), 64,
+                   (16, 1 << 30, 1, 4096, 512, 4), {}),
+    "lifted_l1_B64": (lambda: synth.erdos_renyi(300, 0.05, 14), 64, (16, 1 << 30, 0, 4096, 256, 4),
+                      dict(l=1, lifted=True)),
+    "laplacian_B64": (lambda: synth.erdos_renyi(400, 0.05, 6), 64, (16, 1 << 30, 0, 4096, 256, 4),
+                      dict(form=deco.GRAD_LAPLACIAN, eta=0.01)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(LANES4))
+def test_bf16_four_lane_schedule_parity(name):
+    """Unlifted bfloat16 rows with 4 values per lane (8-byte loads, one row team per wave at
+    B = 256): the same teacher-forced parity, exact cuts and running best."""
+    make, B, sched, kw = LANES4[name]
+    g = make()
+    worst, _, s = check_run(g, B, 15, dtype=deco.BF16, schedule=sched, **kw)
+    assert "vec=4" in s
+    print(f"{name} bf16 4-lane: max |dX| = {worst:.2e}, schedule: {s}")
 
 
 def test_float_weights_cut_within_bound():
