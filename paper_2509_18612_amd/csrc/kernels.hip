@@ -161,10 +161,10 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kSelfBit = (int)0x80000000;  // slot flag: the row's own entry
 
-// Slots gathered together by one row team: 16 loads of 16 bytes in flight per lane for
-// unlifted rows, 8 when the l > 1 components also hold registers (32 for one-element
-// lanes), divided among the l components.
-template <int L, int VEC>
+// Slots gathered together by one row team: 16 loads in flight per lane for unlifted rows,
+// 8 when the l > 1 components also hold registers (32 for one-element lanes), divided
+// among the l components.
+template <typename T, int L, int VEC>
 struct Tune {
   static constexpr int kLoads = VEC == 1 ? 32 : (L == 1 ? 16 : 8);
   static constexpr int W = kLoads / L < 1 ? 1 : kLoads / L;
@@ -454,6 +454,42 @@ __device__ __forceinline__ void take_slot(RowState<T, L, VEC, WM>& st, const typ
           st.zp[k] += z * i16x2{ws, ws};
       }
     }
+  } else if constexpr (sizeof(T) == 2 && VEC >= 2 && (WM == kUnitW || WM == kPm1W)) {
+    // bfloat16 rows of l > 1 components with unit or +-1 weights: the sums with the dot
+    // instruction from the raw words; values are unpacked only to score
+    uint32_t wlo = WM == kUnitW ? 0x00003F80u : (__float_as_uint(wq) >> 16);
+    if (WM == kUnitW) asm volatile("" : "+v"(wlo));  // keep the pair in a register
+    uint32_t whi = wlo << 16;
+    if (WM == kUnitW) asm volatile("" : "+v"(whi));
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      uint32_t wd[VEC / 2];
+      if constexpr (VEC == 8) {
+        wd[0] = xr[i].x;
+        wd[1] = xr[i].y;
+        wd[2] = xr[i].z;
+        wd[3] = xr[i].w;
+      } else {
+        wd[0] = xr[i].x;
+        wd[1] = xr[i].y;
+      }
+#pragma unroll
+      for (int k = 0; k < VEC / 2; ++k) {
+        st.acc[i][2 * k] = dot2_bf16(wd[k], wlo, st.acc[i][2 * k]);
+        st.acc[i][2 * k + 1] = dot2_bf16(wd[k], whi, st.acc[i][2 * k + 1]);
+      }
+    }
+    if (do_score) {
+      float xu[L][VEC];
+#pragma unroll
+      for (int i = 0; i < L; ++i) VecIO<T, VEC>::unpack(xr[i], xu[i]);
+      const uint32_t sm = side_mask<L, VEC>(xu, lifted);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const int bit = (int)((sm >> e) & 1u);
+        st.zs[e] += WM == kUnitW ? bit : (wq < 0.0f ? -bit : bit);
+      }
+    }
   } else {
     float xu[L][VEC];
 #pragma unroll
@@ -495,7 +531,7 @@ __device__ __forceinline__ void gather_window(const StepArgs& a, const T* __rest
                                               const float* __restrict__ eta, RowState<T, L, VEC, WM>& st,
                                               ScoreAcc<T, L, VEC, WM>& sc, bool do_score) {
   using IO = VecIO<T, VEC>;
-  constexpr int W = Tune<L, VEC>::W;
+  constexpr int W = Tune<T, L, VEC>::W;
   const size_t C = (size_t)a.C, B = (size_t)a.B;
   int sl[W];
 #pragma unroll
@@ -607,7 +643,7 @@ __device__ __forceinline__ void complete_step(const StepArgs& a, long long t, bo
 template <typename T, int VEC, int L, int WM>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(DECO_STEP_WAVES_PER_EU)))
 void k_step(StepArgs a) {
-  constexpr int W = Tune<L, VEC>::W;
+  constexpr int W = Tune<T, L, VEC>::W;
   using ST = typename ScoreType<WM>::type;
   using IO = VecIO<T, VEC>;
   __shared__ int s_slot[kEmax];
