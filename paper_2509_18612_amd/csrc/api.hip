@@ -48,7 +48,7 @@ struct Schedule {
 };
 
 struct Layout {
-  size_t xalt, bits0, bits1, best_bits, mask, acc, cur_cut, best_cut, best_step, ctrl, dw, eta,
+  size_t xalt, bits0, bits1, bits2, best_bits, mask, acc, cur_cut, best_cut, best_step, ctrl, dw, eta,
       slots, sw, items, seg, goff, thr, delta, l_active, flags, xt0, xt1, total;
   long long items_cap;
   int R;
@@ -92,9 +92,10 @@ Layout layout_for(long long n, long long nnz, int G, const deco_params* p, bool 
   L.xalt = take((size_t)n * C * elem_size(p->x_dtype));
   L.bits0 = take((size_t)n * NBY);
   L.bits1 = take((size_t)n * NBY);
+  L.bits2 = take((size_t)n * NBY);
   L.best_bits = take((size_t)n * NBY);
-  L.mask = take((size_t)G * NBY);
-  L.acc = take(sizeof(double) * (size_t)L.R * G * p->B);
+  L.mask = take(2 * (size_t)G * NBY);
+  L.acc = take(2 * sizeof(double) * (size_t)L.R * G * p->B);
   L.cur_cut = take(sizeof(double) * (size_t)G * p->B);
   L.best_cut = take(sizeof(double) * (size_t)G * p->B);
   L.best_step = take(sizeof(int) * (size_t)G * p->B);
@@ -453,12 +454,14 @@ deco_status deco_init(deco_handle** out, const deco_graph* g, const deco_params*
   a.eta = reinterpret_cast<float*>(ws + lay.eta);
   a.bits[0] = reinterpret_cast<uint8_t*>(ws + lay.bits0);
   a.bits[1] = reinterpret_cast<uint8_t*>(ws + lay.bits1);
+  a.bits[2] = reinterpret_cast<uint8_t*>(ws + lay.bits2);
   a.best_bits = reinterpret_cast<uint8_t*>(ws + lay.best_bits);
   a.mask = reinterpret_cast<uint8_t*>(ws + lay.mask);
   a.NBY = h->NBY;
   a.acc = reinterpret_cast<double*>(ws + lay.acc);
   a.R = lay.R;
   a.G = h->G;
+  a.nextra = completion_blocks((long long)h->G * p->B);
   a.cur_cut = reinterpret_cast<double*>(ws + lay.cur_cut);
   a.best_cut = reinterpret_cast<double*>(ws + lay.best_cut);
   a.best_step = reinterpret_cast<int*>(ws + lay.best_step);
@@ -520,7 +523,7 @@ deco_status deco_init(deco_handle** out, const deco_graph* g, const deco_params*
     return DECO_E_DEVICE;
   }
   e = launch_fill_eta(const_cast<float*>(a.eta), p->B, p->eta, h->stream);
-  if (e == hipSuccess) e = launch_reset(a, a.acc, (long long)lay.R * h->G * p->B, p->score_every, h->stream);
+  if (e == hipSuccess) e = launch_reset(a, a.acc, 2LL * lay.R * h->G * p->B, p->score_every, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     delete h;
@@ -615,7 +618,7 @@ deco_status deco_start(deco_handle* h, const deco_start_args* s) {
     HIP_TRY(h, launch_init(ia, h->stream));
   }
   if (h->dense) HIP_TRY(h, launch_dense_transpose(h->X, h->args.xT[0], h->n, h->C, h->stream));
-  HIP_TRY(h, launch_reset(h->args, h->args.acc, (long long)h->R * h->G * h->p.B, h->p.score_every, h->stream));
+  HIP_TRY(h, launch_reset(h->args, h->args.acc, 2LL * h->R * h->G * h->p.B, h->p.score_every, h->stream));
   h->t_host = 0;
   return DECO_OK;
 }
@@ -657,6 +660,7 @@ deco_status deco_step(deco_handle* h, int32_t steps, int32_t use_graph) {
     HIP_TRY(h, hipGraphLaunch(it->second, h->stream));
   }
   h->t_host += steps;
+  HIP_TRY(h, launch_drain(h->args, h->n, reinterpret_cast<int*>(h->ws + h->lay.goff), h->stream));
   return DECO_OK;
 }
 
@@ -665,11 +669,12 @@ deco_status deco_round_score(deco_handle* h, double* cut_out, uint8_t* bits_out)
   if (h->poisoned) return DECO_E_STATE;
   deco_status st = launch_steps(h, 1, 0, 1);
   if (st) return st;
+  HIP_TRY(h, launch_drain(h->args, h->n, reinterpret_cast<int*>(h->ws + h->lay.goff), h->stream));
   const size_t gb = (size_t)h->G * h->p.B;
   if (cut_out)
     HIP_TRY(h, hipMemcpyAsync(cut_out, h->args.cur_cut, sizeof(double) * gb, hipMemcpyDeviceToDevice, h->stream));
   if (bits_out)
-    HIP_TRY(h, hipMemcpyAsync(bits_out, h->args.bits[h->t_host & 1], (size_t)h->n * h->NBY,
+    HIP_TRY(h, hipMemcpyAsync(bits_out, h->args.bits[h->t_host % 3], (size_t)h->n * h->NBY,
                               hipMemcpyDeviceToDevice, h->stream));
   return DECO_OK;
 }
@@ -679,7 +684,7 @@ deco_status deco_best(deco_handle* h, double* best_cut, int32_t* best_step, uint
   if (h->poisoned) return DECO_E_STATE;
   const size_t gb = (size_t)h->G * h->p.B;
   const int* goff_dev = reinterpret_cast<int*>(h->ws + h->lay.goff);
-  HIP_TRY(h, launch_merge(h->args, h->n, goff_dev, h->stream));
+  HIP_TRY(h, launch_drain(h->args, h->n, goff_dev, h->stream));
   HIP_TRY(h, hipMemcpyAsync(best_cut, h->args.best_cut, sizeof(double) * gb, hipMemcpyDeviceToHost, h->stream));
   if (best_step)
     HIP_TRY(h, hipMemcpyAsync(best_step, h->args.best_step, sizeof(int) * gb, hipMemcpyDeviceToHost, h->stream));
@@ -883,12 +888,14 @@ deco_status deco_dense_init(deco_handle** out, int64_t n, const void* W, const d
   a.eta = reinterpret_cast<float*>(ws + lay.eta);
   a.bits[0] = reinterpret_cast<uint8_t*>(ws + lay.bits0);
   a.bits[1] = reinterpret_cast<uint8_t*>(ws + lay.bits1);
+  a.bits[2] = reinterpret_cast<uint8_t*>(ws + lay.bits2);
   a.best_bits = reinterpret_cast<uint8_t*>(ws + lay.best_bits);
   a.mask = reinterpret_cast<uint8_t*>(ws + lay.mask);
   a.NBY = h->NBY;
   a.acc = reinterpret_cast<double*>(ws + lay.acc);
   a.R = lay.R;
   a.G = 1;
+  a.nextra = 0;
   a.cur_cut = reinterpret_cast<double*>(ws + lay.cur_cut);
   a.best_cut = reinterpret_cast<double*>(ws + lay.best_cut);
   a.best_step = reinterpret_cast<int*>(ws + lay.best_step);
@@ -923,7 +930,7 @@ deco_status deco_dense_init(deco_handle** out, int64_t n, const void* W, const d
   }
   a.intw = (hflags & 16) ? 0 : 1;
   e = launch_fill_eta(const_cast<float*>(a.eta), p->B, p->eta, h->stream);
-  if (e == hipSuccess) e = launch_reset(a, a.acc, (long long)lay.R * p->B, p->score_every, h->stream);
+  if (e == hipSuccess) e = launch_reset(a, a.acc, 2LL * lay.R * p->B, p->score_every, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     delete h;

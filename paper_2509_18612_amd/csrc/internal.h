@@ -9,12 +9,21 @@ namespace deco {
 // Device-resident control block of one handle. The step kernels read it at their start
 // and the last workgroup of every step updates it, so a captured graph of step launches
 // can be replayed without host involvement.
+//
+// Scoring of step t runs in three stages: launch t accumulates the score sums of X_t into
+// acc[t & 1] and writes its cut bits into bits[t % 3]; the completion of step t (sums to
+// cuts, best cut and step, improvement mask into mask[t & 1]) runs either in the last
+// workgroup of launch t (immediate mode) or in extra workgroups of launch t + 1 (lagged
+// mode, off the critical path); the launch after the completion folds the improved bits
+// into best_bits. A drain (launch_drain) completes and folds whatever is pending, so the
+// results are current after every host call that runs steps.
 struct DevCtrl {
   unsigned int ticket;  // XCDs whose workgroups all finished the current launch
-  int pending_slot;     // bit slot whose improvements are not yet folded into best_bits
-  long long t;          // index of the current iterate
   int score_every;
-  int pad;
+  long long t;          // index of the current iterate
+  long long cpend;      // scored step whose completion is pending (-1: none)
+  long long fpend;      // completed step whose improvements are not yet folded (-1: none)
+  long long drain[2];   // steps the drain folds, in this order (-1: none)
   unsigned int xticket[8][64];  // per-XCD completion counters, 256 bytes apart
 };
 
@@ -45,12 +54,14 @@ struct StepArgs {
   const int* seg;   // [9]
   float cW, cD;     // G = cW * (W X) + cD * (d_w . X)
   const float* eta; // [B]
-  uint8_t* bits[2]; // cut bits of the iterate scored at step t live in bits[t & 1]
+  uint8_t* bits[3]; // cut bits of the iterate scored at step t live in bits[t % 3]
   uint8_t* best_bits;
-  uint8_t* mask;    // [G][NBY] improvements of the last scored step
+  uint8_t* mask;    // [2][G][NBY]: improvements of scored step t in mask[t & 1]
   int NBY;
-  double* acc;      // [R][G][B] partial sums of w 1{z_v != z_u}
+  double* acc;      // [2][R][G][B] partial sums of w 1{z_v != z_u}; step t uses acc[t & 1]
   int R, G;
+  int nextra;       // lagged mode: workgroups after the work grid that complete step t - 1
+                    // (0: immediate mode)
   double* cur_cut;  // [G][B]
   double* best_cut; // [G][B]
   int* best_step;   // [G][B]
@@ -85,6 +96,11 @@ hipError_t launch_build_slots(long long n, long long nnz, const int* rp, const i
 hipError_t launch_reset(StepArgs a, double* acc_all, long long acc_count, int score_every,
                         hipStream_t s);
 hipError_t launch_merge(StepArgs a, long long n, const int* goff, hipStream_t s);
+// Completes a pending scored step and folds the pending improvements into best_bits
+// (two launches); idempotent.
+hipError_t launch_drain(StepArgs a, long long n, const int* goff, hipStream_t s);
+// Workgroups that complete one step's G * B cuts (256 each, at most 64).
+int completion_blocks(long long GB);
 hipError_t launch_fill_eta(float* eta, int B, float v, hipStream_t s);
 
 struct InitArgs {

@@ -562,21 +562,68 @@ __device__ __forceinline__ void gather_window(const StepArgs& a, const T* __rest
   }
 }
 
-// Completion of one step launch: two-level ticket, then the last workgroup finishes the
-// step. Inside a launch, workgroups exchange data only through device-scope atomics (score
-// accumulators, tickets), so no L2 write-back fence is needed: every lane waits until its
-// own atomics are acknowledged, then one lane takes its XCD's ticket and the last workgroup
-// of each XCD takes the global ticket. Plain stores (iterate, bits) are consumed by the
-// next launch, after the kernel boundary. The last workgroup turns the accumulated sums
-// into cuts (cut = a.cut_scale * sum, replicas added in replica order), updates best /
-// best step / improvement mask and advances the step counter. Every workgroup of the grid
-// must call this exactly once.
+// Completion of scored step s for the (graph, initialisation) pairs of the 256-wide blocks
+// blk, blk + nblk, ...: the R replicas of acc[s & 1] are summed in replica order and
+// cleared, cut = a.cut_scale * sum goes to cur_cut and the trace, a strictly larger cut
+// replaces the best cut (best step s), and the improvements go to mask[s & 1]. Every
+// thread of the workgroup calls it (blockDim.x = 256).
 constexpr int kMaxReplicas = 16;
-__device__ __forceinline__ void complete_step(const StepArgs& a, long long t, bool do_score, int par, int& s_last) {
+__device__ __forceinline__ void finish_scores(const StepArgs& a, long long s, int blk, int nblk) {
   const int tid = threadIdx.x, lane = tid & 63;
+  const int GB = a.G * a.B;
+  double* acc = a.acc + (size_t)(s & 1) * a.R * GB;
+  uint8_t* mask = a.mask + (size_t)(s & 1) * a.G * a.NBY;
+  const int chunk = a.B < 8 ? a.B : 8;
+  for (int base = blk * 256; base < GB; base += nblk * 256) {
+    const int idx = base + tid;
+    const bool in = idx < GB;
+    bool imp = false;
+    if (in) {
+      // all replica loads in flight together, summed in replica order
+      double v[kMaxReplicas];
+#pragma unroll
+      for (int r = 0; r < kMaxReplicas; ++r)
+        v[r] = r < a.R ? __hip_atomic_load(acc + (size_t)r * GB + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                       : 0.0;
+      double sum = 0.0;
+#pragma unroll
+      for (int r = 0; r < kMaxReplicas; ++r) sum += v[r];
+#pragma unroll
+      for (int r = 0; r < kMaxReplicas; ++r)
+        if (r < a.R) __hip_atomic_store(acc + (size_t)r * GB + idx, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const double cut = a.cut_scale * sum;
+      a.cur_cut[idx] = cut;
+      if (a.trace) a.trace[(size_t)(s % a.trace_cap) * GB + idx] = cut;
+      imp = cut > a.best_cut[idx];
+      if (imp) {
+        a.best_cut[idx] = cut;
+        a.best_step[idx] = (int)s;
+      }
+    }
+    const unsigned long long bal = __ballot(imp);
+    if (in && (idx % chunk) == 0) {
+      const int g = idx / a.B, b = idx % a.B;
+      mask[g * a.NBY + (b >> 3)] = (uint8_t)((bal >> lane) & ((1ull << chunk) - 1ull));
+    }
+  }
+}
+
+// End of one step launch: two-level ticket (per XCD, then global), and the last workgroup
+// advances the control block. Inside a launch, workgroups exchange data only through
+// device-scope atomics (score accumulators, tickets); plain stores (iterate, bits, cuts)
+// are consumed by later launches, after the kernel boundary. Immediate mode (nextra = 0):
+// every lane first waits until its own score atomics are acknowledged and the last
+// workgroup completes step t itself. Lagged mode: step t is completed by the extra
+// workgroups of the next launch, so nothing waits here. cp is the step whose completion
+// this launch's extra workgroups ran (read from the control block at the start). Every
+// workgroup of the grid must call this exactly once.
+__device__ __forceinline__ void complete_step(const StepArgs& a, long long t, bool do_score, long long cp,
+                                              int& s_last) {
+  const int tid = threadIdx.x;
   const int xcd = blockIdx.x & 7;
   const int nbx = ((int)gridDim.x - xcd + 7) >> 3;
-  __builtin_amdgcn_s_waitcnt(0);
+  const bool lag = a.nextra > 0;
+  if (!lag) __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (tid == 0) {
     bool last = false;
@@ -590,47 +637,16 @@ __device__ __forceinline__ void complete_step(const StepArgs& a, long long t, bo
   }
   __syncthreads();
   if (!s_last) return;
-  const int GB = a.G * a.B;
-  if (do_score) {
-    const int chunk = a.B < 8 ? a.B : 8;
-    for (int base = 0; base < GB; base += (int)blockDim.x) {
-      const int idx = base + tid;
-      const bool in = idx < GB;
-      bool imp = false;
-      if (in) {
-        // all replica loads in flight together, summed in replica order
-        double v[kMaxReplicas];
-#pragma unroll
-        for (int r = 0; r < kMaxReplicas; ++r)
-          v[r] = r < a.R ? __hip_atomic_load(a.acc + (size_t)r * GB + idx, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT)
-                         : 0.0;
-        double s = 0.0;
-#pragma unroll
-        for (int r = 0; r < kMaxReplicas; ++r) s += v[r];
-#pragma unroll
-        for (int r = 0; r < kMaxReplicas; ++r)
-          if (r < a.R)
-            __hip_atomic_store(a.acc + (size_t)r * GB + idx, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const double cut = a.cut_scale * s;
-        a.cur_cut[idx] = cut;
-        if (a.trace) a.trace[(size_t)(t % a.trace_cap) * GB + idx] = cut;
-        imp = cut > a.best_cut[idx];
-        if (imp) {
-          a.best_cut[idx] = cut;
-          a.best_step[idx] = (int)t;
-        }
-      }
-      const unsigned long long bal = __ballot(imp);
-      if (in && (idx % chunk) == 0) {
-        const int g = idx / a.B, b = idx % a.B;
-        a.mask[g * a.NBY + (b >> 3)] = (uint8_t)((bal >> lane) & ((1ull << chunk) - 1ull));
-      }
-    }
-  }
+  if (!lag && do_score) finish_scores(a, t, 0, 1);
   if (tid < 8) a.ctrl->xticket[tid][0] = 0u;
   if (tid == 0) {
-    a.ctrl->pending_slot = do_score ? par : -1;
+    if (lag) {
+      a.ctrl->fpend = cp;
+      a.ctrl->cpend = do_score ? t : -1;
+    } else {
+      a.ctrl->fpend = do_score ? t : -1;
+      a.ctrl->cpend = -1;
+    }
     if (a.do_update) a.ctrl->t = t + 1;
     a.ctrl->ticket = 0u;
   }
@@ -673,18 +689,28 @@ void k_step(StepArgs a) {
 
   const long long t = a.ctrl->t;
   const bool do_score = a.force_score || (t % a.ctrl->score_every) == 0;
-  const int pend = a.ctrl->pending_slot;
+  const long long cp = a.ctrl->cpend;  // step completed by the extra workgroups of this launch
+  const long long fp = a.ctrl->fpend;  // step whose improvements this launch folds
+  // the extra workgroups after the work grid complete step cp, off the critical path
+  const int gw = (int)gridDim.x - a.nextra;
+  if ((int)blockIdx.x >= gw) {
+    if (cp >= 0) finish_scores(a, cp, (int)blockIdx.x - gw, a.nextra);
+    complete_step(a, t, do_score, cp, s_last);
+    return;
+  }
   const int par = (int)(t & 1);
   const T* __restrict__ X = reinterpret_cast<const T*>(a.x[par]);
   T* __restrict__ Y = reinterpret_cast<T*>(a.x[par ^ 1]);
-  uint8_t* __restrict__ bw = a.bits[par];
-  const uint8_t* bm = pend >= 0 ? a.bits[pend] : nullptr;
+  uint8_t* __restrict__ bw = a.bits[t % 3];
+  const uint8_t* bm = fp >= 0 ? a.bits[fp % 3] : nullptr;
+  const uint8_t* fmask = a.mask + (size_t)(fp & 1) * a.G * a.NBY;
+  double* acc = a.acc + (size_t)(t & 1) * a.R * a.G * a.B;
   const int Bt = Wc * VEC;
   const int gb = VEC >= 8 ? 1 : (8 / VEC < Wc ? 8 / VEC : Wc);
 
   const int xcd = blockIdx.x & 7;
   const int kb = blockIdx.x >> 3;
-  const int nbx = ((int)gridDim.x - xcd + 7) >> 3;
+  const int nbx = (gw - xcd + 7) >> 3;
   const int it0 = a.seg[xcd], it1 = a.seg[xcd + 1];
 
   ScoreAcc<T, L, VEC, WM> sc;
@@ -711,7 +737,7 @@ void k_step(StepArgs a) {
 #pragma unroll
       for (int q = 1; q < kWaves; ++q) v += s_red[q * 256 + j];
       if (v != 0.0) {
-        double* dst = a.acc + ((size_t)(blockIdx.x & (a.R - 1)) * a.G + cg) * a.B + (size_t)cbt * Bt + j;
+        double* dst = acc + ((size_t)(blockIdx.x & (a.R - 1)) * a.G + cg) * a.B + (size_t)cbt * Bt + j;
         unsafeAtomicAdd(dst, v);
       }
     }
@@ -738,8 +764,8 @@ void k_step(StepArgs a) {
     const bool fwords = (a.NBY & 3) == 0 && (fTB & 3) == 0;
     const int fTW = fTB >> 2;
     uint32_t fold_m = 0u;
-    if (pend >= 0 && fwords)
-      fold_m = reinterpret_cast<const uint32_t*>(a.mask)[(size_t)cg * (a.NBY >> 2) + (fb0 >> 2) + (tid & (fTW - 1))];
+    if (fp >= 0 && fwords)
+      fold_m = reinterpret_cast<const uint32_t*>(fmask)[(size_t)cg * (a.NBY >> 2) + (fb0 >> 2) + (tid & (fTW - 1))];
     __syncthreads();  // LDS of the previous item is free
     // step sizes of the tile (read by the row updates after the staging barrier)
     for (int j = tid; j < Bt; j += kThreads) {
@@ -890,7 +916,7 @@ void k_step(StepArgs a) {
     // fold the previous scored step's improvements into best_bits for this item's rows and
     // tile (the bit slot bm is rewritten only by the launch after this one): 4-byte words
     // when rows and tiles are word aligned, all loads of a batch in flight together
-    if (pend >= 0) {
+    if (fp >= 0) {
       const int TB = fTB;
       const int b0 = fb0;
       const int R = y - x;
@@ -922,7 +948,7 @@ void k_step(StepArgs a) {
       } else {
         for (int k = tid; k < R * TB; k += kThreads) {
           const int r = k / TB, bb = b0 + k % TB;
-          const uint32_t m = a.mask[cg * a.NBY + bb];
+          const uint32_t m = fmask[cg * a.NBY + bb];
           if (m) {
             const size_t bi = (size_t)(x + r) * a.NBY + bb;
             a.best_bits[bi] = (uint8_t)((a.best_bits[bi] & ~m) | (bm[bi] & m));
@@ -932,7 +958,7 @@ void k_step(StepArgs a) {
     }
   }
 
-  complete_step(a, t, do_score, par, s_last);
+  complete_step(a, t, do_score, cp, s_last);
 }
 
 
@@ -1038,7 +1064,10 @@ __global__ __launch_bounds__(256) void k_dense_step(StepArgs a) {
   const int wm = wv >> 1, wn = wv & 1, hi = lane >> 5, lo = lane & 31;
   const long long t = a.ctrl->t;
   const bool do_score = a.force_score || (t % a.ctrl->score_every) == 0;
-  const int pend = a.ctrl->pending_slot;
+  const long long cp = a.ctrl->cpend;
+  const long long fp = a.ctrl->fpend;  // step whose improvements this launch folds
+  const uint8_t* fbits = fp >= 0 ? a.bits[fp % 3] : nullptr;
+  const uint8_t* fmask = a.mask + (size_t)(fp & 1) * a.NBY;
   const int par = (int)(t & 1);
   const uint16_t* __restrict__ X = reinterpret_cast<const uint16_t*>(a.x[par]);
   uint16_t* __restrict__ Y = reinterpret_cast<uint16_t*>(a.x[par ^ 1]);
@@ -1121,7 +1150,7 @@ __global__ __launch_bounds__(256) void k_dense_step(StepArgs a) {
     __syncthreads();
     if (do_score && tid < kDBN) {
       const double v = s_col[0][tid] + s_col[1][tid];
-      unsafeAtomicAdd(a.acc + (size_t)(blockIdx.x & (a.R - 1)) * a.B + col0 + tid, v);
+      unsafeAtomicAdd(a.acc + ((size_t)(t & 1) * a.R + (blockIdx.x & (a.R - 1))) * a.B + col0 + tid, v);
     }
     if (a.do_update) {
       // X_t+1 rows and XT_t+1 rows (columns of the tile), 16 bytes per store
@@ -1154,26 +1183,26 @@ __global__ __launch_bounds__(256) void k_dense_step(StepArgs a) {
           byte |= (((np & 1u) ^ 1u) | ((((np >> 16) & 1u) ^ 1u) << 1)) << (2 * q);
         }
         const size_t bi = (size_t)(row0 + r) * a.NBY + (col0 >> 3) + b;
-        if (pend >= 0) {
-          const uint32_t m = a.mask[(col0 >> 3) + b];
-          if (m) a.best_bits[bi] = (uint8_t)((a.best_bits[bi] & ~m) | (a.bits[pend][bi] & m));
+        if (fp >= 0) {
+          const uint32_t m = fmask[(col0 >> 3) + b];
+          if (m) a.best_bits[bi] = (uint8_t)((a.best_bits[bi] & ~m) | (fbits[bi] & m));
         }
-        a.bits[par][bi] = (uint8_t)byte;
+        a.bits[t % 3][bi] = (uint8_t)byte;
       }
     }
-  } else if (have && pend >= 0) {
+  } else if (have && fp >= 0) {
     // a launch that does not score still folds the pending improvements of its tile
     for (int e = tid; e < kDBM * (kDBN / 8); e += 256) {
       const int v = row0 + e / (kDBN / 8);
       const int by = (col0 >> 3) + e % (kDBN / 8);
-      const uint32_t m = a.mask[by];
+      const uint32_t m = fmask[by];
       if (m) {
         const size_t bi = (size_t)v * a.NBY + by;
-        a.best_bits[bi] = (uint8_t)((a.best_bits[bi] & ~m) | (a.bits[pend][bi] & m));
+        a.best_bits[bi] = (uint8_t)((a.best_bits[bi] & ~m) | (fbits[bi] & m));
       }
     }
   }
-  complete_step(a, t, do_score, par, s_last);
+  complete_step(a, t, do_score, cp, s_last);
 }
 
 // XT = X^T for the dense path (bfloat16, n x C -> C x n), 64 x 64 tiles through LDS.
@@ -1223,7 +1252,7 @@ __global__ void k_dense_validate(const uint16_t* W, int n, float* dw, int* flags
 
 template <typename T, int VEC, int LL>
 hipError_t step_dispatch(const StepArgs& a, int wmode, int grid, hipStream_t s) {
-  const dim3 g(grid), b(kThreads);
+  const dim3 g(grid + a.nextra), b(kThreads);
   if (wmode == kUnitW)
     hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW>), g, b, 0, s, a);
   else if (wmode == kPm1W)
@@ -1337,22 +1366,39 @@ __global__ void k_reset(StepArgs a, double* acc_all, long long acc_count, int sc
     a.best_step[i] = -1;
     a.cur_cut[i] = -__builtin_inf();
   }
-  if (i < (long long)a.G * a.NBY) a.mask[i] = 0;
+  if (i < 2LL * a.G * a.NBY) a.mask[i] = 0;
   if (i < 8) a.ctrl->xticket[i][0] = 0u;
   if (i == 0) {
     a.ctrl->ticket = 0u;
-    a.ctrl->pending_slot = -1;
-    a.ctrl->t = 0;
     a.ctrl->score_every = score_every;
-    a.ctrl->pad = 0;
+    a.ctrl->t = 0;
+    a.ctrl->cpend = -1;
+    a.ctrl->fpend = -1;
+    a.ctrl->drain[0] = -1;
+    a.ctrl->drain[1] = -1;
   }
 }
 
-// Fold the pending improvement mask into best_bits (idempotent until the slot is reused).
+// First half of a drain: completes the pending scored step (if any) and records the steps
+// whose improvements the merge folds, older first.
+__global__ __launch_bounds__(256) void k_complete(StepArgs a) {
+  const long long cp = a.ctrl->cpend;
+  if (cp >= 0) finish_scores(a, cp, blockIdx.x, gridDim.x);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.ctrl->drain[0] = a.ctrl->fpend;
+    a.ctrl->drain[1] = cp;
+  }
+}
+
+// Second half of a drain: folds the improvements of the recorded steps into best_bits, in
+// order, and clears the pending marks (idempotent until the bit slots are reused).
 __global__ void k_merge(StepArgs a, long long n, const int* goff) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int pend = a.ctrl->pending_slot;
-  if (pend < 0 || i >= n * a.NBY) return;
+  if (i == 0) {
+    a.ctrl->cpend = -1;
+    a.ctrl->fpend = -1;
+  }
+  if (i >= n * a.NBY) return;
   const long long row = i / a.NBY;
   const int by = (int)(i % a.NBY);
   int lo = 0, hi = a.G;
@@ -1360,11 +1406,15 @@ __global__ void k_merge(StepArgs a, long long n, const int* goff) {
     const int mid = (lo + hi) >> 1;
     if (goff[mid] <= row) lo = mid; else hi = mid;
   }
-  const uint32_t m = a.mask[lo * a.NBY + by];
-  if (m) {
-    const uint32_t old = a.bits[pend][i];
-    const uint32_t bb = a.best_bits[i];
-    a.best_bits[i] = (uint8_t)((bb & ~m) | (old & m));
+  for (int k = 0; k < 2; ++k) {
+    const long long s = a.ctrl->drain[k];
+    if (s < 0) continue;
+    const uint32_t m = a.mask[(size_t)(s & 1) * a.G * a.NBY + lo * a.NBY + by];
+    if (m) {
+      const uint32_t bits = a.bits[s % 3][i];
+      const uint32_t bb = a.best_bits[i];
+      a.best_bits[i] = (uint8_t)((bb & ~m) | (bits & m));
+    }
   }
 }
 
@@ -1573,11 +1623,23 @@ hipError_t launch_reset(StepArgs a, double* acc_all, long long acc_count, int sc
   long long m = acc_count;
   const long long GB = (long long)a.G * a.B;
   if (GB > m) m = GB;
-  if ((long long)a.G * a.NBY > m) m = (long long)a.G * a.NBY;
+  if (2LL * a.G * a.NBY > m) m = 2LL * a.G * a.NBY;
   if (m < 1) m = 1;
   hipLaunchKernelGGL(k_reset, dim3(blocks_for(m, 256)), dim3(256), 0, s, a, acc_all, acc_count,
                      score_every);
   return hipGetLastError();
+}
+
+int completion_blocks(long long GB) {
+  const long long b = (GB + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > 64 ? 64 : b));
+}
+
+hipError_t launch_drain(StepArgs a, long long n, const int* goff, hipStream_t s) {
+  hipLaunchKernelGGL(k_complete, dim3(completion_blocks((long long)a.G * a.B)), dim3(256), 0, s, a);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_merge(a, n, goff, s);
 }
 
 hipError_t launch_merge(StepArgs a, long long n, const int* goff, hipStream_t s) {
