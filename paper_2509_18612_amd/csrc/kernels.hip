@@ -161,12 +161,13 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kSelfBit = (int)0x80000000;  // slot flag: the row's own entry
 
-// Slots gathered together by one row team: 16 loads in flight per lane for unlifted rows,
-// 8 when the l > 1 components also hold registers (32 for one-element lanes), divided
-// among the l components.
+// Slots gathered together by one row team: 16 loads in flight per lane for unlifted rows
+// (12 for 16-byte lanes, whose values take twice the registers), 8 when the l > 1
+// components also hold registers (32 for one-element lanes), divided among the l
+// components.
 template <typename T, int L, int VEC>
 struct Tune {
-  static constexpr int kLoads = VEC == 1 ? 32 : (L == 1 ? 16 : 8);
+  static constexpr int kLoads = VEC == 1 ? 32 : (L == 1 ? ((int)sizeof(T) * VEC >= 16 ? 12 : 16) : 8);
   static constexpr int W = kLoads / L < 1 ? 1 : kLoads / L;
 };
 
@@ -251,6 +252,13 @@ struct RowState {
   float dsum; // weighted degree (Laplacian form)
   bool head;  // continuation of an earlier team's row
   bool lazy;  // zm not yet formed from xv
+  uint32_t ulo, uhi;  // bfloat16 pairs (1, 0) and (0, 1) for the dot instruction (unit weights)
+  __device__ __forceinline__ void set_unit_pairs() {
+    ulo = 0x00003F80u;
+    asm volatile("" : "+v"(ulo));  // keep the pair in a register, formed once
+    uhi = ulo << 16;
+    asm volatile("" : "+v"(uhi));
+  }
 };
 
 // Score partials of a workgroup's current item per initialisation of the lane: packed 16-bit
@@ -433,10 +441,8 @@ __device__ __forceinline__ void take_slot(RowState<T, L, VEC, WM>& st, const typ
       wd[0] = xr[0].x;
       wd[1] = xr[0].y;
     }
-    uint32_t wlo = WM == kUnitW ? 0x00003F80u : (__float_as_uint(wq) >> 16);
-    if (WM == kUnitW) asm volatile("" : "+v"(wlo));  // keep the pair in a register
-    uint32_t whi = wlo << 16;
-    if (WM == kUnitW) asm volatile("" : "+v"(whi));
+    const uint32_t wlo = WM == kUnitW ? st.ulo : (__float_as_uint(wq) >> 16);
+    const uint32_t whi = WM == kUnitW ? st.uhi : wlo << 16;
 #pragma unroll
     for (int k = 0; k < VEC / 2; ++k) {
       st.acc[0][2 * k] = dot2_bf16(wd[k], wlo, st.acc[0][2 * k]);
@@ -457,10 +463,8 @@ __device__ __forceinline__ void take_slot(RowState<T, L, VEC, WM>& st, const typ
   } else if constexpr (sizeof(T) == 2 && VEC >= 2 && (WM == kUnitW || WM == kPm1W)) {
     // bfloat16 rows of l > 1 components with unit or +-1 weights: the sums with the dot
     // instruction from the raw words; values are unpacked only to score
-    uint32_t wlo = WM == kUnitW ? 0x00003F80u : (__float_as_uint(wq) >> 16);
-    if (WM == kUnitW) asm volatile("" : "+v"(wlo));  // keep the pair in a register
-    uint32_t whi = wlo << 16;
-    if (WM == kUnitW) asm volatile("" : "+v"(whi));
+    const uint32_t wlo = WM == kUnitW ? st.ulo : (__float_as_uint(wq) >> 16);
+    const uint32_t whi = WM == kUnitW ? st.uhi : wlo << 16;
 #pragma unroll
     for (int i = 0; i < L; ++i) {
       uint32_t wd[VEC / 2];
@@ -539,10 +543,10 @@ __device__ __forceinline__ void gather_window(const StepArgs& a, const T* __rest
   typename IO::raw xr[W][L];
 #pragma unroll
   for (int q = 0; q < W; ++q) {
-    const bool ok = p + q < pe;
+    // slots past the share read row 0 (always present) and are not folded: no branch per load
     const size_t node = (size_t)(sl[q] & 0x7FFFFFFF);
 #pragma unroll
-    for (int i = 0; i < L; ++i) xr[q][i] = ok ? IO::load_raw(X + node * C + i * B + bl) : IO::zero();
+    for (int i = 0; i < L; ++i) xr[q][i] = IO::load_raw(X + node * C + i * B + bl);
   }
   if (st.lazy) {
     st.zm = side_mask_raw<T, VEC, L>(st.xv, a.lifted);
@@ -557,6 +561,64 @@ __device__ __forceinline__ void gather_window(const StepArgs& a, const T* __rest
         open_row<T, L, VEC, WM>(st, sl[q] & 0x7FFFFFFF, xr[q], wq, a.lifted);
       } else {
         take_slot<T, VEC, L, WM>(st, xr[q], wq, do_score, a.lifted);
+      }
+    }
+  }
+}
+
+// Software-pipelined windows of the normal path of lifted rows: the gathers of the next
+// window are in flight while the current one is folded. Two buffers of PW slots with fixed names (the
+// loop is unrolled by two, so both stay in registers), at most 128 bytes of gathered
+// values per lane each.
+template <typename T, int L, int VEC>
+struct PipeTune {
+  static constexpr int kRawBytes = (int)sizeof(typename VecIO<T, VEC>::raw) * L;
+  static constexpr int W0 = Tune<T, L, VEC>::W;
+  static constexpr int W1 = VEC == 1 ? W0 / 2 : W0;  // one-element lanes: the slot indices count too
+  static constexpr int W = W1 * kRawBytes <= 128 ? W1 : (128 / kRawBytes < 1 ? 1 : 128 / kRawBytes);
+};
+
+template <typename T, int VEC, int L, int PW>
+struct WinBuf {
+  int sl[PW];
+  typename VecIO<T, VEC>::raw xr[PW][L];
+};
+
+template <typename T, int VEC, int L, int PW>
+__device__ __forceinline__ void load_window(const StepArgs& a, const T* __restrict__ X, const int* s_slot, int p,
+                                            int pe, int bl, WinBuf<T, VEC, L, PW>& wb) {
+  using IO = VecIO<T, VEC>;
+  const size_t C = (size_t)a.C, B = (size_t)a.B;
+#pragma unroll
+  for (int q = 0; q < PW; ++q) wb.sl[q] = (p + q < pe) ? s_slot[p + q] : 0;
+#pragma unroll
+  for (int q = 0; q < PW; ++q) {
+    // slots past the share read row 0 (always present) and are not folded: no branch per load
+    const size_t node = (size_t)(wb.sl[q] & 0x7FFFFFFF);
+#pragma unroll
+    for (int i = 0; i < L; ++i) wb.xr[q][i] = IO::load_raw(X + node * C + i * B + bl);
+  }
+}
+
+template <typename T, int VEC, int L, int WM, int PW>
+__device__ __forceinline__ void fold_window(const StepArgs& a, T* __restrict__ Y, uint8_t* __restrict__ bw,
+                                            const float* s_sw, float* s_part, int part_idx, int p, int pe, int bl,
+                                            int lc, int gb, const float* __restrict__ eta,
+                                            const WinBuf<T, VEC, L, PW>& wb, RowState<T, L, VEC, WM>& st,
+                                            ScoreAcc<T, L, VEC, WM>& sc, bool do_score) {
+  if (st.lazy) {
+    st.zm = side_mask_raw<T, VEC, L>(st.xv, a.lifted);
+    st.lazy = false;
+  }
+#pragma unroll
+  for (int q = 0; q < PW; ++q) {
+    if (p + q < pe) {
+      const float wq = WM == kUnitW ? 1.0f : s_sw[p + q];
+      if (wb.sl[q] < 0) {
+        if (st.row >= 0) close_row<T, VEC, L, WM>(a, Y, bw, s_part, part_idx, do_score, bl, lc, gb, eta, st, sc);
+        open_row<T, L, VEC, WM>(st, wb.sl[q] & 0x7FFFFFFF, wb.xr[q], wq, a.lifted);
+      } else {
+        take_slot<T, VEC, L, WM>(st, wb.xr[q], wq, do_score, a.lifted);
       }
     }
   }
@@ -790,6 +852,7 @@ void k_step(StepArgs a) {
       const int c1 = (E * (sgi + 1)) >> nsl;
       const int part_idx = (sgi * Wc + lc) * (L * VEC);
       RowState<T, L, VEC, WM> st;
+      st.set_unit_pairs();
       st.row = -1;
       st.zm = 0u;
       st.dsum = 0.0f;
@@ -815,9 +878,26 @@ void k_step(StepArgs a) {
           }
         }
       }
-      for (int p = c0; p < c1; p += W)
-        gather_window<T, VEC, L, WM, true>(a, X, Y, bw, s_slot, s_sw, s_acc, part_idx, p, c1, bl, lc, gb, eta, st,
-                                           sc, do_score);
+      if constexpr (L == 1) {
+        // unlifted rows: one window at a time (their folds are short; the loads of a window
+        // are waited for one by one)
+        for (int p = c0; p < c1; p += W)
+          gather_window<T, VEC, L, WM, true>(a, X, Y, bw, s_slot, s_sw, s_acc, part_idx, p, c1, bl, lc, gb, eta, st,
+                                             sc, do_score);
+      } else {
+        // lifted rows: the next window's gathers are in flight during each fold
+        constexpr int PW = PipeTune<T, L, VEC>::W;
+        WinBuf<T, VEC, L, PW> wa, wb;
+        load_window<T, VEC, L, PW>(a, X, s_slot, c0, c1, bl, wa);
+        for (int p = c0; p < c1; p += 2 * PW) {
+          load_window<T, VEC, L, PW>(a, X, s_slot, p + PW, c1, bl, wb);
+          fold_window<T, VEC, L, WM, PW>(a, Y, bw, s_sw, s_acc, part_idx, p, c1, bl, lc, gb, eta, wa, st, sc,
+                                         do_score);
+          load_window<T, VEC, L, PW>(a, X, s_slot, p + 2 * PW, c1, bl, wa);
+          fold_window<T, VEC, L, WM, PW>(a, Y, bw, s_sw, s_acc, part_idx, p + PW, c1, bl, lc, gb, eta, wb, st, sc,
+                                         do_score);
+        }
+      }
       bool tail = false;
       int next = 0;
       if (st.row >= 0) {
@@ -855,6 +935,7 @@ void k_step(StepArgs a) {
       // one long row: every team takes a contiguous share of each staged chunk of its
       // neighbour slots; the partial sums are reduced in a fixed order
       RowState<T, L, VEC, WM> st;
+      st.set_unit_pairs();
       st.row = x;
 #pragma unroll
       for (int i = 0; i < L; ++i) {
