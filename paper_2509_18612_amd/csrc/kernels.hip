@@ -159,7 +159,7 @@ __device__ __forceinline__ bool side_of(const float (&x)[L], int lifted) {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kSelfBit = (int)0x80000000;  // slot flag: the row's own entry
+constexpr int kSlotPad = 32;  // staged slots are read up to a window past a share
 
 // Slots gathered together by one row team: 16 loads in flight per lane for unlifted rows
 // (12 for 16-byte lanes, whose values take twice the registers), 8 when the l > 1
@@ -363,7 +363,10 @@ __device__ __forceinline__ void finish_row(const StepArgs& a, T* __restrict__ Y,
   }
   // cut bits of X_t: one byte per 8 initialisations, assembled over gb lanes
   uint32_t byte = (st.zm & ((1u << VEC) - 1u)) << ((lc * VEC) & 7);
-  for (int s = 1; s < gb; s <<= 1) byte |= __shfl_xor(byte, s);
+  // neighbour lanes 1 and 2 apart through DPP quad permutations, 4 apart through LDS
+  if (gb > 1) byte |= (uint32_t)__builtin_amdgcn_mov_dpp((int)byte, 0xB1, 0xF, 0xF, false);  // lanes i ^ 1
+  if (gb > 2) byte |= (uint32_t)__builtin_amdgcn_mov_dpp((int)byte, 0x4E, 0xF, 0xF, false);  // lanes i ^ 2
+  if (gb > 4) byte |= __shfl_xor(byte, 4);
   if (do_score && lead && (lc % gb) == 0) bw[(size_t)st.row * a.NBY + (bl >> 3)] = (uint8_t)byte;
 }
 
@@ -537,9 +540,15 @@ __device__ __forceinline__ void gather_window(const StepArgs& a, const T* __rest
   using IO = VecIO<T, VEC>;
   constexpr int W = Tune<T, L, VEC>::W;
   const size_t C = (size_t)a.C, B = (size_t)a.B;
+  static_assert(W <= kSlotPad, "window reads past the staged slots");
+  // branch-free slot reads (the staging array is padded), then the slots past the share
+  // are replaced by row 0
   int sl[W];
 #pragma unroll
-  for (int q = 0; q < W; ++q) sl[q] = (p + q < pe) ? s_slot[p + q] : 0;
+  for (int q = 0; q < W; ++q) {
+    const int v = s_slot[p + q];
+    sl[q] = (p + q < pe) ? v : 0;
+  }
   typename IO::raw xr[W][L];
 #pragma unroll
   for (int q = 0; q < W; ++q) {
@@ -590,7 +599,10 @@ __device__ __forceinline__ void load_window(const StepArgs& a, const T* __restri
   using IO = VecIO<T, VEC>;
   const size_t C = (size_t)a.C, B = (size_t)a.B;
 #pragma unroll
-  for (int q = 0; q < PW; ++q) wb.sl[q] = (p + q < pe) ? s_slot[p + q] : 0;
+  for (int q = 0; q < PW; ++q) {
+    const int v = s_slot[p + q];
+    wb.sl[q] = (p + q < pe) ? v : 0;
+  }
 #pragma unroll
   for (int q = 0; q < PW; ++q) {
     // slots past the share read row 0 (always present) and are not folded: no branch per load
@@ -724,7 +736,7 @@ void k_step(StepArgs a) {
   constexpr int W = Tune<T, L, VEC>::W;
   using ST = typename ScoreType<WM>::type;
   using IO = VecIO<T, VEC>;
-  __shared__ int s_slot[kEmax];
+  __shared__ int s_slot[kEmax + kSlotPad];
   __shared__ float s_sw[WM == kUnitW ? 1 : kEmax];
   __shared__ int s_rp[kRmax + 1];
   __shared__ __align__(16) float s_eta[512];
@@ -887,6 +899,7 @@ void k_step(StepArgs a) {
       } else {
         // lifted rows: the next window's gathers are in flight during each fold
         constexpr int PW = PipeTune<T, L, VEC>::W;
+        static_assert(3 * PW <= kSlotPad, "windows read past the staged slots");
         WinBuf<T, VEC, L, PW> wa, wb;
         load_window<T, VEC, L, PW>(a, X, s_slot, c0, c1, bl, wa);
         for (int p = c0; p < c1; p += 2 * PW) {
