@@ -273,14 +273,16 @@ deco_status upload_schedule(deco_handle* h) {
 }
 
 // Slots one row team gathers per window (the kernel's window for this lane width and l).
-int window_slots(int vec, int L) {
-  const int loads = vec == 1 ? 32 : (L == 1 ? 16 : 8);
+int window_slots(int vec, int L, int dtype) {
+  const int loads = vec == 1 ? 32 : (L == 1 ? (vec * elem_size(dtype) >= 16 ? 12 : 16) : 8);
   return std::max(1, loads / L);
 }
 
 Schedule default_schedule(deco_handle* h) {
   Schedule s;
-  s.vec = vec_for(h->dtype, h->p.B, h->p.l);
+  // lanes of several elements address rows with 32-bit offsets: n < 2^24 and n * C < 2^32
+  const bool small = h->n < (1LL << 24) && (unsigned long long)h->n * h->C < (1ULL << 32);
+  s.vec = small ? vec_for(h->dtype, h->p.B, h->p.l) : 1;
   s.Wc = max_wc(s.vec, h->p.B);
   // lifted rows: half-width tiles (twice the teams) when the tile stays wide enough
   if (h->p.l > 1 && s.Wc > 1) {
@@ -295,7 +297,7 @@ Schedule default_schedule(deco_handle* h) {
   s.blocks_per_xcd = kMaxBlocksPerXcd;
   const long long slots = h->nnz + h->n;
   const long long teams = 256 / s.Wc;
-  const long long per = std::max<long long>(teams * window_slots(s.vec, h->p.l), (slots + 767) / 768);
+  const long long per = std::max<long long>(teams * window_slots(s.vec, h->p.l, h->dtype), (slots + 767) / 768);
   s.nnz_per_item = (int)std::max<long long>(kMinItemSlots, std::min<long long>(kEmax, per));
   s.rows_per_item = kRmax;
   return s;

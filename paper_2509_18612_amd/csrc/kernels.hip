@@ -531,6 +531,15 @@ __device__ __forceinline__ void take_slot(RowState<T, L, VEC, WM>& st, const typ
 // gathers of the window are issued before any is used; then the slots are folded in list
 // order: a self slot (SELF lists only) closes the open row and opens its own, a neighbour
 // slot is taken into the open row.
+// Element offset of a gathered node's row (the slot's flag bit is ignored). Lanes of
+// several elements run only where n < 2^24 and n * C < 2^32 (the host keeps larger graphs
+// on one-element lanes): one full-rate 24-bit multiply instead of a 64-bit one.
+template <int VEC>
+__device__ __forceinline__ size_t row_offset(int slot, int C) {
+  if constexpr (VEC == 1) return (size_t)((uint32_t)slot & 0x7FFFFFFFu) * (size_t)C;
+  else return (size_t)(uint32_t)__umul24((uint32_t)slot, (uint32_t)C);
+}
+
 template <typename T, int VEC, int L, int WM, bool SELF>
 __device__ __forceinline__ void gather_window(const StepArgs& a, const T* __restrict__ X, T* __restrict__ Y,
                                               uint8_t* __restrict__ bw, const int* s_slot, const float* s_sw,
@@ -539,23 +548,23 @@ __device__ __forceinline__ void gather_window(const StepArgs& a, const T* __rest
                                               ScoreAcc<T, L, VEC, WM>& sc, bool do_score) {
   using IO = VecIO<T, VEC>;
   constexpr int W = Tune<T, L, VEC>::W;
-  const size_t C = (size_t)a.C, B = (size_t)a.B;
+  const size_t B = (size_t)a.B;
   static_assert(W <= kSlotPad, "window reads past the staged slots");
   // branch-free slot reads (the staging array is padded), then the slots past the share
   // are replaced by row 0
+  const int rem = pe - p;
   int sl[W];
 #pragma unroll
   for (int q = 0; q < W; ++q) {
     const int v = s_slot[p + q];
-    sl[q] = (p + q < pe) ? v : 0;
+    sl[q] = q < rem ? v : 0;
   }
   typename IO::raw xr[W][L];
 #pragma unroll
   for (int q = 0; q < W; ++q) {
     // slots past the share read row 0 (always present) and are not folded: no branch per load
-    const size_t node = (size_t)(sl[q] & 0x7FFFFFFF);
 #pragma unroll
-    for (int i = 0; i < L; ++i) xr[q][i] = IO::load_raw(X + node * C + i * B + bl);
+    for (int i = 0; i < L; ++i) xr[q][i] = IO::load_raw(X + row_offset<VEC>(sl[q], a.C) + i * B + bl);
   }
   if (st.lazy) {
     st.zm = side_mask_raw<T, VEC, L>(st.xv, a.lifted);
@@ -563,7 +572,7 @@ __device__ __forceinline__ void gather_window(const StepArgs& a, const T* __rest
   }
 #pragma unroll
   for (int q = 0; q < W; ++q) {
-    if (p + q < pe) {
+    if (q < rem) {
       const float wq = WM == kUnitW ? 1.0f : s_sw[p + q];
       if (SELF && sl[q] < 0) {
         if (st.row >= 0) close_row<T, VEC, L, WM>(a, Y, bw, s_part, part_idx, do_score, bl, lc, gb, eta, st, sc);
@@ -597,18 +606,18 @@ template <typename T, int VEC, int L, int PW>
 __device__ __forceinline__ void load_window(const StepArgs& a, const T* __restrict__ X, const int* s_slot, int p,
                                             int pe, int bl, WinBuf<T, VEC, L, PW>& wb) {
   using IO = VecIO<T, VEC>;
-  const size_t C = (size_t)a.C, B = (size_t)a.B;
+  const size_t B = (size_t)a.B;
+  const int rem = pe - p;
 #pragma unroll
   for (int q = 0; q < PW; ++q) {
     const int v = s_slot[p + q];
-    wb.sl[q] = (p + q < pe) ? v : 0;
+    wb.sl[q] = q < rem ? v : 0;
   }
 #pragma unroll
   for (int q = 0; q < PW; ++q) {
     // slots past the share read row 0 (always present) and are not folded: no branch per load
-    const size_t node = (size_t)(wb.sl[q] & 0x7FFFFFFF);
 #pragma unroll
-    for (int i = 0; i < L; ++i) wb.xr[q][i] = IO::load_raw(X + node * C + i * B + bl);
+    for (int i = 0; i < L; ++i) wb.xr[q][i] = IO::load_raw(X + row_offset<VEC>(wb.sl[q], a.C) + i * B + bl);
   }
 }
 
@@ -622,9 +631,10 @@ __device__ __forceinline__ void fold_window(const StepArgs& a, T* __restrict__ Y
     st.zm = side_mask_raw<T, VEC, L>(st.xv, a.lifted);
     st.lazy = false;
   }
+  const int rem = pe - p;
 #pragma unroll
   for (int q = 0; q < PW; ++q) {
-    if (p + q < pe) {
+    if (q < rem) {
       const float wq = WM == kUnitW ? 1.0f : s_sw[p + q];
       if (wb.sl[q] < 0) {
         if (st.row >= 0) close_row<T, VEC, L, WM>(a, Y, bw, s_part, part_idx, do_score, bl, lc, gb, eta, st, sc);

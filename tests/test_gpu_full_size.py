@@ -199,3 +199,32 @@ def test_solver_object_continues_and_multi_graph():
         o = bd.graph_row_offset
         assert r2["best_cut"][i] == oracle.cut(gi, r2["z"][o[i]:o[i + 1]])
     s.destroy()
+
+
+def test_rows_beyond_24_bits_use_one_element_lanes():
+    """A cycle of n = 2^24 + 3 rows, B = 8, bfloat16: lanes of several elements address rows
+    with 24-bit offsets, so a graph this large runs on one-element lanes (64-bit addresses).
+    One step: sampled rows (including the last ones) against the oracle, exact cut of X_0 for
+    every initialisation."""
+    n = (1 << 24) + 3
+    g = synth.cycle(n)
+    G = deco.Graph(g)
+    h = deco.Handle(G, B=8, x_dtype=deco.BF16, eta=0.1, seed=2)
+    assert "vec=1" in h.schedule()
+    h.start(deco.INIT_UNIFORM, batch=0)
+    tr = h.set_trace(2)
+    x0_dev = h.read_x().clone()
+    h.step(1)
+    x1_dev = h.read_x()
+    rng = np.random.default_rng(5)
+    rows = np.concatenate([rng.integers(0, n, 2000), np.arange(n - 8, n), np.arange((1 << 24) - 4, (1 << 24) + 3)])
+    mini, src, centre = star_rows(g, rows)
+    idx = torch.from_numpy(src).cuda()
+    xs = to_np(x0_dev[idx]).astype(np.float64)
+    got = to_np(x1_dev[torch.from_numpy(rows).cuda()]).astype(np.float64)
+    want = oracle.step(mini, xs, 0.1)[centre]
+    emu = oracle.to_bf16(want.astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(got - emu) <= bf16_ulp(emu) + 1e-5)
+    x0 = to_np(x0_dev).astype(np.float64)
+    assert np.array_equal(tr.cpu().numpy()[0], oracle_cuts(g, x0, 8, 1, False)[0])
+    h.destroy()
