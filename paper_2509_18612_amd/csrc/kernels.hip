@@ -246,7 +246,8 @@ struct RowState {
   float acc[L][VEC];
   i16x2 zp[kPacked ? VEC / 2 : 1];
   ST zs[kPacked ? 1 : VEC];
-  ST wsum;
+  ST wsum;   // weights: accumulated per slot; unit weights: set from positions before use
+  int open;  // staged position of the first slot of the open row taken in this share
   uint32_t zm;
   int row;    // -1 while no row is open
   float dsum; // weighted degree (Laplacian form)
@@ -376,9 +377,10 @@ template <typename T, int VEC, int L, int WM>
 __device__ __forceinline__ void close_row(const StepArgs& a, T* __restrict__ Y, uint8_t* __restrict__ bw,
                                           float* s_part, int part_idx, bool do_score, int bl, int lc, int gb,
                                           const float* __restrict__ eta, RowState<T, L, VEC, WM>& st,
-                                          ScoreAcc<T, L, VEC, WM>& sc) {
+                                          ScoreAcc<T, L, VEC, WM>& sc, int pos, int lifted) {
+  if constexpr (WM == kUnitW) st.wsum = pos - st.open;  // neighbours taken in this share
   if (WM == kUnitW && !st.head) st.dsum = (float)st.wsum;  // degree: the row's slots were all taken here
-  if (do_score) close_score(st, sc, a.lifted);
+  if (do_score) close_score(st, sc, lifted);
   if (st.head)
     put_part<L, VEC>(s_part, part_idx, st.acc);
   else
@@ -388,8 +390,10 @@ __device__ __forceinline__ void close_row(const StepArgs& a, T* __restrict__ Y, 
 // Opens the row whose own slot was just read.
 template <typename T, int L, int VEC, int WM>
 __device__ __forceinline__ void open_row(RowState<T, L, VEC, WM>& st, int row,
-                                         const typename VecIO<T, VEC>::raw (&xr)[L], float wself, int lifted) {
+                                         const typename VecIO<T, VEC>::raw (&xr)[L], float wself, int lifted,
+                                         int pos) {
   st.row = row;
+  st.open = pos + 1;
   st.head = false;
   st.dsum = WM == kUnitW ? 0.0f : wself;
 #pragma unroll
@@ -524,7 +528,7 @@ __device__ __forceinline__ void take_slot(RowState<T, L, VEC, WM>& st, const typ
       }
     }
   }
-  st.wsum += WM == kUnitW ? (ST)1 : (ST)wq;
+  if constexpr (WM != kUnitW) st.wsum += (ST)wq;
 }
 
 // One window of the team's slot range: slots [p, min(p + W, pe)) of the staged list. All
@@ -545,7 +549,7 @@ __device__ __forceinline__ void gather_window(const StepArgs& a, const T* __rest
                                               uint8_t* __restrict__ bw, const int* s_slot, const float* s_sw,
                                               float* s_part, int part_idx, int p, int pe, int bl, int lc, int gb,
                                               const float* __restrict__ eta, RowState<T, L, VEC, WM>& st,
-                                              ScoreAcc<T, L, VEC, WM>& sc, bool do_score) {
+                                              ScoreAcc<T, L, VEC, WM>& sc, bool do_score, int lifted) {
   using IO = VecIO<T, VEC>;
   constexpr int W = Tune<T, L, VEC>::W;
   const size_t B = (size_t)a.B;
@@ -567,7 +571,7 @@ __device__ __forceinline__ void gather_window(const StepArgs& a, const T* __rest
     for (int i = 0; i < L; ++i) xr[q][i] = IO::load_raw(X + row_offset<VEC>(sl[q], a.C) + i * B + bl);
   }
   if (st.lazy) {
-    st.zm = side_mask_raw<T, VEC, L>(st.xv, a.lifted);
+    st.zm = side_mask_raw<T, VEC, L>(st.xv, lifted);
     st.lazy = false;
   }
 #pragma unroll
@@ -575,10 +579,11 @@ __device__ __forceinline__ void gather_window(const StepArgs& a, const T* __rest
     if (q < rem) {
       const float wq = WM == kUnitW ? 1.0f : s_sw[p + q];
       if (SELF && sl[q] < 0) {
-        if (st.row >= 0) close_row<T, VEC, L, WM>(a, Y, bw, s_part, part_idx, do_score, bl, lc, gb, eta, st, sc);
-        open_row<T, L, VEC, WM>(st, sl[q] & 0x7FFFFFFF, xr[q], wq, a.lifted);
+        if (st.row >= 0)
+          close_row<T, VEC, L, WM>(a, Y, bw, s_part, part_idx, do_score, bl, lc, gb, eta, st, sc, p + q, lifted);
+        open_row<T, L, VEC, WM>(st, sl[q] & 0x7FFFFFFF, xr[q], wq, lifted, p + q);
       } else {
-        take_slot<T, VEC, L, WM>(st, xr[q], wq, do_score, a.lifted);
+        take_slot<T, VEC, L, WM>(st, xr[q], wq, do_score, lifted);
       }
     }
   }
@@ -626,9 +631,9 @@ __device__ __forceinline__ void fold_window(const StepArgs& a, T* __restrict__ Y
                                             const float* s_sw, float* s_part, int part_idx, int p, int pe, int bl,
                                             int lc, int gb, const float* __restrict__ eta,
                                             const WinBuf<T, VEC, L, PW>& wb, RowState<T, L, VEC, WM>& st,
-                                            ScoreAcc<T, L, VEC, WM>& sc, bool do_score) {
+                                            ScoreAcc<T, L, VEC, WM>& sc, bool do_score, int lifted) {
   if (st.lazy) {
-    st.zm = side_mask_raw<T, VEC, L>(st.xv, a.lifted);
+    st.zm = side_mask_raw<T, VEC, L>(st.xv, lifted);
     st.lazy = false;
   }
   const int rem = pe - p;
@@ -637,10 +642,11 @@ __device__ __forceinline__ void fold_window(const StepArgs& a, T* __restrict__ Y
     if (q < rem) {
       const float wq = WM == kUnitW ? 1.0f : s_sw[p + q];
       if (wb.sl[q] < 0) {
-        if (st.row >= 0) close_row<T, VEC, L, WM>(a, Y, bw, s_part, part_idx, do_score, bl, lc, gb, eta, st, sc);
-        open_row<T, L, VEC, WM>(st, wb.sl[q] & 0x7FFFFFFF, wb.xr[q], wq, a.lifted);
+        if (st.row >= 0)
+          close_row<T, VEC, L, WM>(a, Y, bw, s_part, part_idx, do_score, bl, lc, gb, eta, st, sc, p + q, lifted);
+        open_row<T, L, VEC, WM>(st, wb.sl[q] & 0x7FFFFFFF, wb.xr[q], wq, lifted, p + q);
       } else {
-        take_slot<T, VEC, L, WM>(st, wb.xr[q], wq, do_score, a.lifted);
+        take_slot<T, VEC, L, WM>(st, wb.xr[q], wq, do_score, lifted);
       }
     }
   }
@@ -740,7 +746,8 @@ __device__ __forceinline__ void complete_step(const StepArgs& a, long long t, bo
 #define DECO_STEP_WAVES_PER_EU 3
 #endif
 
-template <typename T, int VEC, int L, int WM>
+// LF: the lifted flag known when compiling (0 or 1, packed rows) or -1 (read from a).
+template <typename T, int VEC, int L, int WM, int LF>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(DECO_STEP_WAVES_PER_EU)))
 void k_step(StepArgs a) {
   constexpr int W = Tune<T, L, VEC>::W;
@@ -771,6 +778,7 @@ void k_step(StepArgs a) {
   const int lc = tid & (Wc - 1);
   const int sgi = tid >> wl;
 
+  const int lifted = LF >= 0 ? LF : a.lifted;
   const long long t = a.ctrl->t;
   const bool do_score = a.force_score || (t % a.ctrl->score_every) == 0;
   const long long cp = a.ctrl->cpend;  // step completed by the extra workgroups of this launch
@@ -880,6 +888,7 @@ void k_step(StepArgs a) {
       st.dsum = 0.0f;
       st.head = false;
       st.lazy = false;
+      st.open = c0;
       reset_counters(st);
       if (c0 < c1) {
         int lo = 0, hi = R;  // first row starting after c0
@@ -892,6 +901,7 @@ void k_step(StepArgs a) {
           st.row = x + lo - 1;
           st.head = true;
           st.lazy = true;
+          st.open = c0;
 #pragma unroll
           for (int i = 0; i < L; ++i) {
             st.xv[i] = IO::load_raw(X + (size_t)st.row * a.C + (size_t)i * a.B + bl);
@@ -905,7 +915,7 @@ void k_step(StepArgs a) {
         // are waited for one by one)
         for (int p = c0; p < c1; p += W)
           gather_window<T, VEC, L, WM, true>(a, X, Y, bw, s_slot, s_sw, s_acc, part_idx, p, c1, bl, lc, gb, eta, st,
-                                             sc, do_score);
+                                             sc, do_score, lifted);
       } else {
         // lifted rows: the next window's gathers are in flight during each fold
         constexpr int PW = PipeTune<T, L, VEC>::W;
@@ -915,26 +925,27 @@ void k_step(StepArgs a) {
         for (int p = c0; p < c1; p += 2 * PW) {
           load_window<T, VEC, L, PW>(a, X, s_slot, p + PW, c1, bl, wb);
           fold_window<T, VEC, L, WM, PW>(a, Y, bw, s_sw, s_acc, part_idx, p, c1, bl, lc, gb, eta, wa, st, sc,
-                                         do_score);
+                                         do_score, lifted);
           load_window<T, VEC, L, PW>(a, X, s_slot, p + 2 * PW, c1, bl, wa);
           fold_window<T, VEC, L, WM, PW>(a, Y, bw, s_sw, s_acc, part_idx, p + PW, c1, bl, lc, gb, eta, wb, st, sc,
-                                         do_score);
+                                         do_score, lifted);
         }
       }
       bool tail = false;
       int next = 0;
       if (st.row >= 0) {
         if (st.head) {
-          close_row<T, VEC, L, WM>(a, Y, bw, s_acc, part_idx, do_score, bl, lc, gb, eta, st, sc);
+          close_row<T, VEC, L, WM>(a, Y, bw, s_acc, part_idx, do_score, bl, lc, gb, eta, st, sc, c1, lifted);
         } else {
           const int i = st.row - x;
           next = s_rp[i + 1];
           if (next <= c1) {
-            close_row<T, VEC, L, WM>(a, Y, bw, s_acc, part_idx, do_score, bl, lc, gb, eta, st, sc);
+            close_row<T, VEC, L, WM>(a, Y, bw, s_acc, part_idx, do_score, bl, lc, gb, eta, st, sc, c1, lifted);
           } else {
             // the row continues in later shares: score this share now, update after them
             tail = true;
-            if (do_score) close_score(st, sc, a.lifted);
+            if constexpr (WM == kUnitW) st.wsum = c1 - st.open;
+            if (do_score) close_score(st, sc, lifted);
             if (WM == kUnitW) st.dsum = (float)(next - s_rp[i] - 1);
           }
         }
@@ -979,19 +990,20 @@ void k_step(StepArgs a) {
           if (WM != kUnitW) s_sw[k] = a.sw[sb + k];
         }
         __syncthreads();
-        st.zm = side_mask_raw<T, VEC, L>(st.xv, a.lifted);
+        st.zm = side_mask_raw<T, VEC, L>(st.xv, lifted);
         const int c0 = (E * sgi) >> nsl;
         const int c1 = (E * (sgi + 1)) >> nsl;
         for (int p = c0; p < c1; p += W)
           gather_window<T, VEC, L, WM, false>(a, X, Y, bw, s_slot, s_sw, s_acc, 0, p, c1, bl, lc, gb, eta, st, sc,
-                                              do_score);
+                                              do_score, lifted);
         // score of this chunk's share; the 16-bit partials hold at most one chunk
         if (do_score) {
-          close_score(st, sc, a.lifted);
+          if constexpr (WM == kUnitW) st.wsum = c1 - c0;
+          close_score(st, sc, lifted);
           flush();
         }
       }
-      st.zm = side_mask_raw<T, VEC, L>(st.xv, a.lifted);
+      st.zm = side_mask_raw<T, VEC, L>(st.xv, lifted);
       // teams of one wave first (butterfly), then the waves in order through LDS
 #pragma unroll
       for (int i = 0; i < L; ++i)
@@ -1357,14 +1369,23 @@ __global__ void k_dense_validate(const uint16_t* W, int n, float* dw, int* flags
 template <typename T, int VEC, int LL>
 hipError_t step_dispatch(const StepArgs& a, int wmode, int grid, hipStream_t s) {
   const dim3 g(grid + a.nextra), b(kThreads);
-  if (wmode == kUnitW)
-    hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW>), g, b, 0, s, a);
-  else if (wmode == kPm1W)
-    hipLaunchKernelGGL((k_step<T, VEC, LL, kPm1W>), g, b, 0, s, a);
-  else if (wmode == kIntW)
-    hipLaunchKernelGGL((k_step<T, VEC, LL, kIntW>), g, b, 0, s, a);
-  else
-    hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW>), g, b, 0, s, a);
+  // packed rows take the lifted flag as a compile-time constant (no per-value flip)
+  constexpr bool kPackU = Packed<T, LL, VEC, kUnitW>::value, kPackP = Packed<T, LL, VEC, kPm1W>::value;
+  if (wmode == kUnitW) {
+    if (kPackU && a.lifted)
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW, kPackU ? 1 : -1>), g, b, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW, kPackU ? 0 : -1>), g, b, 0, s, a);
+  } else if (wmode == kPm1W) {
+    if (kPackP && a.lifted)
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kPm1W, kPackP ? 1 : -1>), g, b, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kPm1W, kPackP ? 0 : -1>), g, b, 0, s, a);
+  } else if (wmode == kIntW) {
+    hipLaunchKernelGGL((k_step<T, VEC, LL, kIntW, -1>), g, b, 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW, -1>), g, b, 0, s, a);
+  }
   return hipGetLastError();
 }
 
