@@ -143,9 +143,12 @@ deco_status deco_set_eta(deco_handle *h, const float *eta_host);
 /* Run 'steps' projected gradient steps (eq. (7) / the lifted update) on the handle's
  * stream, asynchronously, with no host synchronisation. Step t scores the iterate X_t it
  * reads (when t % score_every == 0) and folds it into the running best; X_steps is left
- * unscored until the next step or deco_round_score. With use_graph != 0 the launches are
+ * unscored until the next step or deco_round_score. Inside the call a step's cuts are
+ * completed by the following launch; the call ends with a drain (two small kernels), so
+ * the cuts, trace, running best and best bits of every step it ran are complete on the
+ * stream when the next operation on it starts. With use_graph != 0 the step launches are
  * captured once per step count into a hipGraph and replayed (the stream must not be the
- * NULL stream then). */
+ * NULL stream then); the drain runs after the replay. */
 deco_status deco_step(deco_handle *h, int32_t steps, int32_t use_graph);
 
 /* Round and score the current iterate exactly (eq. (5) or the lifted rule, then eq. (1)),
