@@ -391,3 +391,44 @@ def test_workspace_too_small():
     st = deco.lib().deco_init(ct.byref(h), ct.byref(G.struct), ct.byref(p), X.data_ptr(), ws.data_ptr(),
                               nb.value - 1, None)
     assert st == deco.E_NOMEM and not h.value
+
+
+@pytest.mark.parametrize("lifted", [False, True])
+def test_step_calls_split_and_replayed_agree_bitwise(lifted):
+    """A step's cuts are completed by the next launch and every call ends with a drain: the
+    same 12 steps (scored every step) taken as one call, as 12 calls and as two graph replays
+    give the same iterates, traces, running best (cuts, steps, bits) and round score; reading
+    the best twice gives the same result."""
+    gs = [synth.barabasi_albert(700, 3, 11), synth.erdos_renyi(300, 0.05, 12)]
+    g = synth.block_diagonal(gs)
+    G = deco.Graph(g)
+    B, l = 32, (2 if lifted else 1)
+    x0 = torch.from_numpy(synth.uniform_batch(g.n, l * B, 4)).to(torch.bfloat16).cuda()
+    runs = []
+    for mode in ("one", "each", "graph"):
+        h = deco.Handle(G, B=B, l=l, lifted=lifted, x_dtype=deco.BF16, eta=0.05, seed=3)
+        h.start(deco.INIT_USER, x0=x0)
+        tr = h.set_trace(16)
+        if mode == "one":
+            h.step(12)
+        elif mode == "each":
+            for _ in range(12):
+                h.step(1)
+        else:
+            h.step(6, use_graph=True)
+            h.step(6, use_graph=True)
+        cut_T, bits_T = h.round_score()
+        best = h.best()
+        again = h.best()
+        for u, v in zip(best, again):
+            assert np.array_equal(u, v)
+        runs.append((to_np(h.read_x()), tr.cpu().numpy(), best, to_np(cut_T), to_np(bits_T)))
+        h.destroy()
+    ref = runs[0]
+    assert np.array_equal(ref[1][12], oracle_cuts(g, ref[0].astype(np.float64), B, l, lifted)[0])
+    for other in runs[1:]:
+        assert np.array_equal(ref[0], other[0])
+        assert np.array_equal(ref[1][:13], other[1][:13])
+        for u, v in zip(ref[2], other[2]):
+            assert np.array_equal(u, v)
+        assert np.array_equal(ref[3], other[3]) and np.array_equal(ref[4], other[4])
