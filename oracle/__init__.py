@@ -142,6 +142,17 @@ def step(g, X, eta, form=CUT_FORM) -> np.ndarray:
     return Xn
 
 
+def step_momentum(g, X, V, eta, mu, form=CUT_FORM):
+    """One projected step with heavy-ball momentum (Sec. 4.2 says PGA runs with momentum in
+    practice and Sec. 5 uses 0.9, without the update rule; the reading taken is the
+    heavy-ball form): V' = mu V + G(X), X' = Proj(X + eta V'). Returns (X', V')."""
+    G = grad(g, X, form)
+    Vn = float(mu) * np.asarray(V, dtype=np.float64) + G
+    e = _eta_cols(eta, Vn.shape[1])
+    Xn = np.clip(np.asarray(X, dtype=np.float64) + e[None, :] * Vn, -1.0, 1.0)
+    return Xn, Vn
+
+
 def grad(g, X, form=CUT_FORM) -> np.ndarray:
     g = _g(g)
     X = np.ascontiguousarray(X, dtype=np.float64)

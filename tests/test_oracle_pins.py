@@ -461,3 +461,32 @@ def test_bf16_rounding_emulation():
     assert y[3] == -2.5
     bits = y.view(np.uint32)
     assert np.all(bits & 0xFFFF == 0)
+
+
+def test_momentum_step_pins():
+    """Heavy-ball momentum step (reading of Sec. 4.2 / Sec. 5): mu = 0 is the plain step; a
+    single edge worked by hand; two steps from V = 0 unroll to mu G0 + G1; the box holds."""
+    import oracle
+    from paper_2509_18612_amd import synth
+    g = synth.erdos_renyi(60, 0.1, 4)
+    rng = np.random.default_rng(8)
+    X = rng.uniform(-1, 1, (g.n, 5))
+    V = rng.uniform(-2, 2, (g.n, 5))
+    Xm, Vm = oracle.step_momentum(g, X, V, 0.07, 0.0)
+    assert np.allclose(Xm, oracle.step(g, X, 0.07), rtol=0, atol=1e-15)
+    # one edge 0-1, cut form G = -1/2 W X: G0 = -x1/2, G1 = -x0/2 (worked by hand)
+    e = synth.from_edges(2, np.array([0]), np.array([1]))
+    Xe = np.array([[0.2], [-0.4]])
+    Ve = np.array([[0.1], [-0.3]])
+    Xn, Vn = oracle.step_momentum(e, Xe, Ve, 0.5, 0.9)
+    assert np.allclose(Vn, [[0.29], [-0.37]], rtol=0, atol=1e-15)   # 0.09 + 0.2, -0.27 - 0.1
+    assert np.allclose(Xn, [[0.345], [-0.585]], rtol=0, atol=1e-15)  # 0.2 + 0.145, -0.4 - 0.185
+    # two steps from V = 0: V2 = mu G(X0) + G(X1)
+    X0 = rng.uniform(-0.3, 0.3, (g.n, 3))
+    X1, V1 = oracle.step_momentum(g, X0, np.zeros_like(X0), 0.01, 0.9)
+    X2, V2 = oracle.step_momentum(g, X1, V1, 0.01, 0.9)
+    assert np.allclose(V2, 0.9 * oracle.grad(g, X0) + oracle.grad(g, X1), rtol=0, atol=1e-13)
+    assert np.allclose(X2, np.clip(X1 + 0.01 * V2, -1, 1), rtol=0, atol=1e-15)
+    # a large step lands on the box
+    Xb, _ = oracle.step_momentum(g, X, V, 50.0, 0.9)
+    assert np.all(np.abs(Xb) <= 1.0) and np.any(np.abs(Xb) == 1.0)
