@@ -140,6 +140,14 @@ deco_status deco_start(deco_handle *h, const deco_start_args *a);
 /* Set a per-initialisation step size (host eta[B]); replaces deco_params.eta. */
 deco_status deco_set_eta(deco_handle *h, const float *eta_host);
 
+/* Heavy-ball momentum for the following steps (Sec. 4.2 runs PGA with momentum, Sec. 5 with
+ * coefficient 0.9; the paper gives no update rule, this is the heavy-ball reading):
+ * V' = mu V + G, X' = Proj(X + eta V'). velocity: device float32 n x (l*B), the layout of X,
+ * caller-owned, zeroed by this call and by every deco_start (a start begins at rest); the
+ * library reads and writes it at every step. NULL turns momentum off. Sparse handles only
+ * (DECO_E_UNSUPPORTED on dense ones); DECO_E_NONFINITE for a non-finite mu. Synchronous. */
+deco_status deco_set_momentum(deco_handle *h, float mu, float *velocity);
+
 /* Run 'steps' projected gradient steps (eq. (7) / the lifted update) on the handle's
  * stream, asynchronously, with no host synchronisation. Step t scores the iterate X_t it
  * reads (when t % score_every == 0) and folds it into the running best; X_steps is left

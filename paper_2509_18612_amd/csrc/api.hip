@@ -620,6 +620,8 @@ deco_status deco_start(deco_handle* h, const deco_start_args* s) {
     HIP_TRY(h, launch_init(ia, h->stream));
   }
   if (h->dense) HIP_TRY(h, launch_dense_transpose(h->X, h->args.xT[0], h->n, h->C, h->stream));
+  if (h->args.vel)  // a new start begins at rest
+    HIP_TRY(h, hipMemsetAsync(h->args.vel, 0, sizeof(float) * (size_t)h->n * h->C, h->stream));
   HIP_TRY(h, launch_reset(h->args, h->args.acc, 2LL * h->R * h->G * h->p.B, h->p.score_every, h->stream));
   h->t_host = 0;
   return DECO_OK;
@@ -632,6 +634,22 @@ deco_status deco_set_eta(deco_handle* h, const float* eta_host) {
     if (!std::isfinite(eta_host[b])) return DECO_E_NONFINITE;
   HIP_TRY(h, hipMemcpyAsync(const_cast<float*>(h->args.eta), eta_host, sizeof(float) * h->p.B,
                             hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return DECO_OK;
+}
+
+deco_status deco_set_momentum(deco_handle* h, float mu, float* velocity) {
+  if (!h) return DECO_E_INVAL;
+  if (h->poisoned) return DECO_E_STATE;
+  if (h->dense) return DECO_E_UNSUPPORTED;
+  if (!std::isfinite(mu)) return DECO_E_NONFINITE;
+  h->args.vel = velocity;
+  h->args.mu = velocity ? mu : 0.0f;
+  // captured step graphs hold the old arguments
+  for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+  h->graphs.clear();
+  if (velocity)
+    HIP_TRY(h, hipMemsetAsync(velocity, 0, sizeof(float) * (size_t)h->n * h->C, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   return DECO_OK;
 }

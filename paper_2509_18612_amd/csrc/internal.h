@@ -62,6 +62,8 @@ struct StepArgs {
   int R, G;
   int nextra;       // lagged mode: workgroups after the work grid that complete step t - 1
                     // (0: immediate mode)
+  float* vel;       // heavy-ball velocity, float32 n x C (same layout as X), or NULL
+  float mu;         // momentum coefficient (with vel)
   double* cur_cut;  // [G][B]
   double* best_cut; // [G][B]
   int* best_step;   // [G][B]

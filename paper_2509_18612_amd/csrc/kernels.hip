@@ -344,20 +344,39 @@ __device__ __forceinline__ void put_part(float* s_part, int idx, const float (&a
 template <typename T, int VEC, int L, int WM>
 __device__ __forceinline__ void finish_row(const StepArgs& a, T* __restrict__ Y, uint8_t* __restrict__ bw,
                                            bool do_score, bool lead, int bl, int lc, int gb,
-                                           const float* __restrict__ eta, const RowState<T, L, VEC, WM>& st) {
+                                           const float* __restrict__ eta, const RowState<T, L, VEC, WM>& st,
+                                           float* vel) {
   if (a.do_update && lead) {
 #pragma unroll
     for (int i = 0; i < L; ++i) {
       float xv[VEC], y[VEC];
       VecIO<T, VEC>::unpack(st.xv[i], xv);
+      if (vel == nullptr) {
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        float v;
-        if (a.cD != 0.0f)
-          v = fmaf(eta[e], fmaf(a.cD * st.dsum, xv[e], a.cW * st.acc[i][e]), xv[e]);
-        else
-          v = fmaf(eta[256 + e], st.acc[i][e], xv[e]);
-        y[e] = __builtin_amdgcn_fmed3f(v, -1.0f, 1.0f);
+        for (int e = 0; e < VEC; ++e) {
+          float v;
+          if (a.cD != 0.0f)
+            v = fmaf(eta[e], fmaf(a.cD * st.dsum, xv[e], a.cW * st.acc[i][e]), xv[e]);
+          else
+            v = fmaf(eta[256 + e], st.acc[i][e], xv[e]);
+          y[e] = __builtin_amdgcn_fmed3f(v, -1.0f, 1.0f);
+        }
+      } else {
+        // heavy-ball momentum: V' = mu V + G, X' = clip(X + eta V'), V in float32 beside X
+        float* vp = vel + (size_t)st.row * a.C + (size_t)i * a.B + bl;
+        float vo[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) vo[e] = vp[e];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const float g =
+              a.cD != 0.0f ? fmaf(a.cD * st.dsum, xv[e], a.cW * st.acc[i][e]) : a.cW * st.acc[i][e];
+          const float vn = fmaf(a.mu, vo[e], g);
+          vo[e] = vn;
+          y[e] = __builtin_amdgcn_fmed3f(fmaf(eta[e], vn, xv[e]), -1.0f, 1.0f);
+        }
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) vp[e] = vo[e];
       }
       VecIO<T, VEC>::store(Y + (size_t)st.row * a.C + (size_t)i * a.B + bl, y);
     }
@@ -377,14 +396,14 @@ template <typename T, int VEC, int L, int WM>
 __device__ __forceinline__ void close_row(const StepArgs& a, T* __restrict__ Y, uint8_t* __restrict__ bw,
                                           float* s_part, int part_idx, bool do_score, int bl, int lc, int gb,
                                           const float* __restrict__ eta, RowState<T, L, VEC, WM>& st,
-                                          ScoreAcc<T, L, VEC, WM>& sc, int pos, int lifted) {
+                                          ScoreAcc<T, L, VEC, WM>& sc, int pos, int lifted, float* vel) {
   if constexpr (WM == kUnitW) st.wsum = pos - st.open;  // neighbours taken in this share
   if (WM == kUnitW && !st.head) st.dsum = (float)st.wsum;  // degree: the row's slots were all taken here
   if (do_score) close_score(st, sc, lifted);
   if (st.head)
     put_part<L, VEC>(s_part, part_idx, st.acc);
   else
-    finish_row<T, VEC, L, WM>(a, Y, bw, do_score, true, bl, lc, gb, eta, st);
+    finish_row<T, VEC, L, WM>(a, Y, bw, do_score, true, bl, lc, gb, eta, st, vel);
 }
 
 // Opens the row whose own slot was just read.
@@ -549,7 +568,7 @@ __device__ __forceinline__ void gather_window(const StepArgs& a, const T* __rest
                                               uint8_t* __restrict__ bw, const int* s_slot, const float* s_sw,
                                               float* s_part, int part_idx, int p, int pe, int bl, int lc, int gb,
                                               const float* __restrict__ eta, RowState<T, L, VEC, WM>& st,
-                                              ScoreAcc<T, L, VEC, WM>& sc, bool do_score, int lifted) {
+                                              ScoreAcc<T, L, VEC, WM>& sc, bool do_score, int lifted, float* vel) {
   using IO = VecIO<T, VEC>;
   constexpr int W = Tune<T, L, VEC>::W;
   const size_t B = (size_t)a.B;
@@ -580,7 +599,7 @@ __device__ __forceinline__ void gather_window(const StepArgs& a, const T* __rest
       const float wq = WM == kUnitW ? 1.0f : s_sw[p + q];
       if (SELF && sl[q] < 0) {
         if (st.row >= 0)
-          close_row<T, VEC, L, WM>(a, Y, bw, s_part, part_idx, do_score, bl, lc, gb, eta, st, sc, p + q, lifted);
+          close_row<T, VEC, L, WM>(a, Y, bw, s_part, part_idx, do_score, bl, lc, gb, eta, st, sc, p + q, lifted, vel);
         open_row<T, L, VEC, WM>(st, sl[q] & 0x7FFFFFFF, xr[q], wq, lifted, p + q);
       } else {
         take_slot<T, VEC, L, WM>(st, xr[q], wq, do_score, lifted);
@@ -631,7 +650,7 @@ __device__ __forceinline__ void fold_window(const StepArgs& a, T* __restrict__ Y
                                             const float* s_sw, float* s_part, int part_idx, int p, int pe, int bl,
                                             int lc, int gb, const float* __restrict__ eta,
                                             const WinBuf<T, VEC, L, PW>& wb, RowState<T, L, VEC, WM>& st,
-                                            ScoreAcc<T, L, VEC, WM>& sc, bool do_score, int lifted) {
+                                            ScoreAcc<T, L, VEC, WM>& sc, bool do_score, int lifted, float* vel) {
   if (st.lazy) {
     st.zm = side_mask_raw<T, VEC, L>(st.xv, lifted);
     st.lazy = false;
@@ -643,7 +662,7 @@ __device__ __forceinline__ void fold_window(const StepArgs& a, T* __restrict__ Y
       const float wq = WM == kUnitW ? 1.0f : s_sw[p + q];
       if (wb.sl[q] < 0) {
         if (st.row >= 0)
-          close_row<T, VEC, L, WM>(a, Y, bw, s_part, part_idx, do_score, bl, lc, gb, eta, st, sc, p + q, lifted);
+          close_row<T, VEC, L, WM>(a, Y, bw, s_part, part_idx, do_score, bl, lc, gb, eta, st, sc, p + q, lifted, vel);
         open_row<T, L, VEC, WM>(st, wb.sl[q] & 0x7FFFFFFF, wb.xr[q], wq, lifted, p + q);
       } else {
         take_slot<T, VEC, L, WM>(st, wb.xr[q], wq, do_score, lifted);
@@ -747,7 +766,8 @@ __device__ __forceinline__ void complete_step(const StepArgs& a, long long t, bo
 #endif
 
 // LF: the lifted flag known when compiling (0 or 1, packed rows) or -1 (read from a).
-template <typename T, int VEC, int L, int WM, int LF>
+// MOM: heavy-ball momentum (velocity in a.vel); without it the update code has no velocity path.
+template <typename T, int VEC, int L, int WM, int LF, bool MOM>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(DECO_STEP_WAVES_PER_EU)))
 void k_step(StepArgs a) {
   constexpr int W = Tune<T, L, VEC>::W;
@@ -779,6 +799,7 @@ void k_step(StepArgs a) {
   const int sgi = tid >> wl;
 
   const int lifted = LF >= 0 ? LF : a.lifted;
+  float* const vel = MOM ? a.vel : nullptr;
   const long long t = a.ctrl->t;
   const bool do_score = a.force_score || (t % a.ctrl->score_every) == 0;
   const long long cp = a.ctrl->cpend;  // step completed by the extra workgroups of this launch
@@ -915,7 +936,7 @@ void k_step(StepArgs a) {
         // are waited for one by one)
         for (int p = c0; p < c1; p += W)
           gather_window<T, VEC, L, WM, true>(a, X, Y, bw, s_slot, s_sw, s_acc, part_idx, p, c1, bl, lc, gb, eta, st,
-                                             sc, do_score, lifted);
+                                             sc, do_score, lifted, vel);
       } else {
         // lifted rows: the next window's gathers are in flight during each fold
         constexpr int PW = PipeTune<T, L, VEC>::W;
@@ -925,22 +946,22 @@ void k_step(StepArgs a) {
         for (int p = c0; p < c1; p += 2 * PW) {
           load_window<T, VEC, L, PW>(a, X, s_slot, p + PW, c1, bl, wb);
           fold_window<T, VEC, L, WM, PW>(a, Y, bw, s_sw, s_acc, part_idx, p, c1, bl, lc, gb, eta, wa, st, sc,
-                                         do_score, lifted);
+                                         do_score, lifted, vel);
           load_window<T, VEC, L, PW>(a, X, s_slot, p + 2 * PW, c1, bl, wa);
           fold_window<T, VEC, L, WM, PW>(a, Y, bw, s_sw, s_acc, part_idx, p + PW, c1, bl, lc, gb, eta, wb, st, sc,
-                                         do_score, lifted);
+                                         do_score, lifted, vel);
         }
       }
       bool tail = false;
       int next = 0;
       if (st.row >= 0) {
         if (st.head) {
-          close_row<T, VEC, L, WM>(a, Y, bw, s_acc, part_idx, do_score, bl, lc, gb, eta, st, sc, c1, lifted);
+          close_row<T, VEC, L, WM>(a, Y, bw, s_acc, part_idx, do_score, bl, lc, gb, eta, st, sc, c1, lifted, vel);
         } else {
           const int i = st.row - x;
           next = s_rp[i + 1];
           if (next <= c1) {
-            close_row<T, VEC, L, WM>(a, Y, bw, s_acc, part_idx, do_score, bl, lc, gb, eta, st, sc, c1, lifted);
+            close_row<T, VEC, L, WM>(a, Y, bw, s_acc, part_idx, do_score, bl, lc, gb, eta, st, sc, c1, lifted, vel);
           } else {
             // the row continues in later shares: score this share now, update after them
             tail = true;
@@ -963,7 +984,7 @@ void k_step(StepArgs a) {
               for (int e = 0; e < VEC; ++e) st.acc[i][e] += s_acc[idx + i * VEC + e];
           }
         }
-        finish_row<T, VEC, L, WM>(a, Y, bw, do_score, true, bl, lc, gb, eta, st);
+        finish_row<T, VEC, L, WM>(a, Y, bw, do_score, true, bl, lc, gb, eta, st, vel);
       }
     } else {
       // one long row: every team takes a contiguous share of each staged chunk of its
@@ -995,7 +1016,7 @@ void k_step(StepArgs a) {
         const int c1 = (E * (sgi + 1)) >> nsl;
         for (int p = c0; p < c1; p += W)
           gather_window<T, VEC, L, WM, false>(a, X, Y, bw, s_slot, s_sw, s_acc, 0, p, c1, bl, lc, gb, eta, st, sc,
-                                              do_score, lifted);
+                                              do_score, lifted, vel);
         // score of this chunk's share; the 16-bit partials hold at most one chunk
         if (do_score) {
           if constexpr (WM == kUnitW) st.wsum = c1 - c0;
@@ -1026,7 +1047,7 @@ void k_step(StepArgs a) {
 #pragma unroll
             for (int e = 0; e < VEC; ++e) st.acc[i][e] += s_acc[q * (L * 256) + (lc * L + i) * VEC + e];
       }
-      finish_row<T, VEC, L, WM>(a, Y, bw, do_score, sgi == 0, bl, lc, gb, eta, st);
+      finish_row<T, VEC, L, WM>(a, Y, bw, do_score, sgi == 0, bl, lc, gb, eta, st, vel);
     }
 
     // fold the previous scored step's improvements into best_bits for this item's rows and
@@ -1369,22 +1390,34 @@ __global__ void k_dense_validate(const uint16_t* W, int n, float* dw, int* flags
 template <typename T, int VEC, int LL>
 hipError_t step_dispatch(const StepArgs& a, int wmode, int grid, hipStream_t s) {
   const dim3 g(grid + a.nextra), b(kThreads);
+  if (a.vel != nullptr) {
+    // momentum kernels read the lifted flag at run time
+    if (wmode == kUnitW)
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW, -1, true>), g, b, 0, s, a);
+    else if (wmode == kPm1W)
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kPm1W, -1, true>), g, b, 0, s, a);
+    else if (wmode == kIntW)
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kIntW, -1, true>), g, b, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW, -1, true>), g, b, 0, s, a);
+    return hipGetLastError();
+  }
   // packed rows take the lifted flag as a compile-time constant (no per-value flip)
   constexpr bool kPackU = Packed<T, LL, VEC, kUnitW>::value, kPackP = Packed<T, LL, VEC, kPm1W>::value;
   if (wmode == kUnitW) {
     if (kPackU && a.lifted)
-      hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW, kPackU ? 1 : -1>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW, kPackU ? 1 : -1, false>), g, b, 0, s, a);
     else
-      hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW, kPackU ? 0 : -1>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW, kPackU ? 0 : -1, false>), g, b, 0, s, a);
   } else if (wmode == kPm1W) {
     if (kPackP && a.lifted)
-      hipLaunchKernelGGL((k_step<T, VEC, LL, kPm1W, kPackP ? 1 : -1>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kPm1W, kPackP ? 1 : -1, false>), g, b, 0, s, a);
     else
-      hipLaunchKernelGGL((k_step<T, VEC, LL, kPm1W, kPackP ? 0 : -1>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kPm1W, kPackP ? 0 : -1, false>), g, b, 0, s, a);
   } else if (wmode == kIntW) {
-    hipLaunchKernelGGL((k_step<T, VEC, LL, kIntW, -1>), g, b, 0, s, a);
+    hipLaunchKernelGGL((k_step<T, VEC, LL, kIntW, -1, false>), g, b, 0, s, a);
   } else {
-    hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW, -1>), g, b, 0, s, a);
+    hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW, -1, false>), g, b, 0, s, a);
   }
   return hipGetLastError();
 }

@@ -65,7 +65,8 @@ class deco_solve_report(ct.Structure):
                 ("l_best", ct.c_int32)]
 
 
-EXPORTS = ["deco_status_string", "deco_workspace_size", "deco_init", "deco_start", "deco_set_eta", "deco_step",
+EXPORTS = ["deco_status_string", "deco_workspace_size", "deco_init", "deco_start", "deco_set_eta",
+           "deco_set_momentum", "deco_step",
            "deco_round_score", "deco_best", "deco_read_x", "deco_set_trace", "deco_current_step",
            "deco_autotune", "deco_schedule_string", "deco_destroy", "deco_solve", "deco_evo_next",
            "deco_philox", "deco_philox_device", "deco_solver_create", "deco_solver_run",
@@ -90,6 +91,7 @@ def lib():
         L.deco_init.argtypes = [ct.POINTER(P), P, P, P, P, ct.c_size_t, P]
         L.deco_start.argtypes = [P, P]
         L.deco_set_eta.argtypes = [P, P]
+        L.deco_set_momentum.argtypes = [P, ct.c_float, P]
         L.deco_step.argtypes = [P, I32, I32]
         L.deco_round_score.argtypes = [P, P, P]
         L.deco_best.argtypes = [P, P, P, P]
@@ -250,6 +252,18 @@ class Handle:
     def set_eta(self, eta):
         e = np.ascontiguousarray(np.broadcast_to(np.asarray(eta, np.float32), (self.B,)), np.float32)
         _check(lib().deco_set_eta(self.h, e.ctypes.data), "deco_set_eta")
+
+    def set_momentum(self, mu: float):
+        """Heavy-ball momentum (deco_set_momentum); the velocity buffer (float32, the shape of
+        X) is allocated here and returned. mu = None turns it off."""
+        torch = self.torch
+        if mu is None:
+            _check(lib().deco_set_momentum(self.h, 0.0, None), "deco_set_momentum")
+            self._vel = None
+            return None
+        self._vel = torch.zeros((self.graph.n, self.C), dtype=torch.float32, device="cuda")
+        _check(lib().deco_set_momentum(self.h, float(mu), self._vel.data_ptr()), "deco_set_momentum")
+        return self._vel
 
     def step(self, steps: int, use_graph: bool = False):
         _check(lib().deco_step(self.h, int(steps), int(bool(use_graph))), "deco_step")

@@ -14,7 +14,7 @@ import pytest
 import oracle
 from paper_2509_18612_amd import deco, synth
 
-from gpu_util import bf16_ulp, oracle_cuts, run_teacher_forced, step_bound, to_np
+from gpu_util import U32, bf16_ulp, oracle_cuts, run_teacher_forced, step_bound, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -432,3 +432,56 @@ def test_step_calls_split_and_replayed_agree_bitwise(lifted):
         for u, v in zip(ref[2], other[2]):
             assert np.array_equal(u, v)
         assert np.array_equal(ref[3], other[3]) and np.array_equal(ref[4], other[4])
+
+
+@pytest.mark.parametrize("dtype,l", [(deco.F32, 1), (deco.BF16, 1), (deco.F32, 2)])
+def test_momentum_teacher_forced_parity(dtype, l):
+    """Heavy-ball momentum (deco_set_momentum): from the GPU's own X_t and V_t, the oracle's
+    momentum step gives X_t+1 and V_t+1 (float32: V within 2e-5 relative, X within the step
+    bound; bfloat16 X within one ulp more); cuts stay exact; a new start begins at rest."""
+    g = synth.barabasi_albert(900, 3, 21)
+    B, mu, eta = 32, 0.9, 0.02
+    G = deco.Graph(g)
+    h = deco.Handle(G, B=B, l=l, lifted=l > 1, x_dtype=dtype, eta=eta, seed=5)
+    vel = h.set_momentum(mu)
+    tdt = torch.float32 if dtype == deco.F32 else torch.bfloat16
+    x0 = torch.from_numpy(synth.uniform_batch(g.n, l * B, 6)).to(tdt).cuda()
+    h.start(deco.INIT_USER, x0=x0)
+    tr = h.set_trace(16)
+    X = to_np(h.read_x()).astype(np.float64)
+    V = vel.cpu().numpy().astype(np.float64)
+    assert not V.any()
+    for t in range(8):
+        h.step(1)
+        Xg = to_np(h.read_x()).astype(np.float64)
+        Vg = vel.cpu().numpy().astype(np.float64)
+        Xw, Vw = oracle.step_momentum(g, X, V, eta, mu)
+        assert np.all(np.abs(Vg - Vw) <= 2e-5 * np.maximum(1.0, np.abs(Vw))), t
+        tol = eta * 2e-5 * np.maximum(1.0, np.abs(Vw)) + 4 * U32
+        if dtype == deco.BF16:
+            emu = oracle.to_bf16(np.clip(X + eta * Vg, -1, 1).astype(np.float32)).astype(np.float64)
+            assert np.all(np.abs(Xg - emu) <= bf16_ulp(emu) + tol), t
+        else:
+            assert np.all(np.abs(Xg - Xw) <= tol), t
+        assert np.array_equal(tr.cpu().numpy()[t], oracle_cuts(g, X, B, l, l > 1)[0])
+        X, V = Xg, Vg
+    h.start(deco.INIT_USER, x0=x0)
+    assert not vel.cpu().numpy().any()
+    h.destroy()
+
+
+def test_momentum_zero_equals_plain_steps():
+    """mu = 0 with a velocity buffer gives the plain steps bit for bit (float32 rows)."""
+    g = synth.erdos_renyi(500, 0.04, 9)
+    G = deco.Graph(g)
+    x0 = torch.from_numpy(synth.uniform_batch(g.n, 16, 3)).cuda()
+    out = []
+    for mu in (None, 0.0):
+        h = deco.Handle(G, B=16, eta=0.1, seed=1)
+        if mu is not None:
+            h.set_momentum(mu)
+        h.start(deco.INIT_USER, x0=x0)
+        h.step(6)
+        out.append(to_np(h.read_x()))
+        h.destroy()
+    assert np.array_equal(out[0], out[1])
