@@ -485,3 +485,33 @@ def test_momentum_zero_equals_plain_steps():
         out.append(to_np(h.read_x()))
         h.destroy()
     assert np.array_equal(out[0], out[1])
+
+
+def test_momentum_with_captured_graphs_and_errors():
+    """Turning momentum on after step graphs were captured re-captures them (the replayed
+    steps use the velocity), turning it off restores plain steps; a non-finite coefficient is
+    rejected before any launch."""
+    g = synth.erdos_renyi(400, 0.05, 13)
+    G = deco.Graph(g)
+    x0 = torch.from_numpy(synth.uniform_batch(g.n, 16, 7)).cuda()
+    ref = deco.Handle(G, B=16, eta=0.05, seed=1)
+    ref.start(deco.INIT_USER, x0=x0)
+    ref.step(4)
+    ref.set_momentum(0.8)
+    ref.step(4)
+    ref.set_momentum(None)
+    ref.step(4)
+    h = deco.Handle(G, B=16, eta=0.05, seed=1)
+    h.start(deco.INIT_USER, x0=x0)
+    h.step(4, use_graph=True)
+    h.set_momentum(0.8)
+    h.step(4, use_graph=True)
+    h.set_momentum(None)
+    h.step(4, use_graph=True)
+    assert np.array_equal(to_np(ref.read_x()), to_np(h.read_x()))
+    for u, v in zip(ref.best(), h.best()):
+        assert np.array_equal(u, v)
+    with pytest.raises(deco.DecoError):
+        h.set_momentum(float("nan"))
+    ref.destroy()
+    h.destroy()
