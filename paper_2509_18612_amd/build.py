@@ -6,7 +6,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "api.hip", "mpnn.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "step_momentum.hip", "api.hip", "mpnn.hip")]
 LIB = os.path.join(HERE, "libdeco.so")
 
 FLAGS = [
@@ -19,15 +19,37 @@ FLAGS = [
 
 
 def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile every source to an object in parallel (one hipcc each), then link."""
+    from concurrent.futures import ThreadPoolExecutor
     tmp = out + f".tmp{os.getpid()}"
-    cmd = ["hipcc", *FLAGS, *[f"-D{d}" for d in defines], "-I", os.path.join(ROOT, "include"), "-o", tmp,
-           *SOURCES]
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
-    if verbose:
-        print(" ".join(cmd))
-    os.replace(tmp, out)
+    objs = [f"{tmp}.{os.path.basename(src)}.o" for src in SOURCES]
+    cflags = [f for f in FLAGS if f != "-shared"]
+
+    def compile_one(src_obj):
+        src, obj = src_obj
+        cmd = ["hipcc", *cflags, *[f"-D{d}" for d in defines], "-I", os.path.join(ROOT, "include"), "-c",
+               "-o", obj, src]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if verbose:
+            print(" ".join(cmd))
+        return res, cmd
+
+    try:
+        with ThreadPoolExecutor(len(SOURCES)) as ex:
+            for res, cmd in ex.map(compile_one, zip(SOURCES, objs)):
+                if res.returncode != 0:
+                    raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + res.stdout + res.stderr)
+        cmd = ["hipcc", *FLAGS, "-o", tmp, *objs]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError("hipcc link failed:\n" + res.stdout + res.stderr)
+        if verbose:
+            print(" ".join(cmd))
+        os.replace(tmp, out)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return out
 
 

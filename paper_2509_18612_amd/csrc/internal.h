@@ -83,6 +83,9 @@ struct StepArgs {
 // Kernel launchers (kernels.hip). dtype: 0 float32, 1 bfloat16. vec: elements per lane
 // per load (native_vec, or 1).
 hipError_t launch_step(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s);
+// The same for handles with a velocity (a.vel != NULL): the kernels with the heavy-ball
+// update (step_momentum.hip).
+hipError_t launch_step_momentum(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s);
 int native_vec(int dtype, int L);
 // Dense path: n % 128 == 0, C % 128 == 0, bfloat16 X and W, unlifted.
 hipError_t launch_dense_step(const StepArgs& a, hipStream_t s);

@@ -1387,10 +1387,13 @@ __global__ void k_dense_validate(const uint16_t* W, int n, float* dw, int* flags
   }
 }
 
-template <typename T, int VEC, int LL>
+// MOM selects the kernels with a velocity path; they are instantiated only in the
+// translation unit of the momentum launcher (step_momentum.hip), so the two halves of the
+// step-kernel family compile in parallel.
+template <typename T, int VEC, int LL, bool MOM>
 hipError_t step_dispatch(const StepArgs& a, int wmode, int grid, hipStream_t s) {
   const dim3 g(grid + a.nextra), b(kThreads);
-  if (a.vel != nullptr) {
+  if constexpr (MOM) {
     // momentum kernels read the lifted flag at run time
     if (wmode == kUnitW)
       hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW, -1, true>), g, b, 0, s, a);
@@ -1401,7 +1404,7 @@ hipError_t step_dispatch(const StepArgs& a, int wmode, int grid, hipStream_t s) 
     else
       hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW, -1, true>), g, b, 0, s, a);
     return hipGetLastError();
-  }
+  } else {
   // packed rows take the lifted flag as a compile-time constant (no per-value flip)
   constexpr bool kPackU = Packed<T, LL, VEC, kUnitW>::value, kPackP = Packed<T, LL, VEC, kPm1W>::value;
   if (wmode == kUnitW) {
@@ -1420,21 +1423,36 @@ hipError_t step_dispatch(const StepArgs& a, int wmode, int grid, hipStream_t s) 
     hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW, -1, false>), g, b, 0, s, a);
   }
   return hipGetLastError();
+  }
 }
 
 // All component counts for float32 and one-element lanes; bfloat16 runs unlifted rows 8 or
 // 4 values per lane and lifted rows (l > 1) 4 values per lane.
-template <typename T, int VEC>
+template <typename T, int VEC, bool MOM>
 hipError_t step_dispatch_l(const StepArgs& a, int wmode, int grid, hipStream_t s) {
   constexpr bool bf_wide = sizeof(T) == 2 && VEC == 8;
-  if (a.L == 1) return step_dispatch<T, VEC, 1>(a, wmode, grid, s);
+  if (a.L == 1) return step_dispatch<T, VEC, 1, MOM>(a, wmode, grid, s);
   if constexpr (!bf_wide) {
     switch (a.L) {
-      case 2: return step_dispatch<T, VEC, 2>(a, wmode, grid, s);
-      case 3: return step_dispatch<T, VEC, 3>(a, wmode, grid, s);
-      case 4: return step_dispatch<T, VEC, 4>(a, wmode, grid, s);
+      case 2: return step_dispatch<T, VEC, 2, MOM>(a, wmode, grid, s);
+      case 3: return step_dispatch<T, VEC, 3, MOM>(a, wmode, grid, s);
+      case 4: return step_dispatch<T, VEC, 4, MOM>(a, wmode, grid, s);
       default: break;
     }
+  }
+  return hipErrorInvalidValue;
+}
+
+template <bool MOM>
+hipError_t launch_step_impl(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s) {
+  const int wmode = a.w == nullptr ? kUnitW : (a.pm1 ? kPm1W : (a.intw ? kIntW : kRealW));
+  if (dtype == 0) {
+    if (vec == 4) return step_dispatch_l<float, 4, MOM>(a, wmode, grid, s);
+    if (vec == 1) return step_dispatch_l<float, 1, MOM>(a, wmode, grid, s);
+  } else {
+    if (vec == 8) return step_dispatch_l<uint16_t, 8, MOM>(a, wmode, grid, s);
+    if (vec == 4) return step_dispatch_l<uint16_t, 4, MOM>(a, wmode, grid, s);
+    if (vec == 1) return step_dispatch_l<uint16_t, 1, MOM>(a, wmode, grid, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1726,6 +1744,7 @@ inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1)
 
 }  // namespace
 
+#ifndef DECO_STEP_MOMENTUM_TU  // the host launchers live in this translation unit only
 int native_vec(int dtype, int L) { return dtype == 0 ? 4 : (L == 1 ? 8 : 4); }
 
 hipError_t launch_dense_transpose(const void* X, void* XT, long long n, int C, hipStream_t s) {
@@ -1747,16 +1766,8 @@ hipError_t launch_dense_validate(const uint16_t* W, int n, float* dw, int* flags
 }
 
 hipError_t launch_step(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s) {
-  const int wmode = a.w == nullptr ? kUnitW : (a.pm1 ? kPm1W : (a.intw ? kIntW : kRealW));
-  if (dtype == 0) {
-    if (vec == 4) return step_dispatch_l<float, 4>(a, wmode, grid, s);
-    if (vec == 1) return step_dispatch_l<float, 1>(a, wmode, grid, s);
-  } else {
-    if (vec == 8) return step_dispatch_l<uint16_t, 8>(a, wmode, grid, s);
-    if (vec == 4) return step_dispatch_l<uint16_t, 4>(a, wmode, grid, s);
-    if (vec == 1) return step_dispatch_l<uint16_t, 1>(a, wmode, grid, s);
-  }
-  return hipErrorInvalidValue;
+  if (a.vel != nullptr) return launch_step_momentum(a, dtype, vec, grid, s);
+  return launch_step_impl<false>(a, dtype, vec, grid, s);
 }
 
 hipError_t launch_validate(long long n, const int* rp, const int* ci, const float* w,
@@ -1840,5 +1851,7 @@ hipError_t launch_philox_test(uint32_t c1, uint32_t c2, uint32_t c3, unsigned lo
                      seed, count, out);
   return hipGetLastError();
 }
+
+#endif  // DECO_STEP_MOMENTUM_TU
 
 }  // namespace deco
