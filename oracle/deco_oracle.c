@@ -413,6 +413,31 @@ int64_t orc_perturb_T(int64_t T0, double eps_u, int64_t Tl, int64_t Tu) {
   return t;
 }
 
+/* Step counts of the population after one evolution round (Sec. 4.3): members ranked as in
+ * orc_evo_next; the kept half is copied in rank order and slot keep + j takes the count of
+ * ranked member j perturbed by orc_perturb_T with eps' = u24 of its own draw (index 2). */
+void orc_evo_next_steps(int64_t K, const double *fitness, const int32_t *T, int64_t Tl, int64_t Tu,
+                        uint64_t seed, uint32_t round, int32_t *T_out) {
+  int64_t *rank = (int64_t *)malloc(sizeof(int64_t) * (size_t)K);
+  for (int64_t i = 0; i < K; i++) rank[i] = i;
+  for (int64_t i = 1; i < K; i++) {
+    int64_t x = rank[i], j = i - 1;
+    while (j >= 0 && fitness[rank[j]] < fitness[x]) {
+      rank[j + 1] = rank[j];
+      j--;
+    }
+    rank[j + 1] = x;
+  }
+  int64_t keep = K / 2;
+  for (int64_t i = 0; i < keep; i++) T_out[i] = T[rank[i]];
+  uint32_t r[4];
+  for (int64_t i = keep; i < K; i++) {
+    draw(seed, round, (uint32_t)i, P_EVO, 2, r);
+    T_out[i] = (int32_t)orc_perturb_T(T[rank[i - keep]], u24(r[0]), Tl, Tu);
+  }
+  free(rank);
+}
+
 /* ------------------------------------------------------------------------------------
  * One batch of pQUCO (Alg. 1) or pLUCO (Alg. 2): T steps from X (updated in place), every
  * iterate t = 0..T scored (score_every = 1) and the per-initialisation best kept.

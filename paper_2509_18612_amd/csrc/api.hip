@@ -1023,6 +1023,27 @@ deco_status deco_evo_next(int32_t K, const double* fitness, const double* eq, co
   return DECO_OK;
 }
 
+deco_status deco_evo_next_steps(int32_t K, const double* fitness, const int32_t* T, int32_t T_lo, int32_t T_hi,
+                                uint64_t seed, uint32_t round, int32_t* T_out) {
+  if (K < 1 || !fitness || !T || !T_out || T_lo < 1 || T_lo > T_hi) return DECO_E_INVAL;
+  std::vector<int> order(K);
+  for (int i = 0; i < K; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return fitness[a] > fitness[b]; });
+  const int keep = K / 2;
+  std::vector<int32_t> out(K);
+  for (int i = 0; i < keep; ++i) out[i] = T[order[i]];
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  for (int i = keep; i < K; ++i) {
+    uint32_t c[4] = {round, (uint32_t)i, kSearch, 2u};
+    philox4x32_10(c, k0, k1);
+    const double eps = (double)(c[0] >> 8) * (1.0 / 16777216.0);  // eps' ~ U(0, 1)
+    const double t = std::floor((double)T[order[i - keep]] * (1.0 + 0.2 * (2.0 * eps - 1.0)));
+    out[i] = (int32_t)std::min<double>(T_hi, std::max<double>(T_lo, t));
+  }
+  for (int i = 0; i < K; ++i) T_out[i] = out[i];
+  return DECO_OK;
+}
+
 }  // extern "C"
 
 struct deco_solver {
@@ -1037,6 +1058,7 @@ struct deco_solver {
   long long n = 0;
   std::vector<double> eq, el, gbest, fit, fitg, bc, target;
   std::vector<int32_t> lk, lact;
+  std::vector<int32_t> tq;  // unlifted steps per member (searched when p.T_min > 0)
   std::vector<uint8_t> best_z, zmean, bits;
   std::vector<float> eta;
   std::vector<int> goff;
@@ -1097,7 +1119,8 @@ deco_status deco_solver_create(deco_solver** out, const deco_graph* g, const dec
   if (st) return st;
   if (!sp) return DECO_E_INVAL;
   if (sp->K < 1 || sp->B < 1 || sp->B % sp->K != 0 || sp->l_max < 1 || sp->l_max > 4 || sp->T_q < 0 ||
-      sp->T_l < 0 || sp->evo_rounds < 0 || !(sp->scale > 0.0) || !(sp->sigma2 >= 0.0))
+      sp->T_l < 0 || sp->evo_rounds < 0 || !(sp->scale > 0.0) || !(sp->sigma2 >= 0.0) || sp->T_min < 0 ||
+      (sp->T_min > 0 && sp->T_min > sp->T_q))
     return DECO_E_INVAL;
   if (sp->init_kind != DECO_INIT_IDI && sp->init_kind != DECO_INIT_DUI && sp->init_kind != DECO_INIT_UNIFORM)
     return DECO_E_INVAL;
@@ -1162,10 +1185,18 @@ deco_status deco_solver_create(deco_solver** out, const deco_graph* g, const dec
   v->eq.resize(K);
   v->el.resize(K);
   v->lk.resize(K);
+  v->tq.resize(K);
   for (int k = 0; k < K; ++k) {
     v->eq[k] = sp->eq0 ? sp->eq0[k] : -1.0;
     v->el[k] = sp->el0 ? sp->el0[k] : -3.0;
     v->lk[k] = std::min(v->lmax, std::max(1, sp->l0 ? sp->l0[k] : 2));
+    v->tq[k] = sp->T_q;
+    if (sp->T_min > 0) {
+      // T_k ~ U{T_min, T_q} (Sec. 4.3), Philox counter (0xFFFFFFFF, k, 6, 3)
+      uint32_t c[4] = {0xFFFFFFFFu, (uint32_t)k, kSearch, 3u};
+      philox4x32_10(c, (uint32_t)sp->seed, (uint32_t)(sp->seed >> 32));
+      v->tq[k] = sp->T_min + (int32_t)(c[0] % (uint32_t)(sp->T_q - sp->T_min + 1));
+    }
   }
   if (sp->target_cut) v->target.assign(sp->target_cut, sp->target_cut + v->G);
   v->bc.resize((size_t)v->G * v->B);
@@ -1213,11 +1244,33 @@ deco_status deco_solver_run(deco_solver* v, int32_t rounds, double* best_cut, ui
     sa.beta = sp.beta;
     sa.batch = v->batch++;
     if ((st = deco_start(v->hq, &sa))) return st;
-    if ((st = deco_step(v->hq, sp.T_q, sp.use_graph))) return st;
+    // members step T_k times: the batch runs in segments ending at the distinct T_k, and a
+    // member whose count is reached keeps its columns still with a step of 0 (the
+    // projection leaves an iterate inside the box unchanged)
+    int tmax = 0;
+    {
+      std::vector<int32_t> ends(v->tq);
+      std::sort(ends.begin(), ends.end());
+      ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
+      int done = 0;
+      for (int32_t e : ends) {
+        if (e > done && (st = deco_step(v->hq, e - done, sp.use_graph))) return st;
+        done = std::max(done, (int)e);
+        if (e == ends.back()) break;
+        bool changed = false;
+        for (int b = 0; b < B; ++b)
+          if (v->tq[b / v->per] == e && v->eta[b] != 0.0f) {
+            v->eta[b] = 0.0f;
+            changed = true;
+          }
+        if (changed && (st = deco_set_eta(v->hq, v->eta.data()))) return st;
+      }
+      tmax = done;
+    }
     if ((st = deco_round_score(v->hq, nullptr, nullptr))) return st;
     if ((st = absorb(v, v->hq))) return st;
-    v->steps_done += sp.T_q;
-    v->eu += (double)v->g.nnz * B * sp.T_q;
+    v->steps_done += tmax;
+    v->eu += (double)v->g.nnz * B * tmax;
     // 2. lift its best vector (Alg. 3 step 2) and run the lifted batch (Alg. 2); member k
     //    keeps lk[k] of the lmax components and steps with 10^el[k]; 3. project back
     for (int b = 0; b < B; ++b) {
@@ -1249,6 +1302,13 @@ deco_status deco_solver_run(deco_solver* v, int32_t rounds, double* best_cut, ui
       if ((st = deco_evo_next(K, v->fit.data(), v->eq.data(), v->el.data(), v->lk.data(), -4.0, -1.0, v->lmax,
                               sp.seed, (uint32_t)r, q.data(), m.data(), ll.data())))
         return st;
+      if (sp.T_min > 0) {
+        std::vector<int32_t> tt(K);
+        if ((st = deco_evo_next_steps(K, v->fit.data(), v->tq.data(), sp.T_min, sp.T_q, sp.seed, (uint32_t)r,
+                                      tt.data())))
+          return st;
+        v->tq = tt;
+      }
       v->eq = q;
       v->el = m;
       v->lk = ll;
@@ -1257,6 +1317,7 @@ deco_status deco_solver_run(deco_solver* v, int32_t rounds, double* best_cut, ui
           v->eq[k] = v->eq[0];
           v->el[k] = v->el[0];
           v->lk[k] = v->lk[0];
+          v->tq[k] = v->tq[0];
         }
     }
     v->round++;
@@ -1280,6 +1341,7 @@ deco_status deco_solver_run(deco_solver* v, int32_t rounds, double* best_cut, ui
     report->eq_best = v->eq[0];
     report->el_best = v->el[0];
     report->l_best = v->lk[0];
+    report->T_best = v->tq[0];
   }
   return DECO_OK;
 }

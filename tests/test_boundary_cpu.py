@@ -62,6 +62,23 @@ def test_evolution_step_matches_oracle_exactly(seed):
             assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("seed", [0, 7, 98765])
+def test_step_count_evolution_matches_oracle_exactly(seed):
+    rng = np.random.default_rng(seed)
+    for rnd in range(5):
+        K = 6
+        fit = rng.integers(0, 4, K).astype(float)  # ties on purpose
+        T = rng.integers(3000, 10001, K).astype(np.int32)
+        a = deco.evo_next_steps(fit, T, 3000, 10000, seed, rnd)
+        b = oracle.evo_next_steps(fit, T, 3000, 10000, seed, rnd)
+        assert np.array_equal(a, b)
+        order = sorted(range(K), key=lambda i: (-fit[i], i))
+        assert np.array_equal(a[:K // 2], T[order[:K // 2]])
+        for j in range(K // 2, K):
+            t0 = T[order[j - K // 2]]
+            assert max(3000, int(np.floor(t0 * 0.8))) <= a[j] <= min(10000, int(np.floor(t0 * 1.2)))
+
+
 def test_workspace_size_and_argument_errors_without_device():
     g = deco.deco_graph(100, 400, 1, 1, None, 1, None)  # fake non-null pointers, never dereferenced
     import ctypes as ct

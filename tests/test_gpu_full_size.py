@@ -228,3 +228,34 @@ def test_rows_beyond_24_bits_use_one_element_lanes():
     x0 = to_np(x0_dev).astype(np.float64)
     assert np.array_equal(tr.cpu().numpy()[0], oracle_cuts(g, x0, 8, 1, False)[0])
     h.destroy()
+
+
+def test_zero_step_keeps_columns_still():
+    """A column with step size 0 keeps its iterate bit for bit while the others move (what the
+    step-count search relies on to stop a member)."""
+    g = synth.barabasi_albert(3000, 3, 4)
+    G = deco.Graph(g)
+    h = deco.Handle(G, B=32, x_dtype=deco.BF16, eta=0.05, seed=2)
+    eta = np.full(32, 0.05, np.float32)
+    eta[8:16] = 0.0
+    h.set_eta(eta)
+    h.start(deco.INIT_IDI, scale=1e4, sigma2=0.8)
+    x0 = to_np(h.read_x())
+    h.step(25, use_graph=True)
+    x1 = to_np(h.read_x())
+    assert np.array_equal(x0[:, 8:16], x1[:, 8:16])
+    assert not np.array_equal(x0[:, :8], x1[:, :8])
+    h.destroy()
+
+
+def test_solve_with_step_count_search():
+    """pDECO with the step-count half of the search (T_k in [T_min, T_q] per member): the
+    returned cut is the exact cut of the returned vector and the final count is in range."""
+    g = synth.barabasi_albert(2000, 3, 6)
+    r = deco.solve(deco.Graph(g), B=32, K=4, l_max=2, rounds=3, evo_rounds=2, T_q=160, T_l=40, x_dtype=deco.BF16,
+                   seed=5, T_min=60)
+    assert r["best_cut"][0] == oracle.cut(g, r["z"])
+    assert 60 <= r["T_best"] <= 160
+    assert 3 * (60 + 40) <= r["steps_done"] <= 3 * (160 + 40)
+    gb, _ = oracle.greedy(g, orders=2, seed=1)
+    assert r["best_cut"][0] > 0.95 * gb
