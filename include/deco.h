@@ -261,6 +261,7 @@ typedef struct deco_solve_params {
   int32_t T_min;        /* > 0: the unlifted step count is searched per member in [T_min, T_q]
                            (Sec. 4.3: drawn uniformly, evolved by deco_evo_next_steps; a member
                            past its count keeps its columns still with a step of 0); 0: T_q */
+  int32_t T_l_min;      /* > 0: the same for the lifted step count in [T_l_min, T_l]; 0: T_l */
 } deco_solve_params;
 
 typedef struct deco_solve_report {
@@ -271,6 +272,7 @@ typedef struct deco_solve_report {
   double eq_best, el_best;  /* genes of the best member at the end */
   int32_t l_best;
   int32_t T_best;           /* unlifted step count of the best member at the end */
+  int32_t T_l_best;         /* lifted step count of the best member at the end */
 } deco_solve_report;
 
 deco_status deco_solve(const deco_graph *g, const deco_solve_params *p, void *stream,
@@ -334,9 +336,11 @@ deco_status deco_evo_next(int32_t K, const double *fitness, const double *eq, co
  * members are ranked as by deco_evo_next (descending fitness, ties to the lower index); the
  * top half keeps its counts in rank order and slot K/2 + j takes ranked member j's count
  * T0 as T' = floor(T0 (1 + 0.2 (2 eps' - 1))), eps' ~ U(0,1) (Philox counter (round, slot,
- * 6, 2)), clipped to [T_lo, T_hi]. Host arrays [K]. DECO_E_INVAL for K < 1 or bad bounds. */
+ * 6, 2 + 2 gene); gene 0: unlifted count, 1: lifted count), clipped to [T_lo, T_hi]. Host
+ * arrays [K]. DECO_E_INVAL for K < 1, bad bounds or gene > 1. */
 deco_status deco_evo_next_steps(int32_t K, const double *fitness, const int32_t *T, int32_t T_lo,
-                                int32_t T_hi, uint64_t seed, uint32_t round, int32_t *T_out);
+                                int32_t T_hi, uint64_t seed, uint32_t round, uint32_t gene,
+                                int32_t *T_out);
 
 /* Host utility: Philox4x32-10 of one counter/key (for known-answer tests). */
 void deco_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

@@ -70,7 +70,7 @@ def _declare(L):
     L.orc_init_idi.argtypes = [I64, I64, P, P, P, I64, D, U64, U32, P]
     L.orc_init_gauss.argtypes = [I64, I64, P, D, D, U64, U32, P]
     L.orc_evo_next.argtypes = [I64, P, P, P, P, D, D, I32, U64, U32, P, P, P]
-    L.orc_evo_next_steps.argtypes = [I64, P, P, I64, I64, U64, U32, P]
+    L.orc_evo_next_steps.argtypes = [I64, P, P, I64, I64, U64, U32, U32, P]
     L.orc_perturb_T.argtypes = [I64, D, I64, I64]
     L.orc_perturb_T.restype = I64
     L.orc_run_batch.argtypes = [I64, P, P, P, I64, I64, ct.c_int, ct.c_int, P, I64, I64, P, P, P, P]
@@ -253,13 +253,14 @@ def evo_next(fitness, eq, el, l, seed, rnd, lo=-4.0, hi=-1.0, lmax=4):
     return ao, bo, co
 
 
-def evo_next_steps(fitness, T, Tl, Tu, seed, rnd):
-    """Step counts after one evolution round (Sec. 4.3), paired with evo_next's ranking."""
+def evo_next_steps(fitness, T, Tl, Tu, seed, rnd, gene=0):
+    """Step counts after one evolution round (Sec. 4.3), paired with evo_next's ranking;
+    gene 0 is the unlifted count, 1 the lifted one (separate draws)."""
     K = len(fitness)
     f = np.ascontiguousarray(fitness, np.float64)
     t = np.ascontiguousarray(T, np.int32)
     out = np.zeros(K, np.int32)
-    _L().orc_evo_next_steps(K, _p(f), _p(t), Tl, Tu, seed, rnd, _p(out))
+    _L().orc_evo_next_steps(K, _p(f), _p(t), Tl, Tu, seed, rnd, gene, _p(out))
     return out
 
 

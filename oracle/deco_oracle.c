@@ -415,9 +415,10 @@ int64_t orc_perturb_T(int64_t T0, double eps_u, int64_t Tl, int64_t Tu) {
 
 /* Step counts of the population after one evolution round (Sec. 4.3): members ranked as in
  * orc_evo_next; the kept half is copied in rank order and slot keep + j takes the count of
- * ranked member j perturbed by orc_perturb_T with eps' = u24 of its own draw (index 2). */
+ * ranked member j perturbed by orc_perturb_T with eps' = u24 of its own draw (index
+ * 2 + 2 * gene: gene 0 the unlifted count, 1 the lifted one). */
 void orc_evo_next_steps(int64_t K, const double *fitness, const int32_t *T, int64_t Tl, int64_t Tu,
-                        uint64_t seed, uint32_t round, int32_t *T_out) {
+                        uint64_t seed, uint32_t round, uint32_t gene, int32_t *T_out) {
   int64_t *rank = (int64_t *)malloc(sizeof(int64_t) * (size_t)K);
   for (int64_t i = 0; i < K; i++) rank[i] = i;
   for (int64_t i = 1; i < K; i++) {
@@ -432,7 +433,7 @@ void orc_evo_next_steps(int64_t K, const double *fitness, const int32_t *T, int6
   for (int64_t i = 0; i < keep; i++) T_out[i] = T[rank[i]];
   uint32_t r[4];
   for (int64_t i = keep; i < K; i++) {
-    draw(seed, round, (uint32_t)i, P_EVO, 2, r);
+    draw(seed, round, (uint32_t)i, P_EVO, 2 + 2 * gene, r);
     T_out[i] = (int32_t)orc_perturb_T(T[rank[i - keep]], u24(r[0]), Tl, Tu);
   }
   free(rank);

@@ -1024,8 +1024,8 @@ deco_status deco_evo_next(int32_t K, const double* fitness, const double* eq, co
 }
 
 deco_status deco_evo_next_steps(int32_t K, const double* fitness, const int32_t* T, int32_t T_lo, int32_t T_hi,
-                                uint64_t seed, uint32_t round, int32_t* T_out) {
-  if (K < 1 || !fitness || !T || !T_out || T_lo < 1 || T_lo > T_hi) return DECO_E_INVAL;
+                                uint64_t seed, uint32_t round, uint32_t gene, int32_t* T_out) {
+  if (K < 1 || !fitness || !T || !T_out || T_lo < 1 || T_lo > T_hi || gene > 1) return DECO_E_INVAL;
   std::vector<int> order(K);
   for (int i = 0; i < K; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return fitness[a] > fitness[b]; });
@@ -1034,7 +1034,7 @@ deco_status deco_evo_next_steps(int32_t K, const double* fitness, const int32_t*
   for (int i = 0; i < keep; ++i) out[i] = T[order[i]];
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   for (int i = keep; i < K; ++i) {
-    uint32_t c[4] = {round, (uint32_t)i, kSearch, 2u};
+    uint32_t c[4] = {round, (uint32_t)i, kSearch, 2u + 2u * gene};
     philox4x32_10(c, k0, k1);
     const double eps = (double)(c[0] >> 8) * (1.0 / 16777216.0);  // eps' ~ U(0, 1)
     const double t = std::floor((double)T[order[i - keep]] * (1.0 + 0.2 * (2.0 * eps - 1.0)));
@@ -1059,6 +1059,7 @@ struct deco_solver {
   std::vector<double> eq, el, gbest, fit, fitg, bc, target;
   std::vector<int32_t> lk, lact;
   std::vector<int32_t> tq;  // unlifted steps per member (searched when p.T_min > 0)
+  std::vector<int32_t> tl;  // lifted steps per member (searched when p.T_l_min > 0)
   std::vector<uint8_t> best_z, zmean, bits;
   std::vector<float> eta;
   std::vector<int> goff;
@@ -1079,6 +1080,33 @@ void solver_free(deco_solver* v) {
     (void)hipFree(v->mem);
   }
   delete v;
+}
+
+// Run one batch in which member k steps T[k] times: the batch runs in segments ending at the
+// distinct counts, and a member whose count is reached keeps its columns still with a step of
+// 0 (the projection leaves an iterate inside the box unchanged). eta holds the members' steps
+// and is zeroed in place as they finish. Returns the longest count through *tmax.
+deco_status run_counts(deco_solver* v, deco_handle* h, std::vector<float>& eta, const std::vector<int32_t>& T,
+                       int* tmax) {
+  std::vector<int32_t> ends(T);
+  std::sort(ends.begin(), ends.end());
+  ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
+  deco_status st;
+  int done = 0;
+  for (int32_t e : ends) {
+    if (e > done && (st = deco_step(h, e - done, v->p.use_graph))) return st;
+    done = std::max(done, (int)e);
+    if (e == ends.back()) break;
+    bool changed = false;
+    for (int b = 0; b < v->B; ++b)
+      if (T[b / v->per] == e && eta[b] != 0.0f) {
+        eta[b] = 0.0f;
+        changed = true;
+      }
+    if (changed && (st = deco_set_eta(h, eta.data()))) return st;
+  }
+  *tmax = done;
+  return DECO_OK;
 }
 
 // Fold one batch's best into the global best, update member fitness (max over the
@@ -1120,7 +1148,7 @@ deco_status deco_solver_create(deco_solver** out, const deco_graph* g, const dec
   if (!sp) return DECO_E_INVAL;
   if (sp->K < 1 || sp->B < 1 || sp->B % sp->K != 0 || sp->l_max < 1 || sp->l_max > 4 || sp->T_q < 0 ||
       sp->T_l < 0 || sp->evo_rounds < 0 || !(sp->scale > 0.0) || !(sp->sigma2 >= 0.0) || sp->T_min < 0 ||
-      (sp->T_min > 0 && sp->T_min > sp->T_q))
+      (sp->T_min > 0 && sp->T_min > sp->T_q) || sp->T_l_min < 0 || (sp->T_l_min > 0 && sp->T_l_min > sp->T_l))
     return DECO_E_INVAL;
   if (sp->init_kind != DECO_INIT_IDI && sp->init_kind != DECO_INIT_DUI && sp->init_kind != DECO_INIT_UNIFORM)
     return DECO_E_INVAL;
@@ -1186,6 +1214,7 @@ deco_status deco_solver_create(deco_solver** out, const deco_graph* g, const dec
   v->el.resize(K);
   v->lk.resize(K);
   v->tq.resize(K);
+  v->tl.resize(K);
   for (int k = 0; k < K; ++k) {
     v->eq[k] = sp->eq0 ? sp->eq0[k] : -1.0;
     v->el[k] = sp->el0 ? sp->el0[k] : -3.0;
@@ -1196,6 +1225,13 @@ deco_status deco_solver_create(deco_solver** out, const deco_graph* g, const dec
       uint32_t c[4] = {0xFFFFFFFFu, (uint32_t)k, kSearch, 3u};
       philox4x32_10(c, (uint32_t)sp->seed, (uint32_t)(sp->seed >> 32));
       v->tq[k] = sp->T_min + (int32_t)(c[0] % (uint32_t)(sp->T_q - sp->T_min + 1));
+    }
+    v->tl[k] = sp->T_l;
+    if (sp->T_l_min > 0) {
+      // the lifted count likewise, U{T_l_min, T_l}, Philox counter (0xFFFFFFFF, k, 6, 5)
+      uint32_t c[4] = {0xFFFFFFFFu, (uint32_t)k, kSearch, 5u};
+      philox4x32_10(c, (uint32_t)sp->seed, (uint32_t)(sp->seed >> 32));
+      v->tl[k] = sp->T_l_min + (int32_t)(c[0] % (uint32_t)(sp->T_l - sp->T_l_min + 1));
     }
   }
   if (sp->target_cut) v->target.assign(sp->target_cut, sp->target_cut + v->G);
@@ -1244,29 +1280,8 @@ deco_status deco_solver_run(deco_solver* v, int32_t rounds, double* best_cut, ui
     sa.beta = sp.beta;
     sa.batch = v->batch++;
     if ((st = deco_start(v->hq, &sa))) return st;
-    // members step T_k times: the batch runs in segments ending at the distinct T_k, and a
-    // member whose count is reached keeps its columns still with a step of 0 (the
-    // projection leaves an iterate inside the box unchanged)
     int tmax = 0;
-    {
-      std::vector<int32_t> ends(v->tq);
-      std::sort(ends.begin(), ends.end());
-      ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
-      int done = 0;
-      for (int32_t e : ends) {
-        if (e > done && (st = deco_step(v->hq, e - done, sp.use_graph))) return st;
-        done = std::max(done, (int)e);
-        if (e == ends.back()) break;
-        bool changed = false;
-        for (int b = 0; b < B; ++b)
-          if (v->tq[b / v->per] == e && v->eta[b] != 0.0f) {
-            v->eta[b] = 0.0f;
-            changed = true;
-          }
-        if (changed && (st = deco_set_eta(v->hq, v->eta.data()))) return st;
-      }
-      tmax = done;
-    }
+    if ((st = run_counts(v, v->hq, v->eta, v->tq, &tmax))) return st;
     if ((st = deco_round_score(v->hq, nullptr, nullptr))) return st;
     if ((st = absorb(v, v->hq))) return st;
     v->steps_done += tmax;
@@ -1283,11 +1298,12 @@ deco_status deco_solver_run(deco_solver* v, int32_t rounds, double* best_cut, ui
     sa.batch = v->batch++;
     sa.l_active = v->lact.data();
     if ((st = deco_start(v->hl, &sa))) return st;
-    if ((st = deco_step(v->hl, sp.T_l, sp.use_graph))) return st;
+    int tlmax = 0;
+    if ((st = run_counts(v, v->hl, v->eta, v->tl, &tlmax))) return st;
     if ((st = deco_round_score(v->hl, nullptr, nullptr))) return st;
     if ((st = absorb(v, v->hl))) return st;
-    v->steps_done += sp.T_l;
-    v->eu += (double)v->g.nnz * B * v->lmax * sp.T_l;
+    v->steps_done += tlmax;
+    v->eu += (double)v->g.nnz * B * v->lmax * tlmax;
     for (int k = 0; k < K; ++k) {
       v->fit[k] = 0.0;
       for (int gi = 0; gi < G; ++gi) v->fit[k] += v->fitg[(size_t)k * G + gi];
@@ -1304,10 +1320,17 @@ deco_status deco_solver_run(deco_solver* v, int32_t rounds, double* best_cut, ui
         return st;
       if (sp.T_min > 0) {
         std::vector<int32_t> tt(K);
-        if ((st = deco_evo_next_steps(K, v->fit.data(), v->tq.data(), sp.T_min, sp.T_q, sp.seed, (uint32_t)r,
+        if ((st = deco_evo_next_steps(K, v->fit.data(), v->tq.data(), sp.T_min, sp.T_q, sp.seed, (uint32_t)r, 0,
                                       tt.data())))
           return st;
         v->tq = tt;
+      }
+      if (sp.T_l_min > 0) {
+        std::vector<int32_t> tt(K);
+        if ((st = deco_evo_next_steps(K, v->fit.data(), v->tl.data(), sp.T_l_min, sp.T_l, sp.seed, (uint32_t)r, 1,
+                                      tt.data())))
+          return st;
+        v->tl = tt;
       }
       v->eq = q;
       v->el = m;
@@ -1318,6 +1341,7 @@ deco_status deco_solver_run(deco_solver* v, int32_t rounds, double* best_cut, ui
           v->el[k] = v->el[0];
           v->lk[k] = v->lk[0];
           v->tq[k] = v->tq[0];
+          v->tl[k] = v->tl[0];
         }
     }
     v->round++;
@@ -1342,6 +1366,7 @@ deco_status deco_solver_run(deco_solver* v, int32_t rounds, double* best_cut, ui
     report->el_best = v->el[0];
     report->l_best = v->lk[0];
     report->T_best = v->tq[0];
+    report->T_l_best = v->tl[0];
   }
   return DECO_OK;
 }

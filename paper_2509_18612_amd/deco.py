@@ -51,7 +51,7 @@ class deco_solve_params(ct.Structure):
                 ("sigma2", ct.c_double), ("scale", ct.c_double), ("time_budget_s", ct.c_double),
                 ("seed", ct.c_uint64), ("eq0", ct.c_void_p), ("el0", ct.c_void_p), ("l0", ct.c_void_p),
                 ("target_cut", ct.c_void_p), ("use_graph", ct.c_int32), ("autotune", ct.c_int32),
-                ("T_min", ct.c_int32)]
+                ("T_min", ct.c_int32), ("T_l_min", ct.c_int32)]
 
 
 class deco_schedule(ct.Structure):
@@ -63,7 +63,7 @@ class deco_schedule(ct.Structure):
 class deco_solve_report(ct.Structure):
     _fields_ = [("rounds_done", ct.c_int32), ("steps_done", ct.c_int64), ("edge_updates", ct.c_double),
                 ("seconds", ct.c_double), ("eq_best", ct.c_double), ("el_best", ct.c_double),
-                ("l_best", ct.c_int32), ("T_best", ct.c_int32)]
+                ("l_best", ct.c_int32), ("T_best", ct.c_int32), ("T_l_best", ct.c_int32)]
 
 
 EXPORTS = ["deco_status_string", "deco_workspace_size", "deco_init", "deco_start", "deco_set_eta",
@@ -121,7 +121,7 @@ def lib():
         L.deco_solver_destroy.argtypes = [P]
         L.deco_solver_destroy.restype = None
         L.deco_evo_next.argtypes = [I32, P, P, P, P, D, D, I32, U64, U32, P, P, P]
-        L.deco_evo_next_steps.argtypes = [I32, P, P, I32, I32, U64, U32, P]
+        L.deco_evo_next_steps.argtypes = [I32, P, P, I32, I32, U64, U32, U32, P]
         L.deco_philox.argtypes = [P, P, P]
         L.deco_philox.restype = None
         L.deco_philox_device.argtypes = [U32, U32, U32, U64, I32, P, P]
@@ -434,9 +434,11 @@ def unpack_mpnn(vec) -> dict:
 # ------------------------------------------------------------------------ solve
 def solve(graph: Graph, B=256, K=8, l_max=4, rounds=4, evo_rounds=2, T_q=500, T_l=200, grad_form=GRAD_CUT,
           x_dtype=F32, init_kind=INIT_IDI, beta=0.2, sigma2=0.8, scale=1e4, time_budget_s=0.0, seed=0,
-          eq0=None, el0=None, l0=None, target_cut=None, use_graph=True, autotune=False, stream=None, T_min=0):
+          eq0=None, el0=None, l0=None, target_cut=None, use_graph=True, autotune=False, stream=None, T_min=0,
+          T_l_min=0):
     """Full pDECO with the evolutionary search; returns a dict of host results. T_min > 0
-    also searches the unlifted step count per member in [T_min, T_q]."""
+    also searches the unlifted step count per member in [T_min, T_q], T_l_min > 0 the lifted
+    one in [T_l_min, T_l]."""
     import torch
     stream = stream if stream is not None else torch.cuda.Stream()
     keep = []
@@ -451,7 +453,7 @@ def solve(graph: Graph, B=256, K=8, l_max=4, rounds=4, evo_rounds=2, T_q=500, T_
     p = deco_solve_params(B, K, l_max, rounds, evo_rounds, T_q, T_l, grad_form, x_dtype, init_kind, beta, sigma2,
                           scale, time_budget_s, seed, arr(eq0, np.float64), arr(el0, np.float64),
                           arr(l0, np.int32), arr(target_cut, np.float64), int(bool(use_graph)),
-                          int(bool(autotune)), int(T_min))
+                          int(bool(autotune)), int(T_min), int(T_l_min))
     G = graph.num_graphs
     best = np.zeros(G, np.float64)
     z = np.zeros(graph.n, np.uint8)
@@ -464,7 +466,8 @@ def solve(graph: Graph, B=256, K=8, l_max=4, rounds=4, evo_rounds=2, T_q=500, T_
     r = rep.rounds_done
     return {"best_cut": best, "z": z, "round_time": rt[:r], "round_best": rb[:r], "rounds_done": r,
             "steps_done": rep.steps_done, "edge_updates": rep.edge_updates, "seconds": rep.seconds,
-            "eq_best": rep.eq_best, "el_best": rep.el_best, "l_best": rep.l_best, "T_best": rep.T_best}
+            "eq_best": rep.eq_best, "el_best": rep.el_best, "l_best": rep.l_best, "T_best": rep.T_best,
+            "T_l_best": rep.T_l_best}
 
 
 class Solver:
@@ -473,7 +476,7 @@ class Solver:
     def __init__(self, graph: Graph, B=256, K=8, l_max=4, evo_rounds=2, T_q=500, T_l=200, grad_form=GRAD_CUT,
                  x_dtype=F32, init_kind=INIT_IDI, beta=0.2, sigma2=0.8, scale=1e4, time_budget_s=0.0, seed=0,
                  eq0=None, el0=None, l0=None, target_cut=None, use_graph=True, autotune=False, stream=None,
-                 T_min=0):
+                 T_min=0, T_l_min=0):
         import torch
         self.graph = graph
         self.stream = stream if stream is not None else torch.cuda.Stream()
@@ -489,7 +492,7 @@ class Solver:
         p = deco_solve_params(B, K, l_max, 1, evo_rounds, T_q, T_l, grad_form, x_dtype, init_kind, beta, sigma2,
                               scale, time_budget_s, seed, arr(eq0, np.float64), arr(el0, np.float64),
                               arr(l0, np.int32), arr(target_cut, np.float64), int(bool(use_graph)),
-                              int(bool(autotune)), int(T_min))
+                              int(bool(autotune)), int(T_min), int(T_l_min))
         torch.cuda.synchronize()
         h = ct.c_void_p()
         _check(lib().deco_solver_create(ct.byref(h), ct.byref(graph.struct), ct.byref(p),
@@ -509,7 +512,8 @@ class Solver:
         r = rep.rounds_done
         return {"best_cut": best, "z": z, "round_time": rt[:r], "round_best": rb[:r], "rounds_done": r,
                 "steps_done": rep.steps_done, "edge_updates": rep.edge_updates, "seconds": rep.seconds,
-                "eq_best": rep.eq_best, "el_best": rep.el_best, "l_best": rep.l_best, "T_best": rep.T_best}
+                "eq_best": rep.eq_best, "el_best": rep.el_best, "l_best": rep.l_best, "T_best": rep.T_best,
+                "T_l_best": rep.T_l_best}
 
     def set_target(self, target_cut):
         t = None if target_cut is None else np.ascontiguousarray(target_cut, np.float64)
@@ -541,12 +545,12 @@ def evo_next(fitness, eq, el, l, seed, rnd, lo=-4.0, hi=-1.0, lmax=4):
     return ao, bo, co
 
 
-def evo_next_steps(fitness, T, T_lo, T_hi, seed, rnd):
+def evo_next_steps(fitness, T, T_lo, T_hi, seed, rnd, gene=0):
     K = len(fitness)
     f = np.ascontiguousarray(fitness, np.float64)
     t = np.ascontiguousarray(T, np.int32)
     out = np.zeros(K, np.int32)
-    _check(lib().deco_evo_next_steps(K, f.ctypes.data, t.ctypes.data, T_lo, T_hi, seed, rnd, out.ctypes.data),
+    _check(lib().deco_evo_next_steps(K, f.ctypes.data, t.ctypes.data, T_lo, T_hi, seed, rnd, gene, out.ctypes.data),
            "deco_evo_next_steps")
     return out
 

@@ -62,21 +62,34 @@ def test_evolution_step_matches_oracle_exactly(seed):
             assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("gene", [0, 1])
 @pytest.mark.parametrize("seed", [0, 7, 98765])
-def test_step_count_evolution_matches_oracle_exactly(seed):
+def test_step_count_evolution_matches_oracle_exactly(seed, gene):
     rng = np.random.default_rng(seed)
     for rnd in range(5):
         K = 6
         fit = rng.integers(0, 4, K).astype(float)  # ties on purpose
         T = rng.integers(3000, 10001, K).astype(np.int32)
-        a = deco.evo_next_steps(fit, T, 3000, 10000, seed, rnd)
-        b = oracle.evo_next_steps(fit, T, 3000, 10000, seed, rnd)
+        a = deco.evo_next_steps(fit, T, 3000, 10000, seed, rnd, gene)
+        b = oracle.evo_next_steps(fit, T, 3000, 10000, seed, rnd, gene)
         assert np.array_equal(a, b)
         order = sorted(range(K), key=lambda i: (-fit[i], i))
         assert np.array_equal(a[:K // 2], T[order[:K // 2]])
         for j in range(K // 2, K):
             t0 = T[order[j - K // 2]]
             assert max(3000, int(np.floor(t0 * 0.8))) <= a[j] <= min(10000, int(np.floor(t0 * 1.2)))
+
+
+def test_step_count_genes_draw_apart():
+    """The unlifted and lifted counts perturb with draws of their own: over a wide range the
+    two genes' children differ, and a gene index past the lifted one is refused."""
+    fit = np.arange(8, dtype=float)
+    T = np.full(8, 50000, np.int32)
+    a = deco.evo_next_steps(fit, T, 1, 100000, 3, 0, 0)
+    b = deco.evo_next_steps(fit, T, 1, 100000, 3, 0, 1)
+    assert np.array_equal(a[:4], b[:4]) and not np.array_equal(a[4:], b[4:])
+    with pytest.raises(RuntimeError):
+        deco.evo_next_steps(fit, T, 1, 100000, 3, 0, 2)
 
 
 def test_workspace_size_and_argument_errors_without_device():

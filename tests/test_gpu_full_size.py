@@ -248,14 +248,18 @@ def test_zero_step_keeps_columns_still():
     h.destroy()
 
 
-def test_solve_with_step_count_search():
-    """pDECO with the step-count half of the search (T_k in [T_min, T_q] per member): the
-    returned cut is the exact cut of the returned vector and the final count is in range."""
+@pytest.mark.parametrize("T_l_min", [0, 15])
+def test_solve_with_step_count_search(T_l_min):
+    """pDECO with the step-count half of the search (T_k in [T_min, T_q] per member, and the
+    lifted count in [T_l_min, T_l] when T_l_min > 0): the returned cut is the exact cut of the
+    returned vector and the final counts are in range."""
     g = synth.barabasi_albert(2000, 3, 6)
     r = deco.solve(deco.Graph(g), B=32, K=4, l_max=2, rounds=3, evo_rounds=2, T_q=160, T_l=40, x_dtype=deco.BF16,
-                   seed=5, T_min=60)
+                   seed=5, T_min=60, T_l_min=T_l_min)
     assert r["best_cut"][0] == oracle.cut(g, r["z"])
     assert 60 <= r["T_best"] <= 160
-    assert 3 * (60 + 40) <= r["steps_done"] <= 3 * (160 + 40)
+    tl_lo = T_l_min if T_l_min else 40
+    assert tl_lo <= r["T_l_best"] <= 40
+    assert 3 * (60 + tl_lo) <= r["steps_done"] <= 3 * (160 + 40)
     gb, _ = oracle.greedy(g, orders=2, seed=1)
     assert r["best_cut"][0] > 0.95 * gb
