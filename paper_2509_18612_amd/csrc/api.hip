@@ -332,7 +332,7 @@ deco_status check_params(const deco_params* p) {
   if (p->grad_form != DECO_GRAD_CUT && p->grad_form != DECO_GRAD_LAPLACIAN) return DECO_E_INVAL;
   if (!p->lifted && p->l != 1) return DECO_E_INVAL;
   if (!std::isfinite(p->eta)) return DECO_E_NONFINITE;
-  if (!supported_B(p->B) || p->l > 4) return DECO_E_UNSUPPORTED;
+  if (!supported_B(p->B) || p->l > kMaxL) return DECO_E_UNSUPPORTED;
   return DECO_OK;
 }
 
@@ -1146,7 +1146,7 @@ deco_status deco_solver_create(deco_solver** out, const deco_graph* g, const dec
   deco_status st = check_graph_args(g);
   if (st) return st;
   if (!sp) return DECO_E_INVAL;
-  if (sp->K < 1 || sp->B < 1 || sp->B % sp->K != 0 || sp->l_max < 1 || sp->l_max > 4 || sp->T_q < 0 ||
+  if (sp->K < 1 || sp->B < 1 || sp->B % sp->K != 0 || sp->l_max < 1 || sp->l_max > kMaxL || sp->T_q < 0 ||
       sp->T_l < 0 || sp->evo_rounds < 0 || !(sp->scale > 0.0) || !(sp->sigma2 >= 0.0) || sp->T_min < 0 ||
       (sp->T_min > 0 && sp->T_min > sp->T_q) || sp->T_l_min < 0 || (sp->T_l_min > 0 && sp->T_l_min > sp->T_l))
     return DECO_E_INVAL;

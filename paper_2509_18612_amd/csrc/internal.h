@@ -30,6 +30,7 @@ struct DevCtrl {
 // Work-item limits of the step kernel (LDS staging of one item's slot list).
 constexpr int kEmax = 2048;  // slots staged at a time
 constexpr int kRmax = 512;   // rows of a normal item
+constexpr int kMaxL = 8;     // lifted components per initialisation
 
 // Slot list: row v occupies positions [row_ptr[v] + v, row_ptr[v+1] + v + 1): its own
 // index with the top bit set, then its neighbours in CSR order. The slot weights (weighted
@@ -86,6 +87,8 @@ hipError_t launch_step(const StepArgs& a, int dtype, int vec, int grid, hipStrea
 // The same for handles with a velocity (a.vel != NULL): the kernels with the heavy-ball
 // update (step_momentum.hip).
 hipError_t launch_step_momentum(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s);
+// Step kernels of 5..8 lifted components (plain and momentum).
+hipError_t launch_step_wide(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s);
 int native_vec(int dtype, int L);
 // Dense path: n % 128 == 0, C % 128 == 0, bfloat16 X and W, unlifted.
 hipError_t launch_dense_step(const StepArgs& a, hipStream_t s);

@@ -1443,9 +1443,13 @@ hipError_t step_dispatch_l(const StepArgs& a, int wmode, int grid, hipStream_t s
   return hipErrorInvalidValue;
 }
 
+inline int step_weight_mode(const StepArgs& a) {
+  return a.w == nullptr ? kUnitW : (a.pm1 ? kPm1W : (a.intw ? kIntW : kRealW));
+}
+
 template <bool MOM>
 hipError_t launch_step_impl(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s) {
-  const int wmode = a.w == nullptr ? kUnitW : (a.pm1 ? kPm1W : (a.intw ? kIntW : kRealW));
+  const int wmode = step_weight_mode(a);
   if (dtype == 0) {
     if (vec == 4) return step_dispatch_l<float, 4, MOM>(a, wmode, grid, s);
     if (vec == 1) return step_dispatch_l<float, 1, MOM>(a, wmode, grid, s);
@@ -1744,7 +1748,7 @@ inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1)
 
 }  // namespace
 
-#ifndef DECO_STEP_MOMENTUM_TU  // the host launchers live in this translation unit only
+#ifndef DECO_KERNELS_ONLY_TU  // the host launchers live in this translation unit only
 int native_vec(int dtype, int L) { return dtype == 0 ? 4 : (L == 1 ? 8 : 4); }
 
 hipError_t launch_dense_transpose(const void* X, void* XT, long long n, int C, hipStream_t s) {
@@ -1766,6 +1770,7 @@ hipError_t launch_dense_validate(const uint16_t* W, int n, float* dw, int* flags
 }
 
 hipError_t launch_step(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s) {
+  if (a.L > 4) return launch_step_wide(a, dtype, vec, grid, s);
   if (a.vel != nullptr) return launch_step_momentum(a, dtype, vec, grid, s);
   return launch_step_impl<false>(a, dtype, vec, grid, s);
 }
@@ -1852,6 +1857,6 @@ hipError_t launch_philox_test(uint32_t c1, uint32_t c2, uint32_t c3, unsigned lo
   return hipGetLastError();
 }
 
-#endif  // DECO_STEP_MOMENTUM_TU
+#endif  // DECO_KERNELS_ONLY_TU
 
 }  // namespace deco

@@ -2,7 +2,7 @@
 // runs PGA with momentum, Sec. 4.2 and Sec. 5). The kernel templates are those of
 // kernels.hip; this translation unit instantiates only their velocity variants and the
 // launcher for them, so they compile in parallel with the plain ones.
-#define DECO_STEP_MOMENTUM_TU 1
+#define DECO_KERNELS_ONLY_TU 1
 #include "kernels.hip"
 
 namespace deco {

@@ -99,7 +99,7 @@ def test_workspace_size_and_argument_errors_without_device():
     p = deco.deco_params(16, 1, 0, 0, 0, 1, 0.1, 0)
     assert deco.lib().deco_workspace_size(ct.byref(g), ct.byref(p), ct.byref(nb)) == 0 and nb.value > 0
     bad = [deco.deco_params(3, 1, 0, 0, 0, 1, 0.1, 0),   # B = 3 unsupported
-           deco.deco_params(16, 5, 1, 0, 0, 1, 0.1, 0),  # l = 5 unsupported
+           deco.deco_params(16, 9, 1, 0, 0, 1, 0.1, 0),  # l = 9 unsupported
            deco.deco_params(16, 2, 0, 0, 0, 1, 0.1, 0),  # l > 1 needs lifted rounding
            deco.deco_params(16, 1, 0, 7, 0, 1, 0.1, 0),  # bad gradient form
            deco.deco_params(16, 1, 0, 0, 0, 0, 0.1, 0),  # score_every = 0

@@ -166,10 +166,12 @@ def test_regular3_million_pm1_B128():
     h.destroy()
 
 
-def test_solve_small_graph_bounded_by_brute_force():
+@pytest.mark.parametrize("l_max", [4, 8])
+def test_solve_small_graph_bounded_by_brute_force(l_max):
     g = synth.erdos_renyi(18, 0.4, 3)
     opt = oracle.brute_force(g)[0]
-    r = deco.solve(deco.Graph(g), B=32, K=8, l_max=4, rounds=3, evo_rounds=2, T_q=100, T_l=50, seed=3)
+    r = deco.solve(deco.Graph(g), B=32, K=8, l_max=l_max, rounds=3, evo_rounds=2, T_q=100, T_l=50, seed=3)
+    assert 1 <= r["l_best"] <= l_max
     assert r["best_cut"][0] == oracle.cut(g, r["z"]) <= opt
     assert r["best_cut"][0] >= 0.9 * opt
     assert np.all(np.diff(r["round_best"][:, 0]) >= 0)

@@ -88,6 +88,8 @@ CASES = {
     "lifted_l2_B16": (lambda: synth.erdos_renyi(400, 0.06, 7), 16, dict(l=2, lifted=True)),
     "lifted_l3_B8": (lambda: synth.barabasi_albert(300, 4, 8), 8, dict(l=3, lifted=True)),
     "lifted_l4_B32": (lambda: synth.erdos_renyi(300, 0.05, 9), 32, dict(l=4, lifted=True)),
+    "lifted_l5_B8": (lambda: synth.barabasi_albert(300, 4, 16), 8, dict(l=5, lifted=True)),
+    "lifted_l8_B16": (lambda: synth.erdos_renyi(300, 0.05, 17), 16, dict(l=8, lifted=True)),
     "B1": (lambda: synth.erdos_renyi(200, 0.05, 10), 1, {}),
     "B2": (lambda: synth.erdos_renyi(200, 0.05, 11), 2, {}),
     "B4_lifted": (lambda: synth.erdos_renyi(200, 0.05, 12), 4, dict(l=2, lifted=True)),
@@ -116,7 +118,7 @@ def test_fp32_teacher_forced_parity(name):
 
 
 @pytest.mark.parametrize("name", ["er_unit_B16", "ba_hubs_B64", "lifted_l2_B16", "er_pm1_B24_tiles",
-                                  "laplacian_B16"])
+                                  "laplacian_B16", "lifted_l8_B16"])
 def test_bf16_teacher_forced_parity(name):
     make, B, kw = CASES[name]
     g = make()
@@ -303,12 +305,13 @@ def test_idi_per_graph_statistics_in_a_batch():
     h.destroy()
 
 
-def test_inactive_lift_components_stay_zero():
+@pytest.mark.parametrize("l", [4, 8])
+def test_inactive_lift_components_stay_zero(l):
     g = synth.erdos_renyi(300, 0.05, 3)
-    B, l = 16, 4
+    B = 16
     G = deco.Graph(g)
     h = deco.Handle(G, B=B, l=l, lifted=True, seed=1)
-    la = np.array([1, 2, 3, 4] * 4, np.int32)
+    la = np.array([1 + b % l for b in range(B)], np.int32)
     z = torch.ones(g.n, dtype=torch.uint8, device="cuda")
     h.start(deco.INIT_MEAN, mean_z=z, scale=1e4, sigma2=0.8, batch=2, l_active=la)
     h.step(25)
@@ -434,7 +437,7 @@ def test_step_calls_split_and_replayed_agree_bitwise(lifted):
         assert np.array_equal(ref[3], other[3]) and np.array_equal(ref[4], other[4])
 
 
-@pytest.mark.parametrize("dtype,l", [(deco.F32, 1), (deco.BF16, 1), (deco.F32, 2)])
+@pytest.mark.parametrize("dtype,l", [(deco.F32, 1), (deco.BF16, 1), (deco.F32, 2), (deco.F32, 6)])
 def test_momentum_teacher_forced_parity(dtype, l):
     """Heavy-ball momentum (deco_set_momentum): from the GPU's own X_t and V_t, the oracle's
     momentum step gives X_t+1 and V_t+1 (float32: V within 2e-5 relative, X within the step
