@@ -107,7 +107,7 @@ def test_er800_uniform_start_200_steps():
     h.destroy()
 
 
-@pytest.mark.parametrize("dtype,l", [(deco.F32, 1), (deco.BF16, 1), (deco.F32, 4), (deco.BF16, 2)])
+@pytest.mark.parametrize("dtype,l", [(deco.F32, 1), (deco.BF16, 1), (deco.F32, 4), (deco.BF16, 2), (deco.BF16, 8)])
 def test_ba10k_B256_full_rows(dtype, l):
     g = synth.barabasi_albert(10_000, 4, 0)
     G = deco.Graph(g)
