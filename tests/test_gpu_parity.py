@@ -305,6 +305,30 @@ def test_idi_per_graph_statistics_in_a_batch():
     h.destroy()
 
 
+@pytest.mark.parametrize("B", [1, 8])
+def test_lifted_side_uses_float32_sum_in_component_order(B):
+    """l = 8, float32: a vertex whose components are (0.1, 0.2, 0.3, -0.6, 0, 0, 0, 0) sums
+    to exactly 0 in component order (side 1, the lifted tie), although the exact sum is
+    negative; joined by one edge to a vertex at -0.5 everywhere, every initialisation cuts
+    the edge. B = 1 runs one-element lanes, B = 8 four-element lanes."""
+    l = 8
+    g = synth.from_edges(2, np.array([0]), np.array([1]))
+    comp = np.array([0.1, 0.2, 0.3, -0.6, 0, 0, 0, 0], np.float32)
+    x0 = np.empty((2, l * B), np.float32)
+    for i in range(l):
+        x0[0, i * B:(i + 1) * B] = comp[i]
+        x0[1, i * B:(i + 1) * B] = -0.5
+    h = deco.Handle(deco.Graph(g), B=B, l=l, lifted=True, seed=1)
+    h.start(deco.INIT_USER, x0=torch.from_numpy(x0).cuda())
+    cut, bits = h.round_score()
+    cut = cut.cpu().numpy()
+    z = deco.bits_to_z(bits.cpu().numpy(), B)
+    assert z[0].tolist() == [1] * B and z[1].tolist() == [0] * B
+    assert np.array_equal(cut, np.ones((1, B)))
+    assert np.array_equal(cut[0], oracle_cuts(g, x0.astype(np.float64), B, l, True)[0][0])
+    h.destroy()
+
+
 @pytest.mark.parametrize("l", [4, 8])
 def test_inactive_lift_components_stay_zero(l):
     g = synth.erdos_renyi(300, 0.05, 3)

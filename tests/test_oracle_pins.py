@@ -10,6 +10,8 @@ import math
 import os
 
 import numpy as np
+import scipy.sparse
+import scipy.sparse.csgraph
 import pytest
 
 import oracle
@@ -225,9 +227,13 @@ def test_laplacian_form_saturation_is_absorbing():
         assert np.all(X[0, :8] == 1.0) and np.all(X[0, 8:] == -1.0)
 
 
-def test_theorem1_lifted_boundary_points_fixed_and_zero_cut_iff_constant_rounding():
-    g = synth.erdos_renyi(7, 0.5, 11)
-    l = 3
+@pytest.mark.parametrize("l", [3, 8])
+def test_theorem1_lifted_boundary_points_fixed_and_zero_cut_iff_constant_rounding(l):
+    # the zero-cut side of the statement needs a connected graph (an isolated vertex can
+    # round apart from the rest without cutting an edge)
+    g = synth.barabasi_albert(7, 2, 11)
+    A = scipy.sparse.csr_matrix((np.ones(g.nnz), g.col_idx, g.row_ptr), shape=(g.n, g.n))
+    assert scipy.sparse.csgraph.connected_components(A)[0] == 1
     rng = np.random.default_rng(3)
     Xs = np.where(rng.random((g.n, l * 64)) < 0.5, -1.0, 1.0)
     Xn = oracle.step(g, Xs, 0.2, oracle.LAPLACIAN_FORM)
@@ -236,6 +242,7 @@ def test_theorem1_lifted_boundary_points_fixed_and_zero_cut_iff_constant_roundin
     cuts = oracle.cut_batch(g, z)[0]
     constant = np.all(z == z[0:1], axis=0)
     assert np.array_equal(cuts == 0, constant)
+    assert 0 < constant.sum() < constant.size  # both sides of the equivalence occur
     # X = e_n c' gives a zero cut for every c in {-1,1}^l
     for c in itertools.product([-1.0, 1.0], repeat=l):
         X = np.tile(np.repeat(np.array(c), 1)[None, :], (g.n, 1))
@@ -295,6 +302,20 @@ def test_lifted_rounding_rule_and_tie():
     assert z.tolist() == [[1, 0], [0, 1]]   # v0: 0.6, -0.3 ; v1: -0.45, 0.0 (tie -> 1)
     zu = oracle.round_signs(np.array([[0.0], [-0.0], [1e-30]]), 1)
     assert zu[:, 0].tolist() == [0, 0, 1]   # unlifted eq. (5) is strict
+
+
+def test_lifted_side_is_taken_on_the_float32_sum_in_component_order():
+    """Hand-worked, l = 8: the float32 values of (0.1, 0.2, 0.3, -0.6, 0, 0, 0, 0) add up to
+    exactly 0 from the first component on (0.1f + 0.2f rounds to 0.3f, + 0.3f gives 0.6f),
+    so the side is 1 (the lifted rule's tie); their exact sum is -2^-27 and the reversed
+    float32 sum is negative too, so a double-precision or reordered sum gives side 0."""
+    comp = np.array([0.1, 0.2, 0.3, -0.6, 0, 0, 0, 0], np.float32).astype(np.float64)
+    assert comp.sum() < 0 and math.fsum(comp[::-1]) == -2.0 ** -27
+    z = oracle.round_signs(comp[None, :], 1, 8, lifted=True)
+    assert z.tolist() == [[1]]
+    z = oracle.round_signs(comp[None, ::-1].copy(), 1, 8, lifted=True)
+    assert z.tolist() == [[0]]
+    assert oracle.round_signs(comp[None, :], 1, 8, lifted=True, sum_f32=False).tolist() == [[0]]
 
 
 def test_running_best_strict_improvement_keeps_earliest_step():
