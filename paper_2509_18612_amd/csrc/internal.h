@@ -87,8 +87,9 @@ hipError_t launch_step(const StepArgs& a, int dtype, int vec, int grid, hipStrea
 // The same for handles with a velocity (a.vel != NULL): the kernels with the heavy-ball
 // update (step_momentum.hip).
 hipError_t launch_step_momentum(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s);
-// Step kernels of 5..8 lifted components (plain and momentum).
+// Step kernels of 5..8 lifted components (plain; routes momentum to the second launcher).
 hipError_t launch_step_wide(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s);
+hipError_t launch_step_wide_momentum(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s);
 int native_vec(int dtype, int L);
 // Dense path: n % 128 == 0, C % 128 == 0, bfloat16 X and W, unlifted.
 hipError_t launch_dense_step(const StepArgs& a, hipStream_t s);
