@@ -32,6 +32,28 @@ def test_library_exports_every_declared_symbol():
     assert set(deco.EXPORTS) == set(declared_functions())
 
 
+def declared_param_counts():
+    src = open(os.path.join(ROOT, "include", "deco.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for name, params in re.findall(r"\b(deco_[a-z_0-9]+)\s*\(([^;{]*?)\)\s*;", src, flags=re.S):
+        params = params.strip()
+        out[name] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
+def test_binding_argument_counts_match_the_header():
+    """Every ctypes prototype of the binding takes as many arguments as the C declaration
+    (a signature change on one side only would shift every later argument)."""
+    L = deco.lib()
+    counts = declared_param_counts()
+    assert set(counts) == set(declared_functions())
+    for name, k in counts.items():
+        at = getattr(L, name).argtypes
+        assert at is not None, f"{name} has no prototype"
+        assert len(at) == k, (name, len(at), k)
+
+
 def test_status_strings():
     for s in [0, -1, -2, -3, -4, -5, -6]:
         assert deco.status_string(s) and deco.status_string(s) != "unknown status"
