@@ -54,6 +54,36 @@ def test_binding_argument_counts_match_the_header():
         assert len(at) == k, (name, len(at), k)
 
 
+def test_binding_structs_match_the_c_layout(tmp_path):
+    """The ctypes structures of the binding have the C compiler's size and field offsets for
+    every struct of the header (gcc compiles a probe against include/deco.h)."""
+    import ctypes as ct
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("needs gcc")
+    structs = [deco.deco_graph, deco.deco_params, deco.deco_start_args, deco.deco_schedule,
+               deco.deco_solve_params, deco.deco_solve_report]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "deco.h"', "int main(void) {"]
+    for S in structs:
+        lines.append(f'  printf("{S.__name__} size %zu\\n", sizeof({S.__name__}));')
+        for f in S._fields_:
+            lines.append(f'  printf("{S.__name__} {f[0]} %zu\\n", offsetof({S.__name__}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        s_name, field, val = ln.split()
+        got[(s_name, field)] = int(val)
+    for S in structs:
+        assert got[(S.__name__, "size")] == ct.sizeof(S), S.__name__
+        for f in S._fields_:
+            assert got[(S.__name__, f[0])] == getattr(S, f[0]).offset, (S.__name__, f[0])
+
+
 def test_status_strings():
     for s in [0, -1, -2, -3, -4, -5, -6]:
         assert deco.status_string(s) and deco.status_string(s) != "unknown status"
