@@ -89,6 +89,8 @@ CASES = {
     "lifted_l3_B8": (lambda: synth.barabasi_albert(300, 4, 8), 8, dict(l=3, lifted=True)),
     "lifted_l4_B32": (lambda: synth.erdos_renyi(300, 0.05, 9), 32, dict(l=4, lifted=True)),
     "lifted_l5_B8": (lambda: synth.barabasi_albert(300, 4, 16), 8, dict(l=5, lifted=True)),
+    "lifted_l6_B24": (lambda: synth.erdos_renyi(250, 0.06, 18), 24, dict(l=6, lifted=True)),
+    "lifted_l7_B2": (lambda: synth.barabasi_albert(250, 3, 19), 2, dict(l=7, lifted=True)),
     "lifted_l8_B16": (lambda: synth.erdos_renyi(300, 0.05, 17), 16, dict(l=8, lifted=True)),
     "B1": (lambda: synth.erdos_renyi(200, 0.05, 10), 1, {}),
     "B2": (lambda: synth.erdos_renyi(200, 0.05, 11), 2, {}),
