@@ -251,9 +251,10 @@ typedef struct deco_solve_params {
   double beta, sigma2, scale; /* Sec. 5: 0.2, 0.8, 1e4 */
   double time_budget_s; /* <= 0: no time limit */
   uint64_t seed;
-  const double *eq0;    /* host [K]: initial log10 steps of the unlifted batch, or NULL */
-  const double *el0;    /* host [K]: initial log10 steps of the lifted batch, or NULL */
-  const int32_t *l0;    /* host [K]: initial lift dimensions, or NULL */
+  const double *eq0;    /* host [K]: initial log10 steps of the unlifted batch, or NULL (drawn
+                           by deco_evo_init, Sec. 4.3) */
+  const double *el0;    /* host [K]: initial log10 steps of the lifted batch, or NULL (drawn) */
+  const int32_t *l0;    /* host [K]: initial lift dimensions, or NULL (drawn) */
   const double *target_cut; /* host [G] or NULL */
   int32_t use_graph;    /* capture the step loops in hipGraphs */
   int32_t autotune;     /* run deco_autotune on both handles first (a shape already tuned in
@@ -331,6 +332,22 @@ deco_status deco_mpnn_labels(const deco_graph *g, const uint8_t *z, float *targe
 deco_status deco_evo_next(int32_t K, const double *fitness, const double *eq, const double *el,
                           const int32_t *l, double lo, double hi, int32_t lmax, uint64_t seed,
                           uint32_t round, double *eq_out, double *el_out, int32_t *l_out);
+
+/* Initial population of the evolution-based search (Sec. 4.3: every member's combination is
+ * drawn from the bounds). Member k (host arrays [K] out):
+ *   eq[k], el[k] = lo + (hi - lo) u, u = (r >> 8) 2^-24 of words 0 and 1 of Philox counter
+ *     (0xFFFFFFFF, k, 6, 6): the log10 step sizes of the unlifted and the lifted batch,
+ *     uniform on [lo, hi);
+ *   l[k] = 1 + (word 2 of that draw) mod lmax: the lift dimension, uniform on {1..lmax};
+ *   Tq[k] = Tq_lo + (word 0 of counter (0xFFFFFFFF, k, 6, 3)) mod (Tq_hi - Tq_lo + 1), and
+ *   Tl[k] likewise from counter (0xFFFFFFFF, k, 6, 5): the step counts, uniform on their
+ *     ranges (relative bias of the modulo below 2^-19 for ranges up to 8192 counts).
+ * deco_solver_create draws its population with this function (lo = -4, hi = -1, the bounds
+ * of Sec. 5; counts from [T_min, T_q] and [T_l_min, T_l] when searched). DECO_E_INVAL for
+ * K < 1, lmax < 1, !(lo <= hi), empty count ranges or NULL outputs. */
+deco_status deco_evo_init(int32_t K, double lo, double hi, int32_t lmax, int32_t Tq_lo, int32_t Tq_hi,
+                          int32_t Tl_lo, int32_t Tl_hi, uint64_t seed, double *eq, double *el, int32_t *l,
+                          int32_t *Tq, int32_t *Tl);
 
 /* Step counts after one evolution round (Sec. 4.3, the step-count half of the search): the
  * members are ranked as by deco_evo_next (descending fitness, ties to the lower index); the

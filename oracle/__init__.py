@@ -71,11 +71,12 @@ def _declare(L):
     L.orc_init_gauss.argtypes = [I64, I64, P, D, D, U64, U32, P]
     L.orc_evo_next.argtypes = [I64, P, P, P, P, D, D, I32, U64, U32, P, P, P]
     L.orc_evo_next_steps.argtypes = [I64, P, P, I64, I64, U64, U32, U32, P]
+    L.orc_evo_init.argtypes = [I64, D, D, I32, I64, I64, I64, I64, U64, P, P, P, P, P]
     L.orc_perturb_T.argtypes = [I64, D, I64, I64]
     L.orc_perturb_T.restype = I64
-    L.orc_run_batch.argtypes = [I64, P, P, P, I64, I64, ct.c_int, ct.c_int, P, I64, I64, P, P, P, P]
-    L.orc_deco.argtypes = [I64, P, P, P, I64, I64, I32, I64, I64, I64, I64, ct.c_int, D, D, D, U64,
-                           P, P, P, P, P]
+    L.orc_run_batch.argtypes = [I64, P, P, P, I64, I64, ct.c_int, ct.c_int, P, I64, P, I64, P, P, P, P]
+    L.orc_deco.argtypes = [I64, P, P, P, I64, I64, I32, I64, I64, I64, I64, I64, I64, ct.c_int, D, D, D, U64,
+                           P, P, P, P, P, P, P]
     L.orc_deco.restype = D
     L.orc_brute_force.argtypes = [I64, P, P, P, P]
     L.orc_brute_force.restype = D
@@ -264,36 +265,54 @@ def evo_next_steps(fitness, T, Tl, Tu, seed, rnd, gene=0):
     return out
 
 
+def evo_init(K, seed, lmax=4, Tq=(1, 1), Tl=(1, 1), lo=-4.0, hi=-1.0):
+    """Initial population of the search (Sec. 4.3): per member e_q, e_l ~ U[lo, hi),
+    l ~ U{1..lmax}, T_q ~ U{Tq[0]..Tq[1]}, T_l ~ U{Tl[0]..Tl[1]}. Returns (eq, el, l, tq, tl)."""
+    eq, el = np.zeros(K), np.zeros(K)
+    l, tq, tl = np.zeros(K, np.int32), np.zeros(K, np.int32), np.zeros(K, np.int32)
+    _L().orc_evo_init(K, lo, hi, lmax, int(Tq[0]), int(Tq[1]), int(Tl[0]), int(Tl[1]), seed, _p(eq), _p(el),
+                      _p(l), _p(tq), _p(tl))
+    return eq, el, l, tq, tl
+
+
 def perturb_T(T0, eps_u, Tl, Tu) -> int:
     return int(_L().orc_perturb_T(T0, eps_u, Tl, Tu))
 
 
-def run_batch(g, X, B, l, lifted, eta_b, T, form=CUT_FORM, score_every=1):
-    """Alg. 1 (l = 1, unlifted) or Alg. 2 (lifted): returns (X_T, best, best_step, z_best)."""
+def run_batch(g, X, B, l, lifted, eta_b, T, form=CUT_FORM, score_every=1, T_b=None):
+    """Alg. 1 (l = 1, unlifted) or Alg. 2 (lifted): returns (X_T, best, best_step, z_best).
+    T_b: optional per-initialisation step counts (columns past their count keep still)."""
     g = _g(g)
     X = np.array(X, dtype=np.float64, order="C", copy=True)
     best = np.full(B, -np.inf)
     bstep = np.full(B, -1, np.int64)
     zb = np.zeros((g.n, B), np.uint8)
     e = _eta_cols(eta_b, B)
-    _L().orc_run_batch(g.n, _p(g.rp), _p(g.col), _p(g.w), B, l, int(bool(lifted)), form, _p(e), T,
+    tb = None if T_b is None else np.ascontiguousarray(T_b, np.int64)
+    _L().orc_run_batch(g.n, _p(g.rp), _p(g.col), _p(g.w), B, l, int(bool(lifted)), form, _p(e), T, _p(tb),
                        score_every, _p(X), _p(best), _p(bstep), _p(zb))
     return X, best, bstep, zb
 
 
 def deco(g, B=64, K=8, lmax=4, rounds=4, evo_rounds=2, Tq=200, Tl=100, form=CUT_FORM, beta=0.2,
-         s2=0.8, scale=1e4, seed=0, eq=None, el=None, l=None):
-    """pDECO (Alg. 3) with the column-group population; returns (best_cut, z, trace, genes)."""
+         s2=0.8, scale=1e4, seed=0, eq=None, el=None, l=None, Tq_min=0, Tl_min=0):
+    """pDECO (Alg. 3) with the column-group population; returns (best_cut, z, trace, genes).
+    The initial genes are drawn by evo_init (Sec. 4.3) unless eq / el / l are given; the step
+    counts are searched in [Tq_min, Tq] and [Tl_min, Tl] when the minimum is positive."""
     g = _g(g)
     assert B % K == 0
-    eq = np.full(K, -1.0) if eq is None else np.array(eq, np.float64)
-    el = np.full(K, -3.0) if el is None else np.array(el, np.float64)
-    lk = np.full(K, 2, np.int32) if l is None else np.array(l, np.int32)
+    d_eq, d_el, d_l, d_tq, d_tl = evo_init(K, seed, lmax, (Tq_min if Tq_min > 0 else Tq, Tq),
+                                           (Tl_min if Tl_min > 0 else Tl, Tl))
+    eq = d_eq if eq is None else np.array(eq, np.float64)
+    el = d_el if el is None else np.array(el, np.float64)
+    lk = d_l if l is None else np.array(l, np.int32)
+    tq, tl = d_tq.copy(), d_tl.copy()
     trace = np.zeros(rounds)
     z = np.zeros(g.n, np.uint8)
-    best = _L().orc_deco(g.n, _p(g.rp), _p(g.col), _p(g.w), B, K, lmax, rounds, evo_rounds, Tq, Tl,
-                         form, beta, s2, scale, seed, _p(eq), _p(el), _p(lk), _p(trace), _p(z))
-    return float(best), z, trace, (eq, el, lk)
+    best = _L().orc_deco(g.n, _p(g.rp), _p(g.col), _p(g.w), B, K, lmax, rounds, evo_rounds, Tq, Tl, Tq_min,
+                         Tl_min, form, beta, s2, scale, seed, _p(eq), _p(el), _p(lk), _p(tq), _p(tl), _p(trace),
+                         _p(z))
+    return float(best), z, trace, (eq, el, lk, tq, tl)
 
 
 def brute_force(g):

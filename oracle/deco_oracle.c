@@ -22,11 +22,13 @@
  *  - the running best includes every scored iterate, t = 0..T (Alg. 1/2 score once at T);
  *  - IDI's (Ab)_i counts important neighbours with p = -1;
  *  - the evolutionary genome is (log10 eta for the unlifted batch, log10 eta for the
- *    lifted batch, l) with T fixed per run.
+ *    lifted batch, l), plus the step count of either batch when it is searched; the
+ *    initial population is drawn from the bounds (Sec. 4.3).
  * Parity status: every function here is pinned by a CPU test (brute force, closed forms,
  * identities, fixed points, finite differences, eigen-decomposition, published
- * Philox known-answer vectors) except the evolutionary search and the DECO loop as a
- * whole, which are pinned only by determinism and bounds ("parity unpinned" beyond that).
+ * Philox known-answer vectors, hand-worked draws of the search) except the DECO loop as a
+ * whole, which is pinned only by determinism, bounds, the exactness of its returned cut
+ * and brute force on tiny graphs ("parity unpinned" beyond that).
  */
 #include <math.h>
 #include <stdint.h>
@@ -404,6 +406,31 @@ void orc_evo_next(int64_t K, const double *fitness, const double *eq, const doub
   free(rank);
 }
 
+/* Initial population of the evolution-based search (Sec. 4.3): every member draws its
+ * combination from the bounds. Member k:
+ *   e_q, e_l ~ U[lo, hi): e = lo + (hi - lo) u with u = u24 of words 0 and 1 of the draw
+ *     (counter (0xFFFFFFFF, k, P_EVO, 6)); the steps are 10^e;
+ *   l ~ U{1..lmax}: 1 + (word 2 mod lmax) of the same draw (the lift dimension is this
+ *     build's third gene, Sec. 5 fixes l = 2 where it is not searched);
+ *   T_q ~ U{Tq_lo..Tq_hi}: Tq_lo + (word 0 mod (Tq_hi - Tq_lo + 1)) of the draw
+ *     (0xFFFFFFFF, k, P_EVO, 3); T_l likewise from (0xFFFFFFFF, k, P_EVO, 5).
+ * The modulo draws are uniform up to a relative bias below 2^-19 for ranges below 8193. */
+void orc_evo_init(int64_t K, double lo, double hi, int32_t lmax, int64_t Tq_lo, int64_t Tq_hi,
+                  int64_t Tl_lo, int64_t Tl_hi, uint64_t seed, double *eq, double *el, int32_t *l,
+                  int32_t *Tq, int32_t *Tl) {
+  uint32_t r[4];
+  for (int64_t k = 0; k < K; k++) {
+    draw(seed, 0xFFFFFFFFu, (uint32_t)k, P_EVO, 6, r);
+    eq[k] = lo + (hi - lo) * u24(r[0]);
+    el[k] = lo + (hi - lo) * u24(r[1]);
+    l[k] = 1 + (int32_t)(r[2] % (uint32_t)lmax);
+    draw(seed, 0xFFFFFFFFu, (uint32_t)k, P_EVO, 3, r);
+    Tq[k] = (int32_t)(Tq_lo + (int64_t)(r[0] % (uint32_t)(Tq_hi - Tq_lo + 1)));
+    draw(seed, 0xFFFFFFFFu, (uint32_t)k, P_EVO, 5, r);
+    Tl[k] = (int32_t)(Tl_lo + (int64_t)(r[0] % (uint32_t)(Tl_hi - Tl_lo + 1)));
+  }
+}
+
 /* Step-count perturbation of Sec. 4.3: T' = floor(T0 * (1 + 0.2*(2*eps' - 1))), eps' ~ U(0,1),
  * then clipped to [Tl, Tu]. */
 int64_t orc_perturb_T(int64_t T0, double eps_u, int64_t Tl, int64_t Tu) {
@@ -442,19 +469,19 @@ void orc_evo_next_steps(int64_t K, const double *fitness, const int32_t *T, int6
 /* ------------------------------------------------------------------------------------
  * One batch of pQUCO (Alg. 1) or pLUCO (Alg. 2): T steps from X (updated in place), every
  * iterate t = 0..T scored (score_every = 1) and the per-initialisation best kept.
- * eta_b[b] is the step of initialisation b (all l components share it).
+ * eta_b[b] is the step of initialisation b (all l components share it). T_b (NULL: T for
+ * every initialisation) gives initialisation b its own count: from step T_b[b] on its
+ * columns stay where they are (a step of size 0) while the batch runs on to T.
  * ---------------------------------------------------------------------------------- */
 void orc_run_batch(int64_t n, const int64_t *rp, const int32_t *col, const double *w,
                    int64_t B, int64_t l, int lifted, int form, const double *eta_b, int64_t T,
-                   int64_t score_every, double *X, double *best, int64_t *best_step,
-                   uint8_t *z_best) {
+                   const int64_t *T_b, int64_t score_every, double *X, double *best,
+                   int64_t *best_step, uint8_t *z_best) {
   int64_t C = l * B;
   double *Xn = (double *)malloc(sizeof(double) * (size_t)(n * C + 1));
   double *eta = (double *)malloc(sizeof(double) * (size_t)(C + 1));
   uint8_t *z = (uint8_t *)malloc((size_t)(n * B + 1));
   double *cut = (double *)malloc(sizeof(double) * (size_t)(B + 1));
-  for (int64_t i = 0; i < l; i++)
-    for (int64_t b = 0; b < B; b++) eta[i * B + b] = eta_b[b];
   for (int64_t t = 0; t <= T; t++) {
     if (t % score_every == 0 || t == T) {
       orc_round(n, B, l, lifted, 0, X, z);
@@ -462,6 +489,8 @@ void orc_run_batch(int64_t n, const int64_t *rp, const int32_t *col, const doubl
       orc_best_update(n, B, t, cut, z, best, best_step, z_best);
     }
     if (t == T) break;
+    for (int64_t i = 0; i < l; i++)
+      for (int64_t b = 0; b < B; b++) eta[i * B + b] = (T_b && t >= T_b[b]) ? 0.0 : eta_b[b];
     orc_step(n, rp, col, w, C, X, Xn, eta, form);
     memcpy(X, Xn, sizeof(double) * (size_t)(n * C));
   }
@@ -475,25 +504,32 @@ void orc_run_batch(int64_t n, const int64_t *rp, const int32_t *col, const doubl
  * pDECO (Alg. 3) with the population of Sec. 4.3 laid out as column groups.
  * B initialisations are split into K equal groups (member k owns columns
  * [k*B/K, (k+1)*B/K)). Round r:
- *   1. unlifted batch: X = Proj((mean + sqrt(s2) eps)/scale), T_q steps, member k uses
+ *   1. unlifted batch: X = Proj((mean + sqrt(s2) eps)/scale), member k steps tq[k] times
+ *      (the batch runs to the longest count; a finished member keeps still) with
  *      eta = 10^eq[k]; mean = IDI draw per column in round 0, else 2 z_prev - 1;
  *   2. lift: every component of initialisation b starts at Proj((2 z* - 1 + sqrt(s2) eps)/scale)
  *      with z* the best vector of step 1; member k uses l_k <= lmax components (the rest
- *      are exactly 0 and stay 0, so they do not change the lifted rounding), eta = 10^el[k];
+ *      are exactly 0 and stay 0, so they do not change the lifted rounding), eta = 10^el[k],
+ *      tl[k] steps;
  *   3. project: z_prev = best vector of the lifted batch;
  *   4. fitness_k = best cut over member k's columns in this round; for the first
- *      evo_rounds rounds the population evolves (orc_evo_next), afterwards every member
- *      takes the best genes found.
- * Returns the best cut; z_out (n bytes) receives its vector.
+ *      evo_rounds rounds the population evolves (orc_evo_next for the step exponents and l;
+ *      orc_evo_next_steps for the counts when Tq_min > 0 (range [Tq_min, Tq]) and
+ *      Tl_min > 0 (range [Tl_min, Tl])), afterwards every member takes the first-ranked
+ *      member's genes.
+ * eq, el, lk, tq, tl hold the K initial genes (orc_evo_init draws them) and return the
+ * final ones. Returns the best cut; z_out (n bytes) receives its vector.
  * ---------------------------------------------------------------------------------- */
 double orc_deco(int64_t n, const int64_t *rp, const int32_t *col, const double *w, int64_t B,
                 int64_t K, int32_t lmax, int64_t rounds, int64_t evo_rounds, int64_t Tq,
-                int64_t Tl, int form, double beta, double s2, double scale, uint64_t seed,
-                double *eq, double *el, int32_t *lk, double *trace, uint8_t *z_out) {
+                int64_t Tl, int64_t Tq_min, int64_t Tl_min, int form, double beta, double s2,
+                double scale, uint64_t seed, double *eq, double *el, int32_t *lk, int32_t *tq,
+                int32_t *tl, double *trace, uint8_t *z_out) {
   int64_t Cmax = (int64_t)lmax * B;
   double *X = (double *)calloc((size_t)(n * Cmax + 1), sizeof(double));
   double *M = (double *)calloc((size_t)(n * Cmax + 1), sizeof(double));
   double *eta_b = (double *)malloc(sizeof(double) * (size_t)B);
+  int64_t *T_b = (int64_t *)malloc(sizeof(int64_t) * (size_t)B);
   double *best = (double *)malloc(sizeof(double) * (size_t)B);
   int64_t *bstep = (int64_t *)malloc(sizeof(int64_t) * (size_t)B);
   uint8_t *zb = (uint8_t *)calloc((size_t)(n * B + 1), 1);
@@ -502,6 +538,7 @@ double orc_deco(int64_t n, const int64_t *rp, const int32_t *col, const double *
   double *eq2 = (double *)malloc(sizeof(double) * (size_t)K);
   double *el2 = (double *)malloc(sizeof(double) * (size_t)K);
   int32_t *lk2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)K);
+  int32_t *t2 = (int32_t *)malloc(sizeof(int32_t) * (size_t)K);
   int64_t per = B / K;
   double gbest = -INFINITY;
   uint32_t batch = 0;
@@ -515,12 +552,15 @@ double orc_deco(int64_t n, const int64_t *rp, const int32_t *col, const double *
     }
     orc_init_gauss(n, B, M, s2, scale, seed, batch, X);
     batch++;
+    int64_t tmax = 0;
     for (int64_t b = 0; b < B; b++) {
       eta_b[b] = pow(10.0, eq[b / per]);
+      T_b[b] = tq[b / per];
+      if (T_b[b] > tmax) tmax = T_b[b];
       best[b] = -INFINITY;
       bstep[b] = -1;
     }
-    orc_run_batch(n, rp, col, w, B, 1, 0, form, eta_b, Tq, 1, X, best, bstep, zb);
+    orc_run_batch(n, rp, col, w, B, 1, 0, form, eta_b, tmax, T_b, 1, X, best, bstep, zb);
     for (int64_t k = 0; k < K; k++) fit[k] = -INFINITY;
     int64_t arg = 0;
     for (int64_t b = 0; b < B; b++) {
@@ -542,12 +582,15 @@ double orc_deco(int64_t n, const int64_t *rp, const int32_t *col, const double *
       for (int64_t i = 0; i < lmax; i++)
         for (int64_t b = 0; b < B; b++)
           if (i >= lk[b / per]) X[v * Cmax + i * B + b] = 0.0;
+    tmax = 0;
     for (int64_t b = 0; b < B; b++) {
       eta_b[b] = pow(10.0, el[b / per]);
+      T_b[b] = tl[b / per];
+      if (T_b[b] > tmax) tmax = T_b[b];
       best[b] = -INFINITY;
       bstep[b] = -1;
     }
-    orc_run_batch(n, rp, col, w, B, lmax, 1, form, eta_b, Tl, 1, X, best, bstep, zb);
+    orc_run_batch(n, rp, col, w, B, lmax, 1, form, eta_b, tmax, T_b, 1, X, best, bstep, zb);
     /* 3. project */
     arg = 0;
     for (int64_t b = 0; b < B; b++) {
@@ -566,12 +609,22 @@ double orc_deco(int64_t n, const int64_t *rp, const int32_t *col, const double *
       memcpy(eq, eq2, sizeof(double) * (size_t)K);
       memcpy(el, el2, sizeof(double) * (size_t)K);
       memcpy(lk, lk2, sizeof(int32_t) * (size_t)K);
+      if (Tq_min > 0) {
+        orc_evo_next_steps(K, fit, tq, Tq_min, Tq, seed, (uint32_t)r, 0, t2);
+        memcpy(tq, t2, sizeof(int32_t) * (size_t)K);
+      }
+      if (Tl_min > 0) {
+        orc_evo_next_steps(K, fit, tl, Tl_min, Tl, seed, (uint32_t)r, 1, t2);
+        memcpy(tl, t2, sizeof(int32_t) * (size_t)K);
+      }
       if (r == evo_rounds - 1) {
         /* after the last evolution the ranked-first member's genes are used everywhere */
         for (int64_t k = 1; k < K; k++) {
           eq[k] = eq[0];
           el[k] = el[0];
           lk[k] = lk[0];
+          tq[k] = tq[0];
+          tl[k] = tl[0];
         }
       }
     }
@@ -579,6 +632,7 @@ double orc_deco(int64_t n, const int64_t *rp, const int32_t *col, const double *
   free(X);
   free(M);
   free(eta_b);
+  free(T_b);
   free(best);
   free(bstep);
   free(zb);
@@ -587,6 +641,7 @@ double orc_deco(int64_t n, const int64_t *rp, const int32_t *col, const double *
   free(eq2);
   free(el2);
   free(lk2);
+  free(t2);
   return gbest;
 }
 

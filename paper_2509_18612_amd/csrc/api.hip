@@ -1023,6 +1023,28 @@ deco_status deco_evo_next(int32_t K, const double* fitness, const double* eq, co
   return DECO_OK;
 }
 
+deco_status deco_evo_init(int32_t K, double lo, double hi, int32_t lmax, int32_t Tq_lo, int32_t Tq_hi, int32_t Tl_lo,
+                          int32_t Tl_hi, uint64_t seed, double* eq, double* el, int32_t* l, int32_t* Tq, int32_t* Tl) {
+  if (K < 1 || lmax < 1 || !(lo <= hi) || !std::isfinite(lo) || !std::isfinite(hi) || Tq_lo > Tq_hi ||
+      Tl_lo > Tl_hi || !eq || !el || !l || !Tq || !Tl)
+    return DECO_E_INVAL;
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  for (int k = 0; k < K; ++k) {
+    uint32_t c[4] = {0xFFFFFFFFu, (uint32_t)k, kSearch, 6u};
+    philox4x32_10(c, k0, k1);
+    eq[k] = lo + (hi - lo) * ((double)(c[0] >> 8) * (1.0 / 16777216.0));
+    el[k] = lo + (hi - lo) * ((double)(c[1] >> 8) * (1.0 / 16777216.0));
+    l[k] = 1 + (int32_t)(c[2] % (uint32_t)lmax);
+    uint32_t d[4] = {0xFFFFFFFFu, (uint32_t)k, kSearch, 3u};
+    philox4x32_10(d, k0, k1);
+    Tq[k] = Tq_lo + (int32_t)(d[0] % (uint32_t)((int64_t)Tq_hi - Tq_lo + 1));
+    uint32_t e[4] = {0xFFFFFFFFu, (uint32_t)k, kSearch, 5u};
+    philox4x32_10(e, k0, k1);
+    Tl[k] = Tl_lo + (int32_t)(e[0] % (uint32_t)((int64_t)Tl_hi - Tl_lo + 1));
+  }
+  return DECO_OK;
+}
+
 deco_status deco_evo_next_steps(int32_t K, const double* fitness, const int32_t* T, int32_t T_lo, int32_t T_hi,
                                 uint64_t seed, uint32_t round, uint32_t gene, int32_t* T_out) {
   if (K < 1 || !fitness || !T || !T_out || T_lo < 1 || T_lo > T_hi || gene > 1) return DECO_E_INVAL;
@@ -1215,24 +1237,17 @@ deco_status deco_solver_create(deco_solver** out, const deco_graph* g, const dec
   v->lk.resize(K);
   v->tq.resize(K);
   v->tl.resize(K);
+  // initial population drawn from the bounds (Sec. 4.3); explicit genes override the draw
+  if ((st = deco_evo_init(K, -4.0, -1.0, v->lmax, sp->T_min > 0 ? sp->T_min : sp->T_q, sp->T_q,
+                          sp->T_l_min > 0 ? sp->T_l_min : sp->T_l, sp->T_l, sp->seed, v->eq.data(), v->el.data(),
+                          v->lk.data(), v->tq.data(), v->tl.data()))) {
+    solver_free(v);
+    return st;
+  }
   for (int k = 0; k < K; ++k) {
-    v->eq[k] = sp->eq0 ? sp->eq0[k] : -1.0;
-    v->el[k] = sp->el0 ? sp->el0[k] : -3.0;
-    v->lk[k] = std::min(v->lmax, std::max(1, sp->l0 ? sp->l0[k] : 2));
-    v->tq[k] = sp->T_q;
-    if (sp->T_min > 0) {
-      // T_k ~ U{T_min, T_q} (Sec. 4.3), Philox counter (0xFFFFFFFF, k, 6, 3)
-      uint32_t c[4] = {0xFFFFFFFFu, (uint32_t)k, kSearch, 3u};
-      philox4x32_10(c, (uint32_t)sp->seed, (uint32_t)(sp->seed >> 32));
-      v->tq[k] = sp->T_min + (int32_t)(c[0] % (uint32_t)(sp->T_q - sp->T_min + 1));
-    }
-    v->tl[k] = sp->T_l;
-    if (sp->T_l_min > 0) {
-      // the lifted count likewise, U{T_l_min, T_l}, Philox counter (0xFFFFFFFF, k, 6, 5)
-      uint32_t c[4] = {0xFFFFFFFFu, (uint32_t)k, kSearch, 5u};
-      philox4x32_10(c, (uint32_t)sp->seed, (uint32_t)(sp->seed >> 32));
-      v->tl[k] = sp->T_l_min + (int32_t)(c[0] % (uint32_t)(sp->T_l - sp->T_l_min + 1));
-    }
+    if (sp->eq0) v->eq[k] = sp->eq0[k];
+    if (sp->el0) v->el[k] = sp->el0[k];
+    if (sp->l0) v->lk[k] = std::min(v->lmax, std::max(1, sp->l0[k]));
   }
   if (sp->target_cut) v->target.assign(sp->target_cut, sp->target_cut + v->G);
   v->bc.resize((size_t)v->G * v->B);

@@ -70,7 +70,7 @@ EXPORTS = ["deco_status_string", "deco_workspace_size", "deco_init", "deco_start
            "deco_set_momentum", "deco_step",
            "deco_round_score", "deco_best", "deco_read_x", "deco_set_trace", "deco_current_step",
            "deco_autotune", "deco_schedule_string", "deco_destroy", "deco_solve", "deco_evo_next",
-           "deco_evo_next_steps",
+           "deco_evo_next_steps", "deco_evo_init",
            "deco_philox", "deco_philox_device", "deco_solver_create", "deco_solver_run",
            "deco_solver_set_target", "deco_solver_destroy", "deco_set_schedule", "deco_dense_workspace_size",
            "deco_dense_init", "deco_mpnn_num_params", "deco_mpnn_workspace_size", "deco_mpnn_forward",
@@ -122,6 +122,7 @@ def lib():
         L.deco_solver_destroy.restype = None
         L.deco_evo_next.argtypes = [I32, P, P, P, P, D, D, I32, U64, U32, P, P, P]
         L.deco_evo_next_steps.argtypes = [I32, P, P, I32, I32, U64, U32, U32, P]
+        L.deco_evo_init.argtypes = [I32, D, D, I32, I32, I32, I32, I32, U64, P, P, P, P, P]
         L.deco_philox.argtypes = [P, P, P]
         L.deco_philox.restype = None
         L.deco_philox_device.argtypes = [U32, U32, U32, U64, I32, P, P]
@@ -553,6 +554,16 @@ def evo_next_steps(fitness, T, T_lo, T_hi, seed, rnd, gene=0):
     _check(lib().deco_evo_next_steps(K, f.ctypes.data, t.ctypes.data, T_lo, T_hi, seed, rnd, gene, out.ctypes.data),
            "deco_evo_next_steps")
     return out
+
+
+def evo_init(K, seed, lmax=4, Tq=(1, 1), Tl=(1, 1), lo=-4.0, hi=-1.0):
+    """Initial population of the search (deco_evo_init): returns (eq, el, l, tq, tl)."""
+    eq, el = np.zeros(K), np.zeros(K)
+    l, tq, tl = np.zeros(K, np.int32), np.zeros(K, np.int32), np.zeros(K, np.int32)
+    _check(lib().deco_evo_init(K, lo, hi, lmax, int(Tq[0]), int(Tq[1]), int(Tl[0]), int(Tl[1]), seed,
+                               eq.ctypes.data, el.ctypes.data, l.ctypes.data, tq.ctypes.data, tl.ctypes.data),
+           "deco_evo_init")
+    return eq, el, l, tq, tl
 
 
 def philox(ctr, key) -> np.ndarray:

@@ -132,6 +132,19 @@ def test_step_count_evolution_matches_oracle_exactly(seed, gene):
             assert max(3000, int(np.floor(t0 * 0.8))) <= a[j] <= min(10000, int(np.floor(t0 * 1.2)))
 
 
+@pytest.mark.parametrize("seed", [0, 12345, 2**40 + 7])
+def test_initial_population_matches_oracle_exactly(seed):
+    """The solver's initial population (deco_evo_init) and the oracle's draw (Sec. 4.3) are
+    bit-equal: exponents, lift dimensions and both step counts."""
+    for K, lmax, tq, tl in [(8, 4, (3000, 10000), (100, 400)), (6, 1, (50, 50), (20, 20)), (64, 8, (1, 7), (9, 9))]:
+        a = deco.evo_init(K, seed, lmax, tq, tl)
+        b = oracle.evo_init(K, seed, lmax, tq, tl)
+        for x, y in zip(a, b):
+            assert x.dtype == y.dtype and np.array_equal(x, y)
+    with pytest.raises(RuntimeError):
+        deco.evo_init(4, 0, 4, (10, 9), (1, 1))
+
+
 def test_step_count_genes_draw_apart():
     """The unlifted and lifted counts perturb with draws of their own: over a wide range the
     two genes' children differ, and a gene index past the lifted one is refused."""

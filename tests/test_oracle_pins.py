@@ -438,6 +438,82 @@ def test_evo_next_ranks_keeps_top_half_and_bounds():
     assert np.array_equal(a, a2) and np.array_equal(b, b2) and np.array_equal(c, c2)
 
 
+def load_evo_hand(golden_dir):
+    vals = {}
+    with open(os.path.join(golden_dir, "evo_hand.txt")) as f:
+        for ln in f:
+            if ln.startswith("#") or not ln.strip():
+                continue
+            k, *v = ln.split()
+            vals[k] = v
+    return vals
+
+
+def test_evo_init_hand_worked_member(golden_dir):
+    """One member of the initial population worked out by hand from its Philox words
+    (tests/golden/evo_hand.txt): e = -4 + 3 u24, l = 1 + r mod lmax, T = T_lo + r mod range."""
+    h = load_evo_hand(golden_dir)
+    k = int(h["init_member"][0])
+    eq, el, lk, tq, tl = oracle.evo_init(3, int(h["init_seed"][0]), 4, (3000, 10000), (100, 500))
+    num, den = (int(x) for x in h["init_eq_num"])
+    assert eq[k] == num / den
+    num, den = (int(x) for x in h["init_el_num"])
+    assert el[k] == num / den
+    assert lk[k] == int(h["init_l"][0]) and tq[k] == int(h["init_tq"][0]) and tl[k] == int(h["init_tl"][0])
+
+
+def test_evo_init_bounds_uniformity_and_determinism():
+    """Sec. 4.3 draws the initial combinations uniformly from the bounds: exponents on
+    [-4, -1), l on {1..lmax}, counts on their ranges; members differ; same seed, same draw."""
+    K = 4000
+    eq, el, lk, tq, tl = oracle.evo_init(K, 3, 4, (3000, 10000), (100, 500))
+    for e in (eq, el):
+        assert np.all((e >= -4.0) & (e < -1.0))
+        assert abs(e.mean() + 2.5) < 0.05 and abs(e.std() - 3 / math.sqrt(12)) < 0.03
+        hist = np.histogram(e, bins=6, range=(-4, -1))[0]
+        assert np.all(np.abs(hist - K / 6) < 5 * math.sqrt(K / 6))
+    assert np.corrcoef(eq, el)[0, 1] ** 2 < 0.01          # the two exponents draw apart
+    counts = np.bincount(lk, minlength=5)[1:]
+    assert counts.min() > 0.2 * K and counts.max() < 0.3 * K and lk.min() == 1 and lk.max() == 4
+    assert tq.min() >= 3000 and tq.max() <= 10000 and abs(tq.mean() - 6500) < 120
+    assert tl.min() >= 100 and tl.max() <= 500 and abs(tl.mean() - 300) < 8
+    again = oracle.evo_init(K, 3, 4, (3000, 10000), (100, 500))
+    for x, y in zip((eq, el, lk, tq, tl), again):
+        assert np.array_equal(x, y)
+    other = oracle.evo_init(K, 4, 4, (3000, 10000), (100, 500))
+    assert not np.array_equal(eq, other[0])
+    fixed = oracle.evo_init(8, 3, 1, (400, 400), (200, 200))  # one-point ranges
+    assert np.all(fixed[2] == 1) and np.all(fixed[3] == 400) and np.all(fixed[4] == 200)
+
+
+def test_evo_round_hand_worked_k6(golden_dir):
+    """A whole evolution round for K = 6 worked out by hand (tests/golden/evo_hand.txt):
+    ranking with ties to the lower index, the kept half in rank order, slot K/2 + j from
+    ranked member j, Box-Muller perturbation of both exponents with clipping to [-4, -1], l
+    moved by U{-1,0,1} and clipped, and T' = floor(T0 (1 + 0.2 (2 eps' - 1))) clipped to
+    [3000, 10000] (one child clipped at each end)."""
+    h = load_evo_hand(golden_dir)
+    fit = np.array([float(x) for x in h["evo_fitness"]])
+    T = np.array([int(x) for x in h["evo_T"]], np.int32)
+    got = oracle.evo_next_steps(fit, T, 3000, 10000, 7, 0, 0)
+    assert np.array_equal(got, [int(x) for x in h["evo_T_out"]])
+    eq = np.array([float(x) for x in h["evo_eq"]])
+    el = np.array([float(x) for x in h["evo_el"]])
+    lk = np.array([int(x) for x in h["evo_l"]], np.int32)
+    a, b, c = oracle.evo_next(fit, eq, el, lk, 7, 0, lmax=4)
+    assert np.allclose(a, [float(x) for x in h["evo_eq_out"]], rtol=0, atol=1e-12)
+    assert np.allclose(b, [float(x) for x in h["evo_el_out"]], rtol=0, atol=1e-12)
+    assert np.array_equal(c, [int(x) for x in h["evo_l_out"]])
+
+
+def test_gauss_start_box_muller_hand_value(golden_dir):
+    """One Gaussian draw worked out by hand from its Philox words (cos branch, u1 offset by
+    one grid step so that it is never 0): X = (0 + sqrt(1) eps) / 4 at seed 12."""
+    h = load_evo_hand(golden_dir)
+    X = oracle.init_gauss(np.zeros((1, 1)), 1.0, 4.0, int(h["gauss_seed"][0]), 0)
+    assert abs(X[0, 0] * 4.0 - float(h["gauss_eps"][0])) <= 1e-13
+
+
 def test_step_count_perturbation_formula():
     for T0 in [3000, 5000, 9999]:
         for e in [0.0, 0.25, 0.5, 0.999]:
@@ -471,6 +547,35 @@ def test_deco_deterministic_in_seed():
     r1 = oracle.deco(g, B=16, K=4, rounds=2, evo_rounds=1, Tq=30, Tl=20, seed=7)
     r2 = oracle.deco(g, B=16, K=4, rounds=2, evo_rounds=1, Tq=30, Tl=20, seed=7)
     assert r1[0] == r2[0] and np.array_equal(r1[1], r2[1])
+
+
+def test_deco_draws_its_population_and_searches_step_counts():
+    """Without explicit genes the loop starts from the drawn population (with evo_rounds = 0
+    the genes come back unchanged), and with both counts searched the final counts stay in
+    their ranges; the result is the exact cut of its vector and never beats brute force."""
+    g = synth.erdos_renyi(16, 0.4, 9)
+    opt = oracle.brute_force(g)[0]
+    best, z, _, genes = oracle.deco(g, B=16, K=4, lmax=3, rounds=1, evo_rounds=0, Tq=30, Tl=20, seed=11)
+    want = oracle.evo_init(4, 11, 3, (30, 30), (20, 20))
+    for x, y in zip(genes, want):
+        assert np.array_equal(x, y)
+    best, z, _, (eq, el, lk, tq, tl) = oracle.deco(g, B=16, K=4, lmax=3, rounds=3, evo_rounds=2, Tq=40, Tl=30,
+                                                  seed=11, Tq_min=10, Tl_min=5)
+    assert best == oracle.cut(g, z) <= opt
+    assert np.all((tq >= 10) & (tq <= 40)) and np.all((tl >= 5) & (tl <= 30))
+    assert np.all(tq == tq[0]) and np.all(lk == lk[0])  # the best genes everywhere after the search
+
+
+def test_run_batch_member_counts_stop_columns():
+    """A column whose count is reached keeps its iterate (a step of size 0) while the batch
+    runs on: equal to running that column alone for its own count."""
+    g = synth.erdos_renyi(20, 0.3, 4)
+    X0 = oracle.init_uniform(g.n, 4, seed=5)
+    Tb = np.array([3, 7, 0, 7])
+    X, best, _, _ = oracle.run_batch(g, X0, 4, 1, False, 0.1, 7, T_b=Tb)
+    for b in range(4):
+        Xb, bb, _, _ = oracle.run_batch(g, X0[:, b:b + 1], 1, 1, False, 0.1, int(Tb[b]))
+        assert np.array_equal(X[:, b], Xb[:, 0]) and best[b] == bb[0]
 
 
 def test_bf16_rounding_emulation():
