@@ -312,6 +312,15 @@ deco_status deco_mpnn_workspace_size(const deco_graph *g, size_t *bytes);
 /* y[n] = network output per node. Asynchronous. */
 deco_status deco_mpnn_forward(const deco_graph *g, const float *params, float *y, void *workspace,
                               size_t workspace_bytes, void *stream);
+/* For callers that cannot allocate device memory (code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same forward pass with its activations in a
+ * library-owned scratch array instead of a caller workspace. The scratch is a 32 MiB static
+ * device array, one copy per GPU, held until the process ends (1,056 bytes per node: n <=
+ * 31,774, else DECO_E_UNSUPPORTED before anything is launched). The call allocates nothing.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (several
+ * streams or host threads) race and must be serialised by the caller. Asynchronous; y[n]
+ * (device) as deco_mpnn_forward. */
+deco_status deco_mpnn_forward_static(const deco_graph *g, const float *params, float *y, void *stream);
 /* Loss (host double, after a synchronisation) and its gradient with respect to the
  * bfloat16-rounded parameters (device float32, same packing). */
 deco_status deco_mpnn_loss_grad(const deco_graph *g, const float *params, const float *target,

@@ -15,6 +15,7 @@
 #include <stdint.h>
 
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "../../include/deco.h"
@@ -269,6 +270,62 @@ hipError_t forward(const deco_graph* g, const float* P, const Buffers& b, const 
   return hipGetLastError();
 }
 
+// Forward-only layout (the allocation-free variant): one pre-activation buffer shared by
+// the three layers (the forward pass only writes it), layer 3's input and output reuse
+// layer 1's buffers once layer 2 has consumed them; 1,056 bytes per node plus 256.
+Buffers carve_forward(char* base, long long n) {
+  Buffers b{};
+  size_t off = 0;
+  auto f = [&](size_t count) {
+    float* p = base ? reinterpret_cast<float*>(base + off) : nullptr;
+    off += (count * sizeof(float) + 255) / 256 * 256;
+    return p;
+  };
+  b.F = f(n * 4);
+  b.A1 = f(n * 4);
+  b.P1 = b.P2 = b.P3 = f(n * kH);
+  b.H1 = b.H3 = f(n * kH);
+  b.A2 = b.A3 = f(n * kH);
+  b.H2 = f(n * kH);
+  b.goff = f(2);
+  b.total = off;
+  return b;
+}
+
+__global__ void k_goff_single(int* goff, int n) {
+  if (threadIdx.x == 0) {
+    goff[0] = 0;
+    goff[1] = n;
+  }
+}
+
+// Scratch of deco_mpnn_forward_static: a file-scope device array, one copy per GPU for the
+// life of the process. Host code reaches it only through the per-device address returned
+// by hipGetSymbolAddress (the array's name is not a device address on the host).
+constexpr size_t kStaticScratch = (size_t)32 << 20;
+__device__ __align__(256) char scratch[kStaticScratch];
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices];
+std::mutex g_scratch_mu;
+
+// Address of this device's copy of the scratch array (looked up once per device, with
+// the device current).
+hipError_t static_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 const int* goff_of(const deco_graph* g, const Buffers& b, hipStream_t s, hipError_t* e) {
   if (g->graph_row_offset) return g->graph_row_offset;
   const int h[2] = {0, (int)g->n};
@@ -300,6 +357,30 @@ deco_status deco_mpnn_forward(const deco_graph* g, const float* params, float* y
   const Buffers b = carve(reinterpret_cast<char*>(workspace), g->n);
   hipError_t e = hipSuccess;
   const int* goff = goff_of(g, b, s, &e);
+  if (e == hipSuccess) e = forward(g, params, b, goff, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_head, dim3(nb(g->n, 256)), dim3(256), 0, s, (long long)g->n, b.H3, params, nullptr, y,
+                       nullptr, nullptr, 0.0);
+    e = hipGetLastError();
+  }
+  return e == hipSuccess ? DECO_OK : DECO_E_DEVICE;
+}
+
+deco_status deco_mpnn_forward_static(const deco_graph* g, const float* params, float* y, void* stream) {
+  deco_status st = check(g);
+  if (st) return st;
+  if (!params || !y) return DECO_E_INVAL;
+  if (carve_forward(nullptr, g->n).total > kStaticScratch) return DECO_E_UNSUPPORTED;
+  void* base = nullptr;
+  if (static_scratch(&base) != hipSuccess) return DECO_E_DEVICE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const Buffers b = carve_forward(reinterpret_cast<char*>(base), g->n);
+  const int* goff = g->graph_row_offset;
+  if (!goff) {
+    hipLaunchKernelGGL(k_goff_single, dim3(1), dim3(64), 0, s, reinterpret_cast<int*>(b.goff), (int)g->n);
+    goff = reinterpret_cast<const int*>(b.goff);
+  }
+  hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = forward(g, params, b, goff, s);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_head, dim3(nb(g->n, 256)), dim3(256), 0, s, (long long)g->n, b.H3, params, nullptr, y,

@@ -74,7 +74,7 @@ EXPORTS = ["deco_status_string", "deco_workspace_size", "deco_init", "deco_start
            "deco_philox", "deco_philox_device", "deco_solver_create", "deco_solver_run",
            "deco_solver_set_target", "deco_solver_destroy", "deco_set_schedule", "deco_dense_workspace_size",
            "deco_dense_init", "deco_mpnn_num_params", "deco_mpnn_workspace_size", "deco_mpnn_forward",
-           "deco_mpnn_loss_grad", "deco_mpnn_adam", "deco_mpnn_labels"]
+           "deco_mpnn_loss_grad", "deco_mpnn_adam", "deco_mpnn_labels", "deco_mpnn_forward_static"]
 
 _lib = None
 
@@ -110,6 +110,7 @@ def lib():
         L.deco_mpnn_num_params.argtypes = []
         L.deco_mpnn_workspace_size.argtypes = [P, ct.POINTER(ct.c_size_t)]
         L.deco_mpnn_forward.argtypes = [P, P, P, P, ct.c_size_t, P]
+        L.deco_mpnn_forward_static.argtypes = [P, P, P, P]
         L.deco_mpnn_loss_grad.argtypes = [P, P, P, P, ct.POINTER(D), P, ct.c_size_t, P]
         L.deco_mpnn_adam.argtypes = [P, P, P, P, I32, ct.c_float, P]
         L.deco_mpnn_labels.argtypes = [P, P, P, P]
@@ -384,6 +385,16 @@ class Mpnn:
         self.torch.cuda.current_stream().synchronize()
         _check(lib().deco_mpnn_forward(ct.byref(graph.struct), self.params.data_ptr(), y.data_ptr(), ws.data_ptr(),
                                        ws.numel(), ct.c_void_p(self.stream.cuda_stream)), "deco_mpnn_forward")
+        self.stream.synchronize()
+        return y
+
+    def forward_static(self, graph: Graph):
+        """forward() through deco_mpnn_forward_static: activations in the library's static
+        scratch array, no workspace."""
+        y = self.torch.empty(graph.n, dtype=self.torch.float32, device="cuda")
+        self.torch.cuda.current_stream().synchronize()
+        _check(lib().deco_mpnn_forward_static(ct.byref(graph.struct), self.params.data_ptr(), y.data_ptr(),
+                                              ct.c_void_p(self.stream.cuda_stream)), "deco_mpnn_forward_static")
         self.stream.synchronize()
         return y
 
