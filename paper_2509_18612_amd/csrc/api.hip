@@ -136,6 +136,7 @@ struct deco_handle {
   Schedule sched;
   std::vector<int> rp_host;
   std::vector<int> goff_host;
+  std::vector<int> lact_host;  // host copy of the step kernel's active-component counts
   long long t_host = 0;
   double* trace = nullptr;
   int trace_cap = 0;
@@ -525,6 +526,11 @@ deco_status deco_init(deco_handle** out, const deco_graph* g, const deco_params*
     return DECO_E_DEVICE;
   }
   e = launch_fill_eta(const_cast<float*>(a.eta), p->B, p->eta, h->stream);
+  // every component active until a start says otherwise
+  h->lact_host.assign(p->B, p->l);
+  a.lact = reinterpret_cast<const int*>(ws + lay.l_active);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + lay.l_active, h->lact_host.data(), sizeof(int) * p->B, hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = launch_reset(a, a.acc, 2LL * lay.R * h->G * p->B, p->score_every, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
@@ -552,8 +558,17 @@ deco_status deco_start(deco_handle* h, const deco_start_args* s) {
   if (s->l_active) {
     for (int b = 0; b < h->p.B; ++b)
       if (s->l_active[b] < 0 || s->l_active[b] > h->p.l) return DECO_E_INVAL;
-    lact = reinterpret_cast<int*>(ws + lay.l_active);
-    HIP_TRY(h, hipMemcpyAsync(lact, s->l_active, sizeof(int) * h->p.B, hipMemcpyHostToDevice, h->stream));
+  }
+  if (!h->dense) {
+    // the step kernel gathers only the active components (the start zeroes the others)
+    bool same = true;
+    for (int b = 0; b < h->p.B; ++b) same = same && h->lact_host[b] == (s->l_active ? s->l_active[b] : h->p.l);
+    if (!same) {
+      for (int b = 0; b < h->p.B; ++b) h->lact_host[b] = s->l_active ? s->l_active[b] : h->p.l;
+      HIP_TRY(h, hipMemcpyAsync(ws + lay.l_active, h->lact_host.data(), sizeof(int) * h->p.B, hipMemcpyHostToDevice,
+                                h->stream));
+    }
+    if (s->l_active) lact = reinterpret_cast<int*>(ws + lay.l_active);
   }
   int* goff_dev = reinterpret_cast<int*>(ws + lay.goff);
   if (s->kind == DECO_INIT_USER) {

@@ -55,6 +55,8 @@ struct StepArgs {
   const int* seg;   // [9]
   float cW, cD;     // G = cW * (W X) + cD * (d_w . X)
   const float* eta; // [B]
+  const int* lact;  // [B] active components of each initialisation (components at and past
+                    // it are exactly 0 in X and are not gathered), or NULL (all l active)
   uint8_t* bits[3]; // cut bits of the iterate scored at step t live in bits[t % 3]
   uint8_t* best_bits;
   uint8_t* mask;    // [2][G][NBY]: improvements of scored step t in mask[t & 1]

@@ -563,12 +563,24 @@ __device__ __forceinline__ size_t row_offset(int slot, int C) {
   else return (size_t)(uint32_t)__umul24((uint32_t)slot, (uint32_t)C);
 }
 
+// Gathered values of component i of a neighbour row. Lifted rows skip the components at
+// and past the lane's active count na: those are exactly 0 in every row (the start writes
+// zeros and a zero neighbour sum keeps them there), so the skipped load is replaced by its
+// known value and the step's results are unchanged bit for bit.
+template <typename T, int VEC, int L>
+__device__ __forceinline__ typename VecIO<T, VEC>::raw gather_comp(const T* p, int i, int na) {
+  typename VecIO<T, VEC>::raw v{};
+  if (L == 1 || i < na) v = VecIO<T, VEC>::load_raw(p);
+  return v;
+}
+
 template <typename T, int VEC, int L, int WM, bool SELF>
 __device__ __forceinline__ void gather_window(const StepArgs& a, const T* __restrict__ X, T* __restrict__ Y,
                                               uint8_t* __restrict__ bw, const int* s_slot, const float* s_sw,
                                               float* s_part, int part_idx, int p, int pe, int bl, int lc, int gb,
                                               const float* __restrict__ eta, RowState<T, L, VEC, WM>& st,
-                                              ScoreAcc<T, L, VEC, WM>& sc, bool do_score, int lifted, float* vel) {
+                                              ScoreAcc<T, L, VEC, WM>& sc, bool do_score, int lifted, float* vel,
+                                              int na) {
   using IO = VecIO<T, VEC>;
   constexpr int W = Tune<T, L, VEC>::W;
   const size_t B = (size_t)a.B;
@@ -587,7 +599,7 @@ __device__ __forceinline__ void gather_window(const StepArgs& a, const T* __rest
   for (int q = 0; q < W; ++q) {
     // slots past the share read row 0 (always present) and are not folded: no branch per load
 #pragma unroll
-    for (int i = 0; i < L; ++i) xr[q][i] = IO::load_raw(X + row_offset<VEC>(sl[q], a.C) + i * B + bl);
+    for (int i = 0; i < L; ++i) xr[q][i] = gather_comp<T, VEC, L>(X + row_offset<VEC>(sl[q], a.C) + i * B + bl, i, na);
   }
   if (st.lazy) {
     st.zm = side_mask_raw<T, VEC, L>(st.xv, lifted);
@@ -628,7 +640,7 @@ struct WinBuf {
 
 template <typename T, int VEC, int L, int PW>
 __device__ __forceinline__ void load_window(const StepArgs& a, const T* __restrict__ X, const int* s_slot, int p,
-                                            int pe, int bl, WinBuf<T, VEC, L, PW>& wb) {
+                                            int pe, int bl, int na, WinBuf<T, VEC, L, PW>& wb) {
   using IO = VecIO<T, VEC>;
   const size_t B = (size_t)a.B;
   const int rem = pe - p;
@@ -641,7 +653,7 @@ __device__ __forceinline__ void load_window(const StepArgs& a, const T* __restri
   for (int q = 0; q < PW; ++q) {
     // slots past the share read row 0 (always present) and are not folded: no branch per load
 #pragma unroll
-    for (int i = 0; i < L; ++i) wb.xr[q][i] = IO::load_raw(X + row_offset<VEC>(wb.sl[q], a.C) + i * B + bl);
+    for (int i = 0; i < L; ++i) wb.xr[q][i] = gather_comp<T, VEC, L>(X + row_offset<VEC>(wb.sl[q], a.C) + i * B + bl, i, na);
   }
 }
 
@@ -871,6 +883,16 @@ void k_step(StepArgs a) {
     cg = tl.x;
     cbt = tl.y;
     const int bl = cbt * Bt + lc * VEC;  // first initialisation of this lane
+    // lifted rows: components gathered per neighbour (the largest active count among the
+    // lane's initialisations; the rest are exactly 0)
+    int na = L;
+    if constexpr (L > 1) {
+      if (a.lact) {
+        na = 0;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) na = max(na, bl + e < a.B ? a.lact[bl + e] : 0);
+      }
+    }
     // the improvement mask word this thread folds at the end of the item (word-aligned rows
     // and tiles: a thread's words all lie in one tile column, since TW divides kThreads)
     const int fTB = Bt >= 8 ? (Bt >> 3) : 1, fb0 = (cbt * Bt) >> 3;
@@ -936,18 +958,18 @@ void k_step(StepArgs a) {
         // are waited for one by one)
         for (int p = c0; p < c1; p += W)
           gather_window<T, VEC, L, WM, true>(a, X, Y, bw, s_slot, s_sw, s_acc, part_idx, p, c1, bl, lc, gb, eta, st,
-                                             sc, do_score, lifted, vel);
+                                             sc, do_score, lifted, vel, na);
       } else {
         // lifted rows: the next window's gathers are in flight during each fold
         constexpr int PW = PipeTune<T, L, VEC>::W;
         static_assert(3 * PW <= kSlotPad, "windows read past the staged slots");
         WinBuf<T, VEC, L, PW> wa, wb;
-        load_window<T, VEC, L, PW>(a, X, s_slot, c0, c1, bl, wa);
+        load_window<T, VEC, L, PW>(a, X, s_slot, c0, c1, bl, na, wa);
         for (int p = c0; p < c1; p += 2 * PW) {
-          load_window<T, VEC, L, PW>(a, X, s_slot, p + PW, c1, bl, wb);
+          load_window<T, VEC, L, PW>(a, X, s_slot, p + PW, c1, bl, na, wb);
           fold_window<T, VEC, L, WM, PW>(a, Y, bw, s_sw, s_acc, part_idx, p, c1, bl, lc, gb, eta, wa, st, sc,
                                          do_score, lifted, vel);
-          load_window<T, VEC, L, PW>(a, X, s_slot, p + 2 * PW, c1, bl, wa);
+          load_window<T, VEC, L, PW>(a, X, s_slot, p + 2 * PW, c1, bl, na, wa);
           fold_window<T, VEC, L, WM, PW>(a, Y, bw, s_sw, s_acc, part_idx, p + PW, c1, bl, lc, gb, eta, wb, st, sc,
                                          do_score, lifted, vel);
         }
@@ -1016,7 +1038,7 @@ void k_step(StepArgs a) {
         const int c1 = (E * (sgi + 1)) >> nsl;
         for (int p = c0; p < c1; p += W)
           gather_window<T, VEC, L, WM, false>(a, X, Y, bw, s_slot, s_sw, s_acc, 0, p, c1, bl, lc, gb, eta, st, sc,
-                                              do_score, lifted, vel);
+                                              do_score, lifted, vel, na);
         // score of this chunk's share; the 16-bit partials hold at most one chunk
         if (do_score) {
           if constexpr (WM == kUnitW) st.wsum = c1 - c0;

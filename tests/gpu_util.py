@@ -19,18 +19,17 @@ def step_bound(g, X, eta, cw, form):
     """Per-element bound on |float32 step - exact step|: the float32 sum of d_v products
     (Higham, Accuracy and Stability of Numerical Algorithms, Sec. 3.1: gamma_k sum|w x|),
     scaled by eta*|cW|, plus the roundings of the update itself."""
+    import scipy.sparse as sps
     n, C = X.shape
     d = np.diff(g.row_ptr.astype(np.int64))
-    rows = np.repeat(np.arange(n), d)
     w = np.ones(g.nnz) if g.w is None else np.abs(g.w.astype(np.float64))
-    absum = np.zeros((n, C))
-    np.add.at(absum, rows, w[:, None] * np.abs(X[g.col_idx]))
+    Wabs = sps.csr_matrix((w, g.col_idx.astype(np.int64), g.row_ptr.astype(np.int64)), shape=(n, n))
+    absum = np.asarray(Wabs @ np.abs(X))
     k = np.maximum(d, 1)[:, None]
     gamma = k * U32 / (1 - k * U32)
     b = np.abs(eta) * abs(cw) * gamma * absum
     if form == oracle.LAPLACIAN_FORM:
-        dw = np.zeros(n)
-        np.add.at(dw, rows, w)
+        dw = np.asarray(Wabs.sum(axis=1)).reshape(-1)
         b += np.abs(eta) * (dw[:, None] * np.abs(X)) * 4 * U32
     return b + 4 * U32
 
@@ -42,7 +41,7 @@ def bf16_ulp(x):
 
 
 def run_teacher_forced(g, B, steps, l=1, lifted=False, form=deco.GRAD_CUT, dtype=deco.F32, eta=0.1, x0=None,
-                       seed=3, schedule_tune=False, eta_per_init=None, schedule=None):
+                       seed=3, schedule_tune=False, eta_per_init=None, schedule=None, l_active=None):
     """Returns per-step records: list of (X_t, X_{t+1}) as float64 arrays (GPU values),
     plus the handle's trace of cuts and its final best state. schedule: optional
     set_schedule arguments."""
@@ -59,7 +58,7 @@ def run_teacher_forced(g, B, steps, l=1, lifted=False, form=deco.GRAD_CUT, dtype
     if x0 is None:
         x0 = np.asarray(np.random.default_rng(seed).uniform(-1, 1, (g.n, C)), np.float32)
     tdt = torch.float32 if dtype == deco.F32 else torch.bfloat16
-    h.start(deco.INIT_USER, x0=torch.from_numpy(np.asarray(x0, np.float32)).to(tdt).cuda())
+    h.start(deco.INIT_USER, x0=torch.from_numpy(np.asarray(x0, np.float32)).to(tdt).cuda(), l_active=l_active)
     trace = h.set_trace(steps + 1)
     xs = [to_np(h.read_x()).astype(np.float64)]
     for _ in range(steps):

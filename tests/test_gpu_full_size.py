@@ -11,7 +11,7 @@ import pytest
 import oracle
 from paper_2509_18612_amd import deco, synth
 
-from gpu_util import bf16_ulp, oracle_cuts, to_np
+from gpu_util import bf16_ulp, oracle_cuts, step_bound, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -42,19 +42,43 @@ def star_rows(g, rows):
     return mini, np.concatenate(src_rows), np.array(offs[:-1])
 
 
-def check_rows(g, X_t, X_next, rows, eta, dtype, form=deco.GRAD_CUT):
-    mini, src, centre = star_rows(g, rows)
-    want = oracle.step(mini, X_t[src], eta, form)[centre]
-    got = X_next[rows]
+def block_of(g, i):
+    """Graph i of a block-diagonal batch as a graph of its own (rows renumbered from 0)."""
+    o = g.graph_row_offset
+    r0, r1 = int(o[i]), int(o[i + 1])
+    rp = g.row_ptr[r0:r1 + 1].astype(np.int64)
+    ci = g.col_idx[rp[0]:rp[-1]].astype(np.int64) - r0
+    w = None if g.w is None else g.w[rp[0]:rp[-1]]
+    return synth.CSR(n=r1 - r0, row_ptr=(rp - rp[0]).astype(np.int32), col_idx=ci.astype(np.int32), w=w)
+
+
+def step_tol(g, X_t, want, eta, dtype, form=deco.GRAD_CUT):
+    """Per-element tolerance of one step (the float32 summation bound of Higham, Sec. 3.1,
+    gamma_k sum|w x_u| per row, plus the update's roundings; one bfloat16 ulp on top for
+    bfloat16 storage) and the value the GPU must be compared with (the exact step, or its
+    float32 -> bfloat16 rounding)."""
+    cw = -0.5 if form == deco.GRAD_CUT else -1.0
+    bound = step_bound(g, X_t, eta, cw, form)
     if dtype == deco.BF16:
         emu = oracle.to_bf16(want.astype(np.float32)).astype(np.float64)
-        d = np.abs(got - emu)
-        tol = bf16_ulp(emu) + 1e-5
-    else:
-        d = np.abs(got - want)
-        tol = 1e-5
-    assert np.all(d <= tol), f"max deviation {d.max():.3e}"
-    return float(d.max())
+        return emu, bf16_ulp(emu) + bound
+    return want, np.maximum(1e-5, bound)
+
+
+def check_rows(g, X_t, X_next, rows, eta, dtype, form=deco.GRAD_CUT):
+    """Rows of X_next against the oracle's step of their star subgraphs (each row's result is
+    exact there). Returns the largest deviation and, per checked element, whether the step
+    moved it by more than its tolerance (where a skipped update would be caught)."""
+    mini, src, centre = star_rows(g, rows)
+    Xs = X_t[src]
+    want = oracle.step(mini, Xs, eta, form)
+    cmp, tol = step_tol(mini, Xs, want, eta, dtype, form)
+    cmp, tol = cmp[centre], tol[centre]
+    got = X_next[rows]
+    d = np.abs(got - cmp)
+    assert np.all(d <= tol), f"max deviation {d.max():.3e}, {(d > tol).sum()} elements off"
+    moved = np.abs(want[centre] - X_t[rows]) > tol
+    return float(d.max()), moved
 
 
 def run_steps(G, g, B, l, lifted, dtype, steps, eta, kind=deco.INIT_IDI, seed=1):
@@ -109,60 +133,142 @@ def test_er800_uniform_start_200_steps():
 
 @pytest.mark.parametrize("dtype,l", [(deco.F32, 1), (deco.BF16, 1), (deco.F32, 4), (deco.BF16, 2), (deco.BF16, 8)])
 def test_ba10k_B256_full_rows(dtype, l):
+    """BA(10^4, 4), B = 256 (the bench's graph and batch), uniform starts in [-1, 1], eta =
+    0.05, 12 teacher-forced steps on every row and column: each element within the float32
+    summation bound of its row (1e-5 at least; plus one bfloat16 ulp for bfloat16 storage),
+    exact cuts of every iterate. The starts make the check able to fail: a step leaves most
+    entries of low-degree rows (d <= 8) unclipped and moves them by eta/2 |sum_u x_u|, far
+    above the tolerance, so a kernel that dropped their update would be off on most of them
+    (the test asserts that more than 30% of those entries move by more than the tolerance
+    in the oracle's own step; the share is printed)."""
     g = synth.barabasi_albert(10_000, 4, 0)
     G = deco.Graph(g)
-    h, xs, tr = run_steps(G, g, 256, l, l > 1, dtype, 3, eta=0.05)
-    for t in range(3):
-        cuts = oracle_cuts(g, xs[t], 256, l, l > 1)[0]
-        assert np.array_equal(tr[t], cuts)
-        want = oracle.step(g, xs[t], 0.05)
-        if dtype == deco.BF16:
-            emu = oracle.to_bf16(want.astype(np.float32)).astype(np.float64)
-            assert np.all(np.abs(xs[t + 1] - emu) <= bf16_ulp(emu) + 2e-5)
-        else:
-            # hubs of degree ~400: float32 summation bound above 1e-5 on a few rows
-            assert np.abs(xs[t + 1] - want).max() <= 5e-5
+    B, T, eta = 256, 12, 0.05
+    h = deco.Handle(G, B=B, l=l, lifted=l > 1, x_dtype=dtype, eta=eta, seed=1)
+    h.start(deco.INIT_UNIFORM, batch=0)
+    tr = h.set_trace(T + 1)
+    low = g.degrees() <= 8
+    x = to_np(h.read_x()).astype(np.float64)
+    moved_low = total_low = 0
+    for t in range(T):
+        h.step(1, use_graph=True)
+        xn = to_np(h.read_x()).astype(np.float64)
+        want = oracle.step(g, x, eta)
+        cmp, tol = step_tol(g, x, want, eta, dtype)
+        d = np.abs(xn - cmp)
+        assert np.all(d <= tol), f"step {t}: {(d > tol).sum()} elements off, max {d.max():.3e}"
+        assert np.array_equal(tr.cpu().numpy()[t], oracle_cuts(g, x, B, l, l > 1)[0]), f"cut at step {t}"
+        mv = np.abs(want - x) > tol
+        moved_low += int(mv[low].sum())
+        total_low += int(mv[low].size)
+        x = xn
+    h.round_score()
+    trn = tr.cpu().numpy()
+    assert np.array_equal(trn[T], oracle_cuts(g, x, B, l, l > 1)[0])
+    assert moved_low > 0.3 * total_low, (moved_low, total_low)
+    print(f"BA10k dtype={dtype} l={l}: {moved_low / total_low:.1%} of low-degree entries moved beyond tolerance")
+    h.destroy()
+
+
+def test_ba10k_B256_cuts_every_step():
+    """Exact cuts of every iterate of the bench's lifted shape (l = 4, bfloat16) from an IDI
+    start, the start the solver uses."""
+    g = synth.barabasi_albert(10_000, 4, 0)
+    G = deco.Graph(g)
+    h, xs, tr = run_steps(G, g, 256, 4, True, deco.BF16, 6, eta=0.05)
+    for t in range(7):
+        assert np.array_equal(tr[t], oracle_cuts(g, xs[t], 256, 4, True)[0])
     h.destroy()
 
 
 def test_uneven_512_graph_batch():
     """512 graphs (half ER(n~U{200..1200}, 0.15), half BA(n~U{100..2000}, m~U{2..6})) in one
-    persistent launch, B = 64, bfloat16 storage: exact cuts of all 512 x 64 (graph,
-    initialisation) pairs, sampled rows of every graph against the oracle."""
+    launch per step, B = 64, bfloat16 storage, autotuned schedule, uniform starts, eta =
+    0.02, 10 steps: exact cuts of all 512 x 64 (graph, initialisation) pairs at every
+    iterate; every row of 32 whole graphs (16 ER, 16 BA) and 4 sampled rows of every other
+    graph against the oracle's step within the per-row float32 bound plus one bfloat16 ulp.
+    A step moves more than 30% of the checked entries, and of those of degree <= 8 rows, by
+    more than the tolerance (asserted; the shares are printed), so a dropped update fails."""
     g = synth.uneven_batch(512, 7)
     G = deco.Graph(g)
-    h, xs, tr = run_steps(G, g, 64, 1, False, deco.BF16, 2, eta=0.01)
-    for t in range(3):
-        assert np.array_equal(tr[t], oracle_cuts(g, xs[t], 64, 1, False)[0])
-    rng = np.random.default_rng(0)
+    B, T, eta = 64, 10, 0.02
+    h = deco.Handle(G, B=B, x_dtype=deco.BF16, eta=eta, seed=1)
+    h.autotune(3)
+    h.start(deco.INIT_UNIFORM, batch=0)
+    tr = h.set_trace(T + 1)
     goff = g.graph_row_offset
-    rows = np.concatenate([rng.integers(goff[i], goff[i + 1], 2) for i in range(512)])
-    for t in range(2):
-        check_rows(g, xs[t], xs[t + 1], rows, 0.01, deco.BF16)
+    whole = list(range(0, 32))  # graphs 0..31: even ER, odd BA
+    blocks = [block_of(g, i) for i in whole]
+    rng = np.random.default_rng(0)
+    rows = np.concatenate([rng.integers(goff[i], goff[i + 1], 4) for i in range(32, 512)])
+    deg = g.degrees()
+    x = to_np(h.read_x()).astype(np.float64)
+    moved = checked = moved_low = checked_low = 0
+    for t in range(T):
+        h.step(1, use_graph=True)
+        xn = to_np(h.read_x()).astype(np.float64)
+        assert np.array_equal(tr.cpu().numpy()[t], oracle_cuts(g, x, B, 1, False)[0])
+        for i, bg in zip(whole, blocks):
+            r0, r1 = goff[i], goff[i + 1]
+            want = oracle.step(bg, x[r0:r1], eta)
+            cmp, tol = step_tol(bg, x[r0:r1], want, eta, deco.BF16)
+            d = np.abs(xn[r0:r1] - cmp)
+            assert np.all(d <= tol), f"step {t} graph {i}: {(d > tol).sum()} off, max {d.max():.3e}"
+            mv = np.abs(want - x[r0:r1]) > tol
+            moved += int(mv.sum())
+            checked += mv.size
+            lowr = deg[r0:r1] <= 8
+            moved_low += int(mv[lowr].sum())
+            checked_low += int(mv[lowr].size)
+        _, mv = check_rows(g, x, xn, rows, eta, deco.BF16)
+        moved += int(mv.sum())
+        checked += mv.size
+        x = xn
+    h.round_score()
+    assert np.array_equal(tr.cpu().numpy()[T], oracle_cuts(g, x, B, 1, False)[0])
     bc, bs, bb = h.best()
-    assert np.array_equal(oracle.cut_batch(g, deco.bits_to_z(bb, 64)), bc)
-    print(f"uneven batch: n={g.n} nnz={g.nnz}; schedule {h.schedule()}")
+    assert np.array_equal(oracle.cut_batch(g, deco.bits_to_z(bb, B)), bc)
+    assert moved > 0.3 * checked and moved_low > 0.3 * checked_low, (moved, checked, moved_low, checked_low)
+    print(f"uneven batch: n={g.n} nnz={g.nnz}; schedule {h.schedule()}; {moved / checked:.1%} of checked "
+          f"entries moved beyond tolerance ({moved_low / max(checked_low, 1):.1%} on degree <= 8 rows)")
     h.destroy()
 
 
 def test_regular3_million_pm1_B128():
-    """Random 3-regular n = 1e6 with +-1 weights, B = 128, bfloat16: exact cuts for all 128
-    initialisations and 4000 sampled rows per step."""
+    """Random 3-regular n = 1e6 with +-1 weights, B = 128, bfloat16, autotuned schedule,
+    uniform starts, eta = 0.1, 10 steps: exact cuts for all 128 initialisations at every
+    iterate and 4000 sampled rows per step within the per-row bound plus one bfloat16 ulp;
+    more than 30% of the sampled entries move by more than the tolerance (asserted)."""
     g = synth.with_rademacher_weights(synth.random_regular3(1_000_000, 0), 3)
     G = deco.Graph(g)
-    h = deco.Handle(G, B=128, x_dtype=deco.BF16, eta=0.1, seed=1)
+    B, T, eta = 128, 10, 0.1
+    h = deco.Handle(G, B=B, x_dtype=deco.BF16, eta=eta, seed=1)
+    h.autotune(3)
     h.start(deco.INIT_UNIFORM, batch=0)
-    tr = h.set_trace(4)
-    xs = [to_np(h.read_x()).astype(np.float64)]
-    for _ in range(2):
+    tr = h.set_trace(T + 1)
+    rng = np.random.default_rng(1)
+    moved = checked = 0
+    x_dev = h.read_x().clone()
+    for t in range(T):
         h.step(1, use_graph=True)
-        xs.append(to_np(h.read_x()).astype(np.float64))
-    rows = np.random.default_rng(1).integers(0, g.n, 4000)
-    for t in range(2):
-        check_rows(g, xs[t], xs[t + 1], rows, 0.1, deco.BF16)
-    trn = tr.cpu().numpy()
-    for t in range(2):
-        assert np.array_equal(trn[t], oracle_cuts(g, xs[t], 128, 1, False)[0])
+        xn_dev = h.read_x().clone()
+        rows = rng.integers(0, g.n, 4000)
+        mini, src, centre = star_rows(g, rows)
+        xs = to_np(x_dev[torch.from_numpy(src).cuda()]).astype(np.float64)
+        got = to_np(xn_dev[torch.from_numpy(rows).cuda()]).astype(np.float64)
+        want = oracle.step(mini, xs, eta)
+        cmp, tol = step_tol(mini, xs, want, eta, deco.BF16)
+        d = np.abs(got - cmp[centre])
+        assert np.all(d <= tol[centre]), f"step {t}: max deviation {d.max():.3e}"
+        mv = np.abs(want[centre] - xs[centre]) > tol[centre]
+        moved += int(mv.sum())
+        checked += mv.size
+        x_host = to_np(x_dev).astype(np.float64)
+        assert np.array_equal(tr.cpu().numpy()[t], oracle_cuts(g, x_host, B, 1, False)[0])
+        del x_host
+        x_dev = xn_dev
+    assert moved > 0.3 * checked, (moved, checked)
+    print(f"3-regular: schedule {h.schedule()}; {moved / checked:.1%} of sampled entries moved beyond tolerance")
     h.destroy()
 
 

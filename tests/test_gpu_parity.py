@@ -28,9 +28,9 @@ def cw_of(form):
 
 
 def check_run(g, B, steps, l=1, lifted=False, form=deco.GRAD_CUT, dtype=deco.F32, eta=0.1, x0=None, seed=3,
-              schedule_tune=False, eta_per_init=None, schedule=None):
+              schedule_tune=False, eta_per_init=None, schedule=None, l_active=None):
     r = run_teacher_forced(g, B, steps, l, lifted, form, dtype, eta, x0, seed, schedule_tune, eta_per_init,
-                           schedule=schedule)
+                           schedule=schedule, l_active=l_active)
     xs = r["xs"]
     C = l * B
     eta_cols = (np.full(C, eta) if eta_per_init is None
@@ -92,6 +92,14 @@ CASES = {
     "lifted_l6_B24": (lambda: synth.erdos_renyi(250, 0.06, 18), 24, dict(l=6, lifted=True)),
     "lifted_l7_B2": (lambda: synth.barabasi_albert(250, 3, 19), 2, dict(l=7, lifted=True)),
     "lifted_l8_B16": (lambda: synth.erdos_renyi(300, 0.05, 17), 16, dict(l=8, lifted=True)),
+    # members with fewer active components than l (their other components are exactly 0 and
+    # are not gathered); the active count changes inside a lane's initialisations
+    "lifted_l4_active_B32": (lambda: synth.barabasi_albert(400, 3, 20), 32,
+                             dict(l=4, lifted=True, l_active=np.array([1 + (b // 3) % 4 for b in range(32)],
+                                                                      np.int32))),
+    "lifted_l8_active_B16": (lambda: synth.erdos_renyi(300, 0.05, 21), 16,
+                             dict(l=8, lifted=True, l_active=np.array([1 + (5 * b) % 8 for b in range(16)],
+                                                                      np.int32))),
     "B1": (lambda: synth.erdos_renyi(200, 0.05, 10), 1, {}),
     "B2": (lambda: synth.erdos_renyi(200, 0.05, 11), 2, {}),
     "B4_lifted": (lambda: synth.erdos_renyi(200, 0.05, 12), 4, dict(l=2, lifted=True)),
@@ -115,16 +123,16 @@ CASES["er_intw_B8"] = (_intw_graph, 8, {})
 def test_fp32_teacher_forced_parity(name):
     make, B, kw = CASES[name]
     g = make()
-    worst, widened, sched = check_run(g, B, 30, **kw)
+    worst, widened, sched = check_run(g, B, 50, **kw)
     print(f"{name}: max |dX| = {worst:.2e}, rows on the gamma_k bound: {widened}, schedule: {sched}")
 
 
 @pytest.mark.parametrize("name", ["er_unit_B16", "ba_hubs_B64", "lifted_l2_B16", "er_pm1_B24_tiles",
-                                  "laplacian_B16", "lifted_l8_B16"])
+                                  "laplacian_B16", "lifted_l8_B16", "lifted_l4_active_B32"])
 def test_bf16_teacher_forced_parity(name):
     make, B, kw = CASES[name]
     g = make()
-    worst, _, sched = check_run(g, B, 20, dtype=deco.BF16, **kw)
+    worst, _, sched = check_run(g, B, 50, dtype=deco.BF16, **kw)
     print(f"{name} bf16: max |dX| = {worst:.2e}, schedule: {sched}")
 
 
@@ -350,6 +358,47 @@ def test_inactive_lift_components_stay_zero(l):
             else:
                 assert np.any(col != 0.0)
     h.destroy()
+
+
+@pytest.mark.parametrize("l,dtype", [(4, deco.BF16), (4, deco.F32), (2, deco.BF16), (8, deco.BF16)])
+def test_active_component_gathers_equal_full_gathers(l, dtype):
+    """A start that names each initialisation's active components (the step kernel then
+    gathers only those) gives the same iterates, cuts, running best and best bits, bit for
+    bit, as the same start without them (every component gathered), on the bench's lane
+    layout (B = 256) and with active counts that change inside a lane."""
+    g = synth.barabasi_albert(2000, 4, 31)
+    B = 256
+    G = deco.Graph(g)
+    la = np.array([1 + ((b // 32) + (b % 3)) % l for b in range(B)], np.int32)
+    rng = np.random.default_rng(5)
+    x0 = rng.uniform(-1, 1, (g.n, l * B)).astype(np.float32)
+    for b in range(B):
+        x0[:, la[b] * B + b::B] = 0.0
+    tdt = torch.float32 if dtype == deco.F32 else torch.bfloat16
+    X0 = torch.from_numpy(x0).to(tdt).cuda()
+    runs = []
+    for active in (la, None):
+        h = deco.Handle(G, B=B, l=l, lifted=True, x_dtype=dtype, eta=0.05, seed=2)
+        h.start(deco.INIT_USER, x0=X0, l_active=active)
+        tr = h.set_trace(31)
+        xs = []
+        for _ in range(3):
+            h.step(10, use_graph=True)
+            xs.append(h.read_x().clone())
+        cut, bits = h.round_score()
+        bc, bs, bb = h.best()
+        runs.append((xs, tr.cpu().numpy(), cut.cpu().numpy(), bits.cpu().numpy(), bc, bs, bb))
+        h.destroy()
+    (xa, ta, ca, ba, bca, bsa, bba), (xf, tf, cf, bf, bcf, bsf, bbf) = runs
+    for u, v in zip(xa, xf):
+        assert torch.equal(u.view(torch.int16) if dtype == deco.BF16 else u.view(torch.int32),
+                           v.view(torch.int16) if dtype == deco.BF16 else v.view(torch.int32))
+    for u, v in [(ta, tf), (ca, cf), (ba, bf), (bca, bcf), (bsa, bsf), (bba, bbf)]:
+        assert np.array_equal(u, v)
+    # and the inactive components are still exactly 0
+    x = to_np(xa[-1])
+    for b in range(B):
+        assert np.all(x[:, la[b] * B + b::B] == 0.0)
 
 
 def test_philox_device_matches_host_and_oracle():
