@@ -247,7 +247,8 @@ typedef struct deco_solve_params {
   int32_t T_l;          /* steps of every lifted batch */
   int32_t grad_form;    /* DECO_GRAD_* */
   int32_t x_dtype;      /* DECO_F32 or DECO_BF16 */
-  int32_t init_kind;    /* DECO_INIT_IDI or DECO_INIT_DUI for the first batch */
+  int32_t init_kind;    /* DECO_INIT_IDI, DECO_INIT_DUI, DECO_INIT_UNIFORM or DECO_INIT_LEARNED
+                           (with 'magnitude') for the first batch */
   double beta, sigma2, scale; /* Sec. 5: 0.2, 0.8, 1e4 */
   double time_budget_s; /* <= 0: no time limit */
   uint64_t seed;
@@ -263,12 +264,19 @@ typedef struct deco_solve_params {
                            (Sec. 4.3: drawn uniformly, evolved by deco_evo_next_steps; a member
                            past its count keeps its columns still with a step of 0); 0: T_q */
   int32_t T_l_min;      /* > 0: the same for the lifted step count in [T_l_min, T_l]; 0: T_l */
+  const float *magnitude; /* init_kind == DECO_INIT_LEARNED: device [n] per-node magnitudes
+                             (e.g. from deco_mpnn_forward), read by the first batch of every
+                             run of a solver, so it must stay valid while the solver exists;
+                             NULL otherwise */
 } deco_solve_params;
 
 typedef struct deco_solve_report {
   int32_t rounds_done;
   int64_t steps_done;       /* gradient steps over all batches */
-  double edge_updates;      /* sum over steps of nnz * columns */
+  double edge_updates;      /* sum over the members' own gradient steps of nnz * active
+                               columns: B/K initialisations per member, times its lift
+                               dimension in the lifted batch (inactive components and the
+                               still steps of a member past its count are not counted) */
   double seconds;           /* wall time of the whole call */
   double eq_best, el_best;  /* genes of the best member at the end */
   int32_t l_best;

@@ -1187,7 +1187,8 @@ deco_status deco_solver_create(deco_solver** out, const deco_graph* g, const dec
       sp->T_l < 0 || sp->evo_rounds < 0 || !(sp->scale > 0.0) || !(sp->sigma2 >= 0.0) || sp->T_min < 0 ||
       (sp->T_min > 0 && sp->T_min > sp->T_q) || sp->T_l_min < 0 || (sp->T_l_min > 0 && sp->T_l_min > sp->T_l))
     return DECO_E_INVAL;
-  if (sp->init_kind != DECO_INIT_IDI && sp->init_kind != DECO_INIT_DUI && sp->init_kind != DECO_INIT_UNIFORM)
+  if (sp->init_kind != DECO_INIT_IDI && sp->init_kind != DECO_INIT_DUI && sp->init_kind != DECO_INIT_UNIFORM &&
+      !(sp->init_kind == DECO_INIT_LEARNED && sp->magnitude))
     return DECO_E_INVAL;
   if (!supported_B(sp->B)) return DECO_E_UNSUPPORTED;
   deco_solver* v = new deco_solver();
@@ -1305,6 +1306,7 @@ deco_status deco_solver_run(deco_solver* v, int32_t rounds, double* best_cut, ui
     deco_start_args sa{};
     sa.kind = r == 0 ? sp.init_kind : DECO_INIT_MEAN;
     sa.mean_z = v->mean_dev;
+    sa.magnitude = sp.magnitude;
     sa.scale = (sp.init_kind == DECO_INIT_UNIFORM && r == 0) ? 1.0 : sp.scale;
     sa.sigma2 = sp.sigma2;
     sa.beta = sp.beta;
@@ -1315,7 +1317,8 @@ deco_status deco_solver_run(deco_solver* v, int32_t rounds, double* best_cut, ui
     if ((st = deco_round_score(v->hq, nullptr, nullptr))) return st;
     if ((st = absorb(v, v->hq))) return st;
     v->steps_done += tmax;
-    v->eu += (double)v->g.nnz * B * tmax;
+    // edge updates of the members' own steps (a member past its count keeps still)
+    for (int k = 0; k < K; ++k) v->eu += (double)v->g.nnz * v->per * v->tq[k];
     // 2. lift its best vector (Alg. 3 step 2) and run the lifted batch (Alg. 2); member k
     //    keeps lk[k] of the lmax components and steps with 10^el[k]; 3. project back
     for (int b = 0; b < B; ++b) {
@@ -1333,7 +1336,8 @@ deco_status deco_solver_run(deco_solver* v, int32_t rounds, double* best_cut, ui
     if ((st = deco_round_score(v->hl, nullptr, nullptr))) return st;
     if ((st = absorb(v, v->hl))) return st;
     v->steps_done += tlmax;
-    v->eu += (double)v->g.nnz * B * v->lmax * tlmax;
+    // active components only: components past a member's lift dimension stay exactly 0
+    for (int k = 0; k < K; ++k) v->eu += (double)v->g.nnz * v->per * v->lk[k] * v->tl[k];
     for (int k = 0; k < K; ++k) {
       v->fit[k] = 0.0;
       for (int gi = 0; gi < G; ++gi) v->fit[k] += v->fitg[(size_t)k * G + gi];
