@@ -8,11 +8,14 @@ A "step" of this benchmark is one lift-and-project round: T_q unlifted gradient 
 T_l lifted gradient steps (each fused with rounding, exact scoring of every iterate and the
 running best), the lift, the projection and one evolution update.
 
-Reported value: edge-updates/s = sum over gradient steps of nnz * columns, divided by the
-wall time of the timed rounds (inputs resident in HBM). Also reported: the live roofline of
-the step kernels (HIP events on the library's stream), the CPU oracle timed on this host's
-cores on a bounded sample, and time-to-cut (0.995 of the plain float32 method's best) for
-float32 and bfloat16 storage of X.
+Reported value: edge-updates/s of the float32-storage run = sum over the members' own
+gradient steps of nnz * active columns, divided by the wall time of the timed rounds (inputs
+resident in HBM). The bfloat16-storage run (float32 accumulation) is reported beside it, with
+its per-step error against an exact float64 step. Also reported: the live roofline of the
+dominant step kernel (HIP events on the library's stream), the CPU oracle timed on this host
+(one thread and all cores) on a bounded sample, and time-to-cut (0.995 of the best cut of a
+long plain float32 run) for float32, bfloat16, bfloat16 + learned start and bfloat16 + learned
+start + batched seeds, median of 5 seeds.
 """
 import argparse
 import json
@@ -25,8 +28,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "edge-updates/s (nnz·B·steps/s); time-to-cut within 0.5% of best, plain vs chosen"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_ba10k_B256_bf16_traffic.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_ba10k_B256_traffic.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2509_18612_amd", "csrc", "kernels.hip")
+MPNN_WEIGHTS = os.path.join(ROOT, "paper_2509_18612_amd", "data", "mpnn_ba.npy")
+
+
+def log(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
 
 
 def measured_traffic(which):
@@ -52,15 +60,30 @@ def measured_traffic(which):
 
 def algorithmic_bytes(n, nnz, C, G, s_x, s_w):
     """Minimum HBM bytes of one fused step: row_ptr, col_idx (+ weights), X_t read once,
-    X_t+1 written once, one double per (graph, column) of cut results."""
+    X_t+1 written once (C = active columns), one double per (graph, column) of cut results."""
     return 4 * (n + G) + (4 + s_w) * nnz + 2 * s_x * n * C + 8 * C * G
 
 
-def time_step_kernel(deco, torch, G, B, l, dtype, steps, eta=0.01, seed=1):
-    """Average duration per launch of the fused step kernel, HIP events on its stream."""
-    lifted = l > 1
-    h = deco.Handle(G, B=B, l=l, lifted=lifted, x_dtype=dtype, eta=eta, seed=seed)
-    h.start(deco.INIT_IDI, scale=1e4, sigma2=0.8, batch=0)
+def parse_schedule(s):
+    return {k: v for k, v in (tok.split("=", 1) for tok in s.split() if "=" in tok)}
+
+
+def pin_args(sched, dtype_bf16, l):
+    """set_schedule arguments reproducing a schedule string."""
+    d = parse_schedule(sched)
+    vec = int(d["vec"])
+    lane_elems = 4 if (dtype_bf16 and l == 1 and vec == 4) else 0
+    return (int(d["Wc"]), int(d["dlong"]), int(d["xcd_mode"]), int(d["grid"]) // 8, int(d["nnz_per_item"]),
+            lane_elems)
+
+
+def time_step_kernel(deco, torch, G, B, l, dtype, steps, l_active=None, pin=None, eta=0.01, seed=1):
+    """Average duration per launch (ms) of the fused step kernel, HIP events on the handle's
+    stream; the schedule is the cached autotune winner of the shape unless pinned."""
+    h = deco.Handle(G, B=B, l=l, lifted=l > 1, x_dtype=dtype, eta=eta, seed=seed)
+    if pin is not None:
+        h.set_schedule(*pin)
+    h.start(deco.INIT_IDI, scale=1e4, sigma2=0.8, batch=0, l_active=l_active)
     h.step(steps, use_graph=True)  # capture + warm
     h.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -101,6 +124,7 @@ def other_workloads(deco, synth, torch, which):
         out["er800_B16_f32"] = {"us_per_step": round(us, 3), "edge_updates_per_s": g.nnz * 16 / us * 1e6,
                                 "hbm_frac": round(A / us / 1e3 / HBM_PEAK_GBS, 4), "schedule": h.schedule()}
         h.destroy()
+        log(f"er800: {us:.2f} us/step")
     if "uneven" in which:
         g = synth.uneven_batch(512, 7)
         h = deco.Handle(deco.Graph(g), B=64, x_dtype=deco.BF16, eta=0.01)
@@ -111,6 +135,7 @@ def other_workloads(deco, synth, torch, which):
                                      "hbm_frac": round(A / us / 1e3 / HBM_PEAK_GBS, 4), "n": g.n, "nnz": g.nnz,
                                      "schedule": h.schedule()}
         h.destroy()
+        log(f"uneven batch: {us:.1f} us/step")
     if "reg3" in which:
         g = synth.with_rademacher_weights(synth.random_regular3(1_000_000, 0), 3)
         h = deco.Handle(deco.Graph(g), B=128, x_dtype=deco.BF16, eta=0.01)
@@ -122,6 +147,7 @@ def other_workloads(deco, synth, torch, which):
                                          "hbm_frac": round(A / us / 1e3 / HBM_PEAK_GBS, 4),
                                          "bytes_per_launch": A, "schedule": h.schedule()}
         h.destroy()
+        log(f"3-regular: {us:.1f} us/step")
     if "dense" in which:
         g = synth.erdos_renyi(8192, 0.5, 0)
         W = torch.zeros((g.n, g.n), dtype=torch.float32, device="cuda")
@@ -138,12 +164,14 @@ def other_workloads(deco, synth, torch, which):
                                               "edge_updates_per_s": g.nnz * 512 / us * 1e6,
                                               "flop_per_launch": flop}
         h.destroy()
+        log(f"dense: {us:.1f} us/step")
     return out
 
 
-def kernel_only(deco, torch, G, B, l_max, dtype, args):
-    """Counter runs: the step kernel of one bench shape with its autotuned schedule, or a
-    plain 256 MiB device-to-device copy (the calibration of the traffic counters)."""
+def kernel_only(deco, torch, G, B, args):
+    """Counter runs: the step kernel of one bench shape with a pinned schedule (the one the
+    bench timed), or a plain 256 MiB device-to-device copy (the calibration of the traffic
+    counters)."""
     if args.kernel_only == "copy":
         a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -152,58 +180,252 @@ def kernel_only(deco, torch, G, B, l_max, dtype, args):
         torch.cuda.synchronize()
         print(f"# copied {a.numel() * 4} bytes x {args.kernel_steps}", flush=True)
         return
-    l = 1 if args.kernel_only == "unlifted" else l_max
+    import numpy as np
+    dtype = deco.BF16 if args.storage == "bf16" else deco.F32
+    l = 1 if args.kernel_only == "unlifted" else args.l
+    la = None
+    if l > 1 and args.l_active:
+        la = np.full(B, args.l_active, np.int32)
     h = deco.Handle(G, B=B, l=l, lifted=l > 1, x_dtype=dtype, eta=0.01, seed=1)
-    h.autotune(10)
-    h.start(deco.INIT_IDI, scale=1e4, sigma2=0.8, batch=0)
+    if args.pin:
+        h.set_schedule(*[int(v) for v in args.pin.split(",")])
+    else:
+        h.autotune(10)
+    h.start(deco.INIT_IDI, scale=1e4, sigma2=0.8, batch=0, l_active=la)
     h.synchronize()
     h.step(args.kernel_steps)
     h.synchronize()
-    print(f"# {args.kernel_only}: {args.kernel_steps} launches, schedule {h.schedule()}", flush=True)
+    print(f"# {args.kernel_only} l={l} l_active={args.l_active} {args.storage}: {args.kernel_steps} launches, "
+          f"schedule {h.schedule()}", flush=True)
     h.destroy()
 
 
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(oracle, csr, B, budget_s):
-    """The oracle's batch (step + rounding + exact cut + running best per step, FP64,
-    one thread) on the same graph, for as many steps as fit in about budget_s seconds."""
+    """The oracle's batch (FP64 step + rounding + exact cut + running best per step) on the same
+    graph, unlifted, B initialisations: one thread, and all usable cores with the columns split
+    into one contiguous chunk per thread (the columns are independent; ctypes releases the
+    interpreter lock during each call). Steps are chosen so each run takes about budget_s."""
     import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
     g = oracle.Graph(csr)
     x0 = np.random.default_rng(0).uniform(-1e-4, 1e-4, (csr.n, B))
     t0 = time.perf_counter()
     oracle.run_batch(g, x0, B, 1, False, 0.01, 1)
     one = time.perf_counter() - t0
-    k = max(1, int(budget_s / max(one, 1e-6)))
+    k1 = max(1, int(budget_s / max(one, 1e-6)))
     t0 = time.perf_counter()
-    oracle.run_batch(g, x0, B, 1, False, 0.01, k)
+    oracle.run_batch(g, x0, B, 1, False, 0.01, k1)
+    dt1 = time.perf_counter() - t0
+    v1 = csr.nnz * B * k1 / dt1
+    nproc = os.cpu_count() or 1
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else nproc
+    threads = max(1, min(16, usable, B))
+    chunks = np.array_split(np.arange(B), threads)
+    kp = max(1, int(k1 * threads * 0.8))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda c: oracle.run_batch(g, np.ascontiguousarray(x0[:, c]), len(c), 1, False, 0.01, kp),
+                    chunks))
+    dtp = time.perf_counter() - t0
+    vp = csr.nnz * B * kp / dtp
+    return {"value": vp, "unit": "edge-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{kp} oracle steps (FP64 step + rounding + exact cut + running best, unlifted, B={B}) on the "
+                      f"bench's BA graph, columns split over {threads} threads, {dtp:.1f}s",
+            "single_thread": {"value": v1, "steps": k1, "seconds": round(dt1, 2)},
+            "host": {"nproc": nproc, "usable_cpus": usable, "model": cpu_model()}}
+
+
+def solver_arm(deco, torch, G, B, K, l_max, args, dtype, seed, warmup, rounds):
+    """One pDECO run: warm-up rounds, then 'rounds' timed rounds; edge-updates/s over the timed
+    rounds (active work only) and the run's results."""
+    solver = deco.Solver(G, B=B, K=K, l_max=l_max, evo_rounds=2, T_q=args.Tq, T_l=args.Tl, x_dtype=dtype,
+                         init_kind=deco.INIT_IDI, seed=seed, use_graph=True, autotune=not args.no_autotune)
+    w = solver.run(warmup) if warmup > 0 else None
+    eu0 = w["edge_updates"] if w else 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = solver.run(rounds)
+    torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return csr.nnz * B * k / dt, k, dt
+    solver.destroy()
+    eu = res["edge_updates"] - eu0
+    return {"value": eu / dt, "seconds": dt, "edge_updates": eu, "rounds": res["rounds_done"],
+            "ms_per_round": dt / max(res["rounds_done"], 1) * 1e3, "best_cut": float(res["best_cut"][0]),
+            "genes": [res["eq_best"], res["el_best"], res["l_best"]]}
+
+
+def bf16_error_report(deco, torch, G, csr, B, steps=4):
+    """Per-step error of bfloat16 storage with float32 accumulation: the GPU's X_t+1 against
+    the exact step from the GPU's own X_t (float64 on the host: clip(X + eta (-1/2) W X)),
+    rounded to float32 and then to bfloat16 (round to nearest even), in bfloat16 ulps of the
+    larger of the two values, on the bench's graph and batch (unlifted, and lifted l = 4), from
+    the solver's kind of start (importance-based signs plus noise, scaled by 1e-4); also the
+    count of elements off by more than one ulp plus the row's float32 summation bound."""
+    import numpy as np
+    import scipy.sparse as sps
+    W = sps.csr_matrix((np.ones(csr.nnz), csr.col_idx.astype(np.int64), csr.row_ptr.astype(np.int64)),
+                       shape=(csr.n, csr.n))
+
+    def ulp(x):
+        a = np.maximum(np.abs(x), 2.0 ** -126)
+        return 2.0 ** (np.floor(np.log2(a)) - 7)
+
+    cw = 0.5
+    gamma = np.maximum(np.diff(csr.row_ptr.astype(np.int64)), 1)[:, None] * 2.0 ** -24
+
+    out = {}
+    for l, eta in ((1, 10 ** -1.5), (4, 10 ** -2.0)):
+        h = deco.Handle(G, B=B, l=l, lifted=l > 1, x_dtype=deco.BF16, eta=eta, seed=3)
+        h.start(deco.INIT_IDI, scale=1e4, sigma2=0.8, batch=0)
+        x = h.read_x().float().cpu().numpy().astype(np.float64)
+        rows = []
+        for _ in range(steps):
+            h.step(1)
+            xn = h.read_x().float().cpu().numpy().astype(np.float64)
+            exact = np.clip(x + eta * (-cw) * (W @ x), -1.0, 1.0)
+            emu = torch.from_numpy(exact.astype(np.float32)).to(torch.bfloat16).float().numpy().astype(np.float64)
+            diff = np.abs(xn - emu)
+            d = diff / ulp(np.maximum(np.abs(emu), np.abs(xn)))
+            # float32 summation bound of the row (Higham, Sec. 3.1), in the same ulps
+            bound = eta * cw * gamma * (W @ np.abs(x))
+            rows.append({"max_ulp": float(d.max()), "mean_ulp": float(d.mean()),
+                         "frac_not_equal": float((xn != emu).mean()), "max_abs": float(diff.max()),
+                         "beyond_1ulp_plus_f32_bound": int((diff > ulp(emu) + bound).sum())})
+            x = xn
+        h.destroy()
+        out[f"l{l}"] = rows
+    return out
+
+
+def load_mpnn(deco):
+    import numpy as np
+    if not os.path.exists(MPNN_WEIGHTS):
+        return None
+    return deco.Mpnn(np.load(MPNN_WEIGHTS, allow_pickle=False).astype(np.float32))
+
+
+def time_to_cut(deco, synth, torch, csr, B, K, l_max, args):
+    """Time to a cut within 0.5% of the plain float32 method's best. Reference: plain float32
+    pDECO (importance-based start, one graph per launch) for args.ref_rounds rounds gives
+    best_plain; targets 0.995 best_plain (the metric's) and best_plain itself. Every run is
+    timed from solver creation (validation, schedule, start; the network's forward pass for
+    learned starts; graph upload excluded) until its best reaches the target: the solver checks
+    the target every args.check_every steps inside each batch and stops there. 5 seeds per arm
+    (median reported, every seed listed); a run that does not reach the target within
+    args.ttc_rounds rounds counts as not reached. Batched: the 5 seeds as 5 copies of the graph
+    in one block-diagonal batch (one launch per step for all of them), timed until every copy
+    reached the target."""
+    import numpy as np
+    G1 = deco.Graph(csr)
+    ref = deco.Solver(G1, B=B, K=K, l_max=l_max, evo_rounds=2, T_q=args.Tq, T_l=args.Tl, x_dtype=deco.F32,
+                      init_kind=deco.INIT_IDI, seed=1000, use_graph=True, autotune=not args.no_autotune)
+    t0 = time.perf_counter()
+    r = ref.run(args.ref_rounds)
+    ref_s = time.perf_counter() - t0
+    ref.destroy()
+    best_plain = float(r["best_cut"][0])
+    targets = {"0.995": 0.995 * best_plain, "1.0": best_plain}
+    log(f"time-to-cut reference: {best_plain:.0f} after {args.ref_rounds} float32 rounds ({ref_s:.1f}s)")
+    net = load_mpnn(deco)
+    seeds = list(range(1, 6))
+    Gb = deco.Graph(synth.block_diagonal([csr] * len(seeds))) if net is not None else None
+    if net is not None:
+        # untimed warm-up: schedule cache of the batched shape, network kernels
+        s = deco.Solver(Gb, B=B, K=K, l_max=l_max, evo_rounds=2, T_q=args.Tq, T_l=args.Tl, x_dtype=deco.BF16,
+                        init_kind=deco.INIT_IDI, seed=0, use_graph=True, autotune=not args.no_autotune)
+        s.destroy()
+        net.forward(G1)
+        net.forward(Gb)
+
+    def run_arm(graph, dtype, kind, seed, G, target):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mag = net.forward(graph) if kind == deco.INIT_LEARNED else None
+        s = deco.Solver(graph, B=B, K=K, l_max=l_max, evo_rounds=2, T_q=args.Tq, T_l=args.Tl, x_dtype=dtype,
+                        init_kind=kind, seed=seed, use_graph=True, target_cut=[target] * G,
+                        autotune=not args.no_autotune, magnitude=mag, check_every=args.check_every)
+        rr = s.run(args.ttc_rounds)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s.destroy()
+        reached = bool(np.all(rr["best_cut"] >= target))
+        return (dt if reached else None), rr
+
+    result = {"best_plain_f32": best_plain, "reference_rounds": args.ref_rounds, "reference_seconds": ref_s,
+              "targets": targets, "max_rounds_per_run": args.ttc_rounds, "check_every_steps": args.check_every,
+              "seeds": seeds, "round_steps": args.Tq + args.Tl}
+    arms = [("f32", deco.F32, deco.INIT_IDI), ("bf16", deco.BF16, deco.INIT_IDI)]
+    if net is not None:
+        arms.append(("bf16_learned", deco.BF16, deco.INIT_LEARNED))
+    for name, dtype, kind in arms:
+        result[name] = {}
+        for tname, tv in targets.items():
+            secs, steps = [], []
+            for sd in seeds:
+                dt, rr = run_arm(G1, dtype, kind, sd, 1, tv)
+                secs.append(None if dt is None else round(dt, 4))
+                steps.append(int(rr["steps_done"]))
+            hit = [v for v in secs if v is not None]
+            result[name][tname] = {"median_s": float(np.median(hit)) if len(hit) * 2 > len(secs) else None,
+                                   "reached": f"{len(hit)}/{len(secs)}", "seconds": secs,
+                                   "gradient_steps": steps}
+        log(f"time-to-cut {name}: {result[name]}")
+    if net is not None:
+        result["bf16_learned_batched"] = {"note": f"{len(seeds)} copies of the graph in one block-diagonal batch; "
+                                                  "seconds until every copy reached the target"}
+        for tname, tv in targets.items():
+            dt, rr = run_arm(Gb, deco.BF16, deco.INIT_LEARNED, seeds[0], len(seeds), tv)
+            result["bf16_learned_batched"][tname] = {
+                "seconds_all_copies": None if dt is None else round(dt, 4),
+                "copies_reached": int(np.sum(rr["best_cut"] >= tv)), "gradient_steps": int(rr["steps_done"])}
+        log(f"time-to-cut bf16_learned_batched: {result['bf16_learned_batched']}")
+    else:
+        result["learned"] = f"no trained weights at {os.path.relpath(MPNN_WEIGHTS, ROOT)}"
+    return result
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4, help="timed lift-and-project rounds")
+    ap.add_argument("--steps", type=int, default=8, help="timed lift-and-project rounds")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--storage", choices=["bf16", "f32"], default="bf16")
     ap.add_argument("--B", type=int, default=256)
     ap.add_argument("--Tq", type=int, default=1000)
     ap.add_argument("--Tl", type=int, default=400)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttc", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--ref-rounds", type=int, default=200, help="rounds of the time-to-cut reference run")
+    ap.add_argument("--ttc-rounds", type=int, default=30, help="round cap of each time-to-cut run")
+    ap.add_argument("--check-every", type=int, default=50, help="time-to-cut runs check the target every this "
+                                                                 "many steps")
     ap.add_argument("--kernel-steps", type=int, default=200)
     ap.add_argument("--others", default="er800,uneven,reg3,dense",
                     help="comma list of other workload shapes to time (empty: none)")
     ap.add_argument("--kernel-only", choices=["unlifted", "lifted", "copy"], default=None,
-                    help="run only the step kernel of that shape (autotuned as in the bench) for "
-                         "--kernel-steps launches, or a 256 MiB device copy, for counter runs")
+                    help="run only the step kernel of that shape for --kernel-steps launches (schedule pinned "
+                         "by --pin, else autotuned), or a 256 MiB device copy, for counter runs")
+    ap.add_argument("--storage", choices=["bf16", "f32"], default="f32", help="--kernel-only: X storage")
+    ap.add_argument("--l", type=int, default=4, help="--kernel-only lifted: components")
+    ap.add_argument("--l-active", type=int, default=0, help="--kernel-only lifted: active components (0: all)")
+    ap.add_argument("--pin", default="", help="--kernel-only: set_schedule arguments, comma separated")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1",
-                          "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark measures one GPU; multi-GPU runs are not part of it "
+                                   "(--gpus must be 1)", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np
@@ -215,107 +437,87 @@ def main():
     n, m, B = 10_000, 4, args.B
     csr = synth.barabasi_albert(n, m, 0)
     G = deco.Graph(csr)
-    dtype = deco.BF16 if args.storage == "bf16" else deco.F32
     K, l_max = 8, 4
     if args.kernel_only:
-        kernel_only(deco, torch, G, B, l_max, dtype, args)
+        kernel_only(deco, torch, G, B, args)
         return
-    print(f"# graph BA({n},{m}) nnz={csr.nnz}; B={B}; storage={args.storage}", file=sys.stderr, flush=True)
+    log(f"graph BA({n},{m}) nnz={csr.nnz}; B={B}")
 
-    # the first solver of a shape autotunes both step kernels; later handles of the same
-    # shape (the kernel timing and time-to-cut below) reuse the cached winner
-    solver = deco.Solver(G, B=B, K=K, l_max=l_max, evo_rounds=2, T_q=args.Tq, T_l=args.Tl, x_dtype=dtype,
-                         init_kind=deco.INIT_IDI, seed=0, use_graph=True, autotune=not args.no_autotune)
-    w = solver.run(args.warmup) if args.warmup > 0 else None
-    eu0 = w["edge_updates"] if w else 0.0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = solver.run(args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    solver.destroy()
-    dt = t1 - t0
-    eu = res["edge_updates"] - eu0
-    value = eu / dt
-    print(f"# timed {args.steps} rounds in {dt:.3f}s; best cut {res['best_cut'][0]:.0f}", file=sys.stderr,
-          flush=True)
+    # the first solver of a shape autotunes both step kernels; later handles of the same shape
+    # (the kernel timing and time-to-cut below) reuse the cached winner
+    arm32 = solver_arm(deco, torch, G, B, K, l_max, args, deco.F32, 0, args.warmup, args.steps)
+    log(f"float32 storage: {arm32['value']:.3e} EU/s, {arm32['ms_per_round']:.1f} ms/round, best {arm32['best_cut']:.0f}")
+    arm16 = solver_arm(deco, torch, G, B, K, l_max, args, deco.BF16, 0, args.warmup, args.steps)
+    log(f"bfloat16 storage: {arm16['value']:.3e} EU/s, {arm16['ms_per_round']:.1f} ms/round, best {arm16['best_cut']:.0f}")
 
-    # live roofline of the two step-kernel shapes of a round
-    s_x = 2 if dtype == deco.BF16 else 4
-    ms_q, sched_q = time_step_kernel(deco, torch, G, B, 1, dtype, args.kernel_steps)
-    ms_l, sched_l = time_step_kernel(deco, torch, G, B, l_max, dtype, args.kernel_steps)
-    A_q = algorithmic_bytes(n, csr.nnz, B, 1, s_x, 0)
-    A_l = algorithmic_bytes(n, csr.nnz, B * l_max, 1, s_x, 0)
-    share_q = args.Tq * ms_q
-    share_l = args.Tl * ms_l
-    dom_ms, dom_A, dom_name = (ms_l, A_l, f"k_step lifted l={l_max}") if share_l >= share_q else \
-        (ms_q, A_q, "k_step unlifted")
-    achieved = dom_A / (dom_ms * 1e-3) / 1e9
+    # live roofline of the step kernels of the float32 run (lifted: the final genes' active count)
+    l_act = int(arm32["genes"][2])
+    la = np.full(B, l_act, np.int32)
+    kern = {}
+    for tag, dtype, s_x in (("f32", deco.F32, 4), ("bf16", deco.BF16, 2)):
+        ms_q, sched_q = time_step_kernel(deco, torch, G, B, 1, dtype, args.kernel_steps)
+        ms_l, sched_l = time_step_kernel(deco, torch, G, B, l_max, dtype, args.kernel_steps, l_active=la)
+        A_q = algorithmic_bytes(n, csr.nnz, B, 1, s_x, 0)
+        A_l = algorithmic_bytes(n, csr.nnz, B * l_act, 1, s_x, 0)
+        kern[tag] = {"unlifted": {"us": ms_q * 1e3, "bytes": A_q, "schedule": sched_q,
+                                  "pin": pin_args(sched_q, dtype == deco.BF16, 1)},
+                     "lifted": {"us": ms_l * 1e3, "bytes": A_l, "schedule": sched_l, "l": l_max, "l_active": l_act,
+                                "pin": pin_args(sched_l, dtype == deco.BF16, l_max)}}
+        log(f"{tag} step kernels: unlifted {ms_q * 1e3:.2f} us, lifted (l={l_max}, {l_act} active) {ms_l * 1e3:.2f} us")
+    k32 = kern["f32"]
+    share_q = args.Tq * k32["unlifted"]["us"]
+    share_l = args.Tl * k32["lifted"]["us"]
+    dom = "lifted" if share_l >= share_q else "unlifted"
+    dk = k32[dom]
+    achieved = dk["bytes"] / (dk["us"] * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic("lifted" if dom_name.startswith("k_step lifted") else "unlifted"),
-                "kernel": dom_name, "bytes_per_launch": dom_A, "us_per_launch": round(dom_ms * 1e3, 3)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(f"f32 {dom}"),
+                "kernel": f"k_step {dom} f32" + (f" l={l_max} ({l_act} active)" if dom == "lifted" else ""),
+                "bytes_per_launch": dk["bytes"], "us_per_launch": round(dk["us"], 3),
+                "schedule": dk["schedule"]}
 
     cpu = None
     if not args.no_cpu:
         import oracle
-        v, k, cdt = cpu_baseline(oracle, csr, B, args.cpu_seconds)
-        cpu = {"value": v, "unit": "edge-updates/s", "cores": 1, "kind": "oracle",
-               "sample": f"{k} oracle steps (FP64 step + rounding + exact cut + running best, unlifted, "
-                         f"B={B}) on the same BA graph, {cdt:.1f}s on 1 thread"}
+        cpu = cpu_baseline(oracle, csr, B, args.cpu_seconds)
+        log(f"cpu oracle: {cpu['value']:.3e} EU/s on {cpu['cores']} threads, "
+            f"{cpu['single_thread']['value']:.3e} on 1")
+
+    err = bf16_error_report(deco, torch, G, csr, B)
+    log(f"bf16 error report: {err}")
 
     others = other_workloads(deco, synth, torch, set(filter(None, args.others.split(","))))
     ttc = None
     if not args.no_ttc:
-        ttc = time_to_cut(deco, torch, G, B, K, l_max, args)
+        ttc = time_to_cut(deco, synth, torch, csr, B, K, l_max, args)
 
     line = {
-        "metric": METRIC, "value": value, "unit": "edge-updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": dt / max(res["rounds_done"], 1) * 1e3, "higher_is_better": True,
+        "metric": METRIC, "value": arm32["value"], "unit": "edge-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": arm32["ms_per_round"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"pDECO on BA(n={n},m={m}) unit weights, B={B}, population {K}, l_max={l_max}, "
-                               f"T_q={args.Tq}, T_l={args.Tl} per round",
-                   "x_storage": args.storage, "accumulate": "f32", "global_batch": B, "graphs": 1,
-                   "nnz": csr.nnz},
+                               f"T_q={args.Tq}, T_l={args.Tl} per round; float32 X storage and arithmetic",
+                   "x_storage": "f32", "accumulate": "f32", "global_batch": B, "graphs": 1, "nnz": csr.nnz,
+                   "edge_updates": "nnz x active columns per member step (B/K columns x own lift dimension)"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "time_to_cut": ttc,
-        "extra": {"step_kernel_us": {"unlifted": round(ms_q * 1e3, 3), "lifted": round(ms_l * 1e3, 3)},
-                  "hbm_frac": {"unlifted": round(A_q / (ms_q * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                               "lifted": round(A_l / (ms_l * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
-                  "schedule": {"unlifted": sched_q, "lifted": sched_l},
-                  "best_cut": float(res["best_cut"][0]), "genes": [res["eq_best"], res["el_best"], res["l_best"]],
-                  "workloads": others},
+        "extra": {
+            "bf16_storage_f32_accumulate": {"value": arm16["value"], "unit": "edge-updates/s",
+                                            "ms_per_round": arm16["ms_per_round"], "best_cut": arm16["best_cut"],
+                                            "genes": arm16["genes"]},
+            "f32_run": {"best_cut": arm32["best_cut"], "genes": arm32["genes"], "rounds": arm32["rounds"],
+                        "seconds": arm32["seconds"]},
+            "bf16_error": {"per_step_vs_exact_step_rounded": err,
+                           "best_cut_f32_minus_bf16": arm32["best_cut"] - arm16["best_cut"],
+                           "note": "same seed and rounds; bf16 X storage, f32 accumulation"},
+            "step_kernels": {t: {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in d.items()}
+                                 for k, d in v.items()} for t, v in kern.items()},
+            "hbm_frac": {f"{t} {k}": round(d["bytes"] / (d["us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+                         for t, v in kern.items() for k, d in v.items()},
+            "workloads": others},
     }
     print(json.dumps(line), flush=True)
-
-
-def time_to_cut(deco, torch, G, B, K, l_max, args):
-    """Reference: plain float32 pDECO for a fixed 8 rounds gives best_plain; target = 0.995
-    best_plain. Each variant is timed from solver creation to the first round whose best
-    reaches the target (at most 12 rounds)."""
-    import numpy as np
-    ref = deco.Solver(G, B=B, K=K, l_max=l_max, evo_rounds=2, T_q=args.Tq, T_l=args.Tl, x_dtype=deco.F32,
-                      init_kind=deco.INIT_IDI, seed=1, use_graph=True, autotune=not args.no_autotune)
-    r = ref.run(8)
-    ref.destroy()
-    best_plain = float(r["best_cut"][0])
-    target = 0.995 * best_plain
-    out = {"best_plain_f32": best_plain, "target": target, "reference_rounds": 8}
-    for name, dt in [("f32", deco.F32), ("bf16", deco.BF16)]:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s = deco.Solver(G, B=B, K=K, l_max=l_max, evo_rounds=2, T_q=args.Tq, T_l=args.Tl, x_dtype=dt,
-                        init_kind=deco.INIT_IDI, seed=2, use_graph=True, target_cut=[target],
-                        autotune=not args.no_autotune)
-        rr = s.run(12)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        s.destroy()
-        reached = bool(rr["best_cut"][0] >= target)
-        out[name] = {"seconds": t1 - t0 if reached else None, "reached": reached,
-                     "rounds": rr["rounds_done"], "best": float(rr["best_cut"][0])}
-    return out
 
 
 if __name__ == "__main__":

@@ -233,7 +233,8 @@ void deco_destroy(deco_handle *h);
  * evo_rounds rounds evolve the population (rank, keep the top half, perturb it into the
  * bottom half); later rounds use the best member's genes everywhere. The loop stops after
  * 'rounds' rounds, when 'time_budget_s' (> 0) is spent, or when every graph's best
- * reaches target_cut[g] (if target_cut != NULL). Allocates and frees its own device
+ * reaches target_cut[g] (if target_cut != NULL; checked after every round, or every
+ * check_every steps). Allocates and frees its own device
  * memory. Outputs (HOST): best cut per graph [G], its bits z[n] (bytes in {0,1}),
  * per-round wall time since the start [rounds] and best cut per graph [rounds*G].
  * --------------------------------------------------------------------------------- */
@@ -268,6 +269,11 @@ typedef struct deco_solve_params {
                              (e.g. from deco_mpnn_forward), read by the first batch of every
                              run of a solver, so it must stay valid while the solver exists;
                              NULL otherwise */
+  int32_t check_every;  /* > 0 with target_cut: every batch also pauses every check_every steps
+                           to compare the graphs' bests with their targets (one synchronisation
+                           each) and the run ends as soon as every graph reached its target, in
+                           the middle of a round if need be; 0: targets are checked after each
+                           round */
 } deco_solve_params;
 
 typedef struct deco_solve_report {

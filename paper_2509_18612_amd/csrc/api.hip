@@ -1123,17 +1123,40 @@ void solver_free(deco_solver* v) {
 // distinct counts, and a member whose count is reached keeps its columns still with a step of
 // 0 (the projection leaves an iterate inside the box unchanged). eta holds the members' steps
 // and is zeroed in place as they finish. Returns the longest count through *tmax.
+// With targets and check_every > 0, the batch also pauses every check_every steps and ends as
+// soon as every graph's best (this batch's or an earlier one's) reaches its target (*hit).
 deco_status run_counts(deco_solver* v, deco_handle* h, std::vector<float>& eta, const std::vector<int32_t>& T,
-                       int* tmax) {
+                       int* tmax, bool* hit) {
   std::vector<int32_t> ends(T);
   std::sort(ends.begin(), ends.end());
   ends.erase(std::unique(ends.begin(), ends.end()), ends.end());
+  const int last = ends.empty() ? 0 : ends.back();
+  const bool check = v->p.check_every > 0 && !v->target.empty();
+  std::vector<int32_t> stops(ends);
+  if (check)
+    for (int c = v->p.check_every; c < last; c += v->p.check_every) stops.push_back(c);
+  std::sort(stops.begin(), stops.end());
+  stops.erase(std::unique(stops.begin(), stops.end()), stops.end());
   deco_status st;
   int done = 0;
-  for (int32_t e : ends) {
+  *hit = false;
+  for (int32_t e : stops) {
     if (e > done && (st = deco_step(h, e - done, v->p.use_graph))) return st;
     done = std::max(done, (int)e);
-    if (e == ends.back()) break;
+    if (e == last) break;
+    if (check) {
+      if ((st = deco_best(h, v->bc.data(), nullptr, nullptr))) return st;
+      bool all = true;
+      for (int gi = 0; gi < v->G && all; ++gi) {
+        double best = v->gbest[gi];
+        for (int b = 0; b < v->B; ++b) best = std::max(best, v->bc[(size_t)gi * v->B + b]);
+        all = best >= v->target[gi];
+      }
+      if (all) {
+        *hit = true;
+        break;
+      }
+    }
     bool changed = false;
     for (int b = 0; b < v->B; ++b)
       if (T[b / v->per] == e && eta[b] != 0.0f) {
@@ -1185,7 +1208,8 @@ deco_status deco_solver_create(deco_solver** out, const deco_graph* g, const dec
   if (!sp) return DECO_E_INVAL;
   if (sp->K < 1 || sp->B < 1 || sp->B % sp->K != 0 || sp->l_max < 1 || sp->l_max > kMaxL || sp->T_q < 0 ||
       sp->T_l < 0 || sp->evo_rounds < 0 || !(sp->scale > 0.0) || !(sp->sigma2 >= 0.0) || sp->T_min < 0 ||
-      (sp->T_min > 0 && sp->T_min > sp->T_q) || sp->T_l_min < 0 || (sp->T_l_min > 0 && sp->T_l_min > sp->T_l))
+      (sp->T_min > 0 && sp->T_min > sp->T_q) || sp->T_l_min < 0 || (sp->T_l_min > 0 && sp->T_l_min > sp->T_l) ||
+      sp->check_every < 0)
     return DECO_E_INVAL;
   if (sp->init_kind != DECO_INIT_IDI && sp->init_kind != DECO_INIT_DUI && sp->init_kind != DECO_INIT_UNIFORM &&
       !(sp->init_kind == DECO_INIT_LEARNED && sp->magnitude))
@@ -1313,31 +1337,34 @@ deco_status deco_solver_run(deco_solver* v, int32_t rounds, double* best_cut, ui
     sa.batch = v->batch++;
     if ((st = deco_start(v->hq, &sa))) return st;
     int tmax = 0;
-    if ((st = run_counts(v, v->hq, v->eta, v->tq, &tmax))) return st;
+    bool hit = false;
+    if ((st = run_counts(v, v->hq, v->eta, v->tq, &tmax, &hit))) return st;
     if ((st = deco_round_score(v->hq, nullptr, nullptr))) return st;
     if ((st = absorb(v, v->hq))) return st;
     v->steps_done += tmax;
     // edge updates of the members' own steps (a member past its count keeps still)
-    for (int k = 0; k < K; ++k) v->eu += (double)v->g.nnz * v->per * v->tq[k];
+    for (int k = 0; k < K; ++k) v->eu += (double)v->g.nnz * v->per * std::min(v->tq[k], tmax);
     // 2. lift its best vector (Alg. 3 step 2) and run the lifted batch (Alg. 2); member k
     //    keeps lk[k] of the lmax components and steps with 10^el[k]; 3. project back
-    for (int b = 0; b < B; ++b) {
-      v->eta[b] = (float)std::pow(10.0, v->el[b / v->per]);
-      v->lact[b] = v->lk[b / v->per];
+    if (!hit) {
+      for (int b = 0; b < B; ++b) {
+        v->eta[b] = (float)std::pow(10.0, v->el[b / v->per]);
+        v->lact[b] = v->lk[b / v->per];
+      }
+      if ((st = deco_set_eta(v->hl, v->eta.data()))) return st;
+      sa.kind = DECO_INIT_MEAN;
+      sa.scale = sp.scale;
+      sa.batch = v->batch++;
+      sa.l_active = v->lact.data();
+      if ((st = deco_start(v->hl, &sa))) return st;
+      int tlmax = 0;
+      if ((st = run_counts(v, v->hl, v->eta, v->tl, &tlmax, &hit))) return st;
+      if ((st = deco_round_score(v->hl, nullptr, nullptr))) return st;
+      if ((st = absorb(v, v->hl))) return st;
+      v->steps_done += tlmax;
+      // active components only: components past a member's lift dimension stay exactly 0
+      for (int k = 0; k < K; ++k) v->eu += (double)v->g.nnz * v->per * v->lk[k] * std::min(v->tl[k], tlmax);
     }
-    if ((st = deco_set_eta(v->hl, v->eta.data()))) return st;
-    sa.kind = DECO_INIT_MEAN;
-    sa.scale = sp.scale;
-    sa.batch = v->batch++;
-    sa.l_active = v->lact.data();
-    if ((st = deco_start(v->hl, &sa))) return st;
-    int tlmax = 0;
-    if ((st = run_counts(v, v->hl, v->eta, v->tl, &tlmax))) return st;
-    if ((st = deco_round_score(v->hl, nullptr, nullptr))) return st;
-    if ((st = absorb(v, v->hl))) return st;
-    v->steps_done += tlmax;
-    // active components only: components past a member's lift dimension stay exactly 0
-    for (int k = 0; k < K; ++k) v->eu += (double)v->g.nnz * v->per * v->lk[k] * v->tl[k];
     for (int k = 0; k < K; ++k) {
       v->fit[k] = 0.0;
       for (int gi = 0; gi < G; ++gi) v->fit[k] += v->fitg[(size_t)k * G + gi];
@@ -1380,7 +1407,7 @@ deco_status deco_solver_run(deco_solver* v, int32_t rounds, double* best_cut, ui
     }
     v->round++;
     done_here++;
-    bool stop = sp.time_budget_s > 0 && now_s() - t_start >= sp.time_budget_s;
+    bool stop = hit || (sp.time_budget_s > 0 && now_s() - t_start >= sp.time_budget_s);
     if (!v->target.empty()) {
       bool all = true;
       for (int gi = 0; gi < G; ++gi) all = all && v->gbest[gi] >= v->target[gi];

@@ -81,25 +81,6 @@ __global__ void k_aggregate(long long n, const int* rp, const int* ci, const flo
   A[v * ld + j] = adjoint ? s : (end > beg ? s / (float)(end - beg) : 0.0f);
 }
 
-// Pre = H Ws + A Wn + b (weights rounded to bfloat16), Hout = relu(Pre). 64 outputs per row.
-__global__ __launch_bounds__(256) void k_linear(long long n, const float* H, const float* A, int ld, int dim,
-                                                const float* P, int ows, int own, int ob, float* Pre, float* Hout) {
-  __shared__ float sws[kH * kH], swn[kH * kH], sb[kH];
-  for (int i = threadIdx.x; i < dim * kH; i += blockDim.x) {
-    sws[i] = rbf16(P[ows + i]);
-    swn[i] = rbf16(P[own + i]);
-  }
-  for (int i = threadIdx.x; i < kH; i += blockDim.x) sb[i] = rbf16(P[ob + i]);
-  __syncthreads();
-  const long long v = (long long)blockIdx.x * (blockDim.x / kH) + threadIdx.x / kH;
-  const int j = threadIdx.x % kH;
-  if (v >= n) return;
-  float s = sb[j];
-  for (int i = 0; i < dim; ++i) s = fmaf(H[v * ld + i], sws[i * kH + j], fmaf(A[v * ld + i], swn[i * kH + j], s));
-  Pre[v * kH + j] = s;
-  Hout[v * kH + j] = fmaxf(s, 0.0f);
-}
-
 // y = sigmoid(H3 wo + bo); with a target, also dz = dL/dz and the per-row loss terms.
 __global__ void k_head(long long n, const float* H3, const float* P, const float* t, float* y, float* dz,
                        double* lossterm, double inv_n) {
@@ -125,8 +106,8 @@ __global__ void k_head_back(long long n, const float* dz, const float* P, const 
   dPre[i] = Pre3[i] > 0.0f ? dz[v] * rbf16(P[oWo + j]) : 0.0f;
 }
 
-// Stage 1 of a weight gradient G[i][j] = sum_v X[v][i] D[v][j] (i < dim, plus i == dim for
-// a column of ones, i.e. the bias), per workgroup over a contiguous row range.
+// Stage 1 of the head's weight gradient G[i][j] = sum_v X[v][i] D[v][j] (i < dim, plus i ==
+// dim for a column of ones, i.e. the bias), per workgroup over a contiguous row range.
 __global__ __launch_bounds__(256) void k_wgrad_partial(long long n, const float* Xm, int ldx, int dim,
                                                        const float* D, int ldd, int dout, float* part) {
   const long long per = (n + gridDim.x - 1) / gridDim.x;
@@ -154,26 +135,201 @@ __global__ void k_wgrad_final(const float* part, int nparts, int dim, int dout, 
     gb[j] = (float)s;
 }
 
-// T1 = dPre Ws^T, T2 = dPre Wn^T (rows x dim), weights rounded to bfloat16.
-__global__ __launch_bounds__(256) void k_dinput(long long n, const float* dPre, const float* P, int ows, int own,
-                                                int dim, float* T1, float* T2, int ld) {
-  __shared__ float sws[kH * kH], swn[kH * kH];
-  for (int i = threadIdx.x; i < dim * kH; i += blockDim.x) {
-    sws[i] = rbf16(P[ows + i]);
-    swn[i] = rbf16(P[own + i]);
+// ---------------------------------------------------------------- matrix-core versions
+// The three dense products of a layer run on the matrix cores with float32 operands and
+// accumulation (v_mfma_f32_32x32x2f32): the weights are the bfloat16-rounded parameters, the
+// activations stay float32. Operand layout of one 32 x 32 x 2 step for lane (lo, hi) =
+// (lane % 32, lane / 32): A[lo][k0 + hi] and B[k0 + hi][lo]; element r of the 16 results is
+// row 8 (r / 4) + 4 hi + r % 4, column lo.
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+constexpr int kTile = 64;      // nodes per tile
+constexpr int kWgBlocks = 256; // workgroups (partial sums) of a weight gradient
+
+__device__ __forceinline__ int mfma_row(int r, int hi) { return 8 * (r >> 2) + 4 * hi + (r & 3); }
+
+// Pre = [H | A] [Ws; Wn] + b, Hout = relu(Pre): each workgroup stages the concatenated
+// weights once and walks tiles of 64 nodes; wave (wm, wn) computes nodes 32 wm.. and
+// outputs 32 wn.. of a tile.
+__global__ __launch_bounds__(256) void k_linear_mfma(long long n, const float* H, const float* A, int ld, int dim,
+                                                     const float* P, int ows, int own, int ob, float* Pre,
+                                                     float* Hout) {
+  __shared__ float sw[2 * kH][kH];
+  __shared__ float sb[kH];
+  __shared__ float sx[kTile][2 * kH + 1];  // odd row stride: a column read hits 32 banks
+  const int K = 2 * dim, Kp = (K + 1) & ~1;
+  for (int i = threadIdx.x; i < Kp * kH; i += blockDim.x) {
+    const int k = i / kH, j = i % kH;
+    float w = 0.0f;
+    if (k < dim)
+      w = rbf16(P[ows + k * kH + j]);
+    else if (k < K)
+      w = rbf16(P[own + (k - dim) * kH + j]);
+    sw[k][j] = w;
   }
-  __syncthreads();
-  const long long v = (long long)blockIdx.x * (blockDim.x / kH) + threadIdx.x / kH;
-  const int i = threadIdx.x % kH;
-  if (v >= n || i >= dim) return;
-  float s1 = 0.0f, s2 = 0.0f;
-  for (int j = 0; j < kH; ++j) {
-    const float d = dPre[v * kH + j];
-    s1 = fmaf(d, sws[i * kH + j], s1);
-    s2 = fmaf(d, swn[i * kH + j], s2);
+  for (int i = threadIdx.x; i < kH; i += blockDim.x) sb[i] = rbf16(P[ob + i]);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lo = lane & 31, hi = lane >> 5;
+  const int wm = wv >> 1, wn = wv & 1;
+  const long long ntiles = (n + kTile - 1) / kTile;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long v0 = tile * kTile;
+    __syncthreads();  // the previous tile is consumed (first pass: the weights are staged)
+    for (int i = threadIdx.x; i < kTile * Kp; i += blockDim.x) {
+      const int r = i / Kp, k = i % Kp;
+      const long long v = v0 + r;
+      float x = 0.0f;
+      if (v < n) {
+        if (k < dim)
+          x = H[v * ld + k];
+        else if (k < K)
+          x = A[v * ld + (k - dim)];
+      }
+      sx[r][k] = x;
+    }
+    __syncthreads();
+    f32x16_t acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    for (int k0 = 0; k0 < Kp; k0 += 2)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(sx[wm * 32 + lo][k0 + hi], sw[k0 + hi][wn * 32 + lo], acc, 0, 0,
+                                                 0);
+    const int j = wn * 32 + lo;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const long long v = v0 + wm * 32 + mfma_row(r, hi);
+      if (v < n) {
+        const float y = acc[r] + sb[j];
+        Pre[v * kH + j] = y;
+        Hout[v * kH + j] = fmaxf(y, 0.0f);
+      }
+    }
   }
-  T1[v * ld + i] = s1;
-  T2[v * ld + i] = s2;
+}
+
+// T1 = dPre Ws^T, T2 = dPre Wn^T for a hidden layer (64 inputs): B = [Ws^T | Wn^T] (64 x 128);
+// wave (wm, wn) computes nodes 32 wm.. of T1 (wn = 0) or T2 (wn = 1) as two 32-column blocks.
+__global__ __launch_bounds__(256) void k_dinput_mfma(long long n, const float* dPre, const float* P, int ows, int own,
+                                                     float* T1, float* T2) {
+  __shared__ float sw[kH][2 * kH];
+  __shared__ float sx[kTile][kH + 1];
+  for (int e = threadIdx.x; e < kH * 2 * kH; e += blockDim.x) {
+    const int j = e / (2 * kH), c = e % (2 * kH);
+    sw[j][c] = c < kH ? rbf16(P[ows + c * kH + j]) : rbf16(P[own + (c - kH) * kH + j]);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lo = lane & 31, hi = lane >> 5;
+  const int wm = wv >> 1, wn = wv & 1;
+  float* T = wn ? T2 : T1;
+  const long long ntiles = (n + kTile - 1) / kTile;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long v0 = tile * kTile;
+    __syncthreads();
+    for (int i = threadIdx.x; i < kTile * kH; i += blockDim.x) {
+      const int r = i / kH, k = i % kH;
+      const long long v = v0 + r;
+      sx[r][k] = v < n ? dPre[v * kH + k] : 0.0f;
+    }
+    __syncthreads();
+    f32x16_t acc[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
+    for (int k0 = 0; k0 < kH; k0 += 2) {
+      const float a = sx[wm * 32 + lo][k0 + hi];
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, sw[k0 + hi][wn * kH + q * 32 + lo], acc[q], 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const long long v = v0 + wm * 32 + mfma_row(r, hi);
+        if (v < n) T[v * kH + q * 32 + lo] = acc[q][r];
+      }
+  }
+}
+
+// Stage 1 of the weight gradients of a layer: per workgroup, over its chunks of 64 nodes,
+// Gs = Hin^T D and Gn = Ain^T D (M = 2 dim rows, 64 columns, as 32 x 32 blocks spread over the
+// waves) and gb = column sums of D (fixed order). part[block] holds (2 dim + 1) x 64 floats:
+// rows k < dim Gs, dim <= k < 2 dim Gn, row 2 dim gb.
+__global__ __launch_bounds__(256) void k_wgrad_mfma(long long n, const float* Hin, const float* Ain, int ld, int dim,
+                                                    const float* D, float* part) {
+  __shared__ float sx[kTile][2 * kH + 1];
+  __shared__ float sd[kTile][kH];
+  const int M = 2 * dim, mb = (M + 31) / 32, Mp = 32 * mb, nblk = 2 * mb;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lo = lane & 31, hi = lane >> 5;
+  f32x16_t acc[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[q][r] = 0.0f;
+  float bsum = 0.0f;
+  const long long nchunks = (n + kTile - 1) / kTile;
+  for (long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const long long v0 = c * kTile;
+    __syncthreads();
+    for (int i = threadIdx.x; i < kTile * Mp; i += blockDim.x) {
+      const int r = i / Mp, k = i % Mp;
+      const long long v = v0 + r;
+      float x = 0.0f;
+      if (v < n) {
+        if (k < dim)
+          x = Hin[v * ld + k];
+        else if (k < M)
+          x = Ain[v * ld + (k - dim)];
+      }
+      sx[r][k] = x;
+    }
+    for (int i = threadIdx.x; i < kTile * kH; i += blockDim.x) {
+      const int r = i / kH, j = i % kH;
+      const long long v = v0 + r;
+      sd[r][j] = v < n ? D[v * kH + j] : 0.0f;
+    }
+    __syncthreads();
+    if (threadIdx.x < kH)
+      for (int r = 0; r < kTile; ++r) bsum += sd[r][threadIdx.x];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = wv + 4 * q;
+      if (idx < nblk) {
+        const int bm = idx >> 1, bn = idx & 1;
+        for (int k0 = 0; k0 < kTile; k0 += 2)
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(sx[k0 + hi][bm * 32 + lo], sd[k0 + hi][bn * 32 + lo], acc[q],
+                                                        0, 0, 0);
+      }
+    }
+  }
+  float* out = part + (size_t)blockIdx.x * (M + 1) * kH;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int idx = wv + 4 * q;
+    if (idx < nblk) {
+      const int bm = idx >> 1, bn = idx & 1;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = bm * 32 + mfma_row(r, hi);
+        if (m < M) out[m * kH + bn * 32 + lo] = acc[q][r];
+      }
+    }
+  }
+  if (threadIdx.x < kH) out[M * kH + threadIdx.x] = bsum;
+}
+
+// Stage 2: fixed-order (double) sum of the partials into gWs, gWn (dim x 64) and gb (64).
+__global__ void k_wgrad_final_layer(const float* part, int nparts, int dim, float* gWs, float* gWn, float* gb) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = (2 * dim + 1) * kH;
+  if (o >= total) return;
+  double s = 0.0;
+  for (int p = 0; p < nparts; ++p) s += part[(size_t)p * total + o];
+  const int m = o / kH, j = o % kH;
+  if (m < dim)
+    gWs[m * kH + j] = (float)s;
+  else if (m < 2 * dim)
+    gWn[(m - dim) * kH + j] = (float)s;
+  else
+    gb[j] = (float)s;
 }
 
 // dPre_prev = (T1 + aggT) * relu'(Pre_prev), where aggT was computed into Agg.
@@ -241,7 +397,7 @@ Buffers carve(char* base, long long n) {
   for (auto p : hk) *p = f(n * kH);
   b.y = f(n);
   b.dz = f(n);
-  b.part = f((size_t)kRedBlocks * (kH + 1) * kH);
+  b.part = f((size_t)kWgBlocks * (2 * kH + 1) * kH);  // also holds the head's kRedBlocks x (kH + 1)
   b.goff = f(2);
   b.lt = reinterpret_cast<double*>(f(2 * n));
   b.loss = reinterpret_cast<double*>(f(2));
@@ -256,17 +412,25 @@ deco_status check(const deco_graph* g) {
   return DECO_OK;
 }
 
+// Workgroups of the tiled dense kernels: one per 64-node tile, at most 1024 (each walks the
+// rest, reusing its staged weights).
+unsigned lin_grid(long long n) {
+  const long long t = (n + kTile - 1) / kTile;
+  return (unsigned)(t < 1024 ? t : 1024);
+}
+
 hipError_t forward(const deco_graph* g, const float* P, const Buffers& b, const int* goff, hipStream_t s) {
   const long long n = g->n;
   const int G = g->num_graphs;
   hipLaunchKernelGGL(k_features, dim3(nb(n, 256)), dim3(256), 0, s, n, g->row_ptr, g->col_idx, goff, G, b.F);
   // layer 1 (input dim 3, stored with row stride 4)
   hipLaunchKernelGGL(k_aggregate, dim3(nb(n * 4, 256)), dim3(256), 0, s, n, g->row_ptr, g->col_idx, b.F, 4, 4, b.A1, 0);
-  hipLaunchKernelGGL(k_linear, dim3(nb(n, 4)), dim3(256), 0, s, n, b.F, b.A1, 4, kIn, P, oWs1, oWn1, oB1, b.P1, b.H1);
+  const unsigned lg = lin_grid(n);
+  hipLaunchKernelGGL(k_linear_mfma, dim3(lg), dim3(256), 0, s, n, b.F, b.A1, 4, kIn, P, oWs1, oWn1, oB1, b.P1, b.H1);
   hipLaunchKernelGGL(k_aggregate, dim3(nb(n * kH, 256)), dim3(256), 0, s, n, g->row_ptr, g->col_idx, b.H1, kH, kH, b.A2, 0);
-  hipLaunchKernelGGL(k_linear, dim3(nb(n, 4)), dim3(256), 0, s, n, b.H1, b.A2, kH, kH, P, oWs2, oWn2, oB2, b.P2, b.H2);
+  hipLaunchKernelGGL(k_linear_mfma, dim3(lg), dim3(256), 0, s, n, b.H1, b.A2, kH, kH, P, oWs2, oWn2, oB2, b.P2, b.H2);
   hipLaunchKernelGGL(k_aggregate, dim3(nb(n * kH, 256)), dim3(256), 0, s, n, g->row_ptr, g->col_idx, b.H2, kH, kH, b.A3, 0);
-  hipLaunchKernelGGL(k_linear, dim3(nb(n, 4)), dim3(256), 0, s, n, b.H2, b.A3, kH, kH, P, oWs3, oWn3, oB3, b.P3, b.H3);
+  hipLaunchKernelGGL(k_linear_mfma, dim3(lg), dim3(256), 0, s, n, b.H2, b.A3, kH, kH, P, oWs3, oWn3, oB3, b.P3, b.H3);
   return hipGetLastError();
 }
 
@@ -418,18 +582,15 @@ deco_status deco_mpnn_loss_grad(const deco_graph* g, const float* params, const 
   const L layers[3] = {{b.H2, b.A3, b.P2, kH, kH, oWs3, oWn3, oB3, b.D3, b.D2},
                        {b.H1, b.A2, b.P1, kH, kH, oWs2, oWn2, oB2, b.D2, b.D1},
                        {b.F, b.A1, nullptr, 4, kIn, oWs1, oWn1, oB1, b.D1, nullptr}};
+  const long long nchunks = (n + kTile - 1) / kTile;
+  const int wg = (int)(nchunks < kWgBlocks ? nchunks : kWgBlocks);
   for (const L& l : layers) {
-    hipLaunchKernelGGL(k_wgrad_partial, dim3(kRedBlocks), dim3(256), 0, s, n, l.Hin, l.ldin, l.dim, l.D, kH, kH,
-                       b.part);
-    hipLaunchKernelGGL(k_wgrad_final, dim3(nb((l.dim + 1) * kH, 256)), dim3(256), 0, s, b.part, kRedBlocks, l.dim,
-                       kH, grads + l.ows, grads + l.ob);
-    hipLaunchKernelGGL(k_wgrad_partial, dim3(kRedBlocks), dim3(256), 0, s, n, l.Ain, l.ldin, l.dim, l.D, kH, kH,
-                       b.part);
-    hipLaunchKernelGGL(k_wgrad_final, dim3(nb((l.dim + 1) * kH, 256)), dim3(256), 0, s, b.part, kRedBlocks, l.dim,
-                       kH, grads + l.own, (float*)nullptr);
+    hipLaunchKernelGGL(k_wgrad_mfma, dim3(wg), dim3(256), 0, s, n, l.Hin, l.Ain, l.ldin, l.dim, l.D, b.part);
+    hipLaunchKernelGGL(k_wgrad_final_layer, dim3(nb((2 * l.dim + 1) * kH, 256)), dim3(256), 0, s, b.part, wg, l.dim,
+                       grads + l.ows, grads + l.own, grads + l.ob);
     if (l.Dprev) {
-      hipLaunchKernelGGL(k_dinput, dim3(nb(n, 4)), dim3(256), 0, s, n, l.D, params, l.ows, l.own, l.dim, b.T1, b.T2,
-                         kH);
+      hipLaunchKernelGGL(k_dinput_mfma, dim3(lin_grid(n)), dim3(256), 0, s, n, l.D, params, l.ows, l.own, b.T1,
+                         b.T2);
       hipLaunchKernelGGL(k_aggregate, dim3(nb(n * kH, 256)), dim3(256), 0, s, n, rp, ci, b.T2, kH, kH, b.AG, 1);
       hipLaunchKernelGGL(k_combine, dim3(nb(n * kH, 256)), dim3(256), 0, s, n, b.T1, b.AG, l.PrePrev, l.Dprev);
     }

@@ -371,3 +371,20 @@ def test_solve_with_step_count_search(T_l_min):
     assert 3 * (60 + tl_lo) <= r["steps_done"] <= 3 * (160 + 40)
     gb, _ = oracle.greedy(g, orders=2, seed=1)
     assert r["best_cut"][0] > 0.95 * gb
+
+
+def test_solver_stops_inside_a_batch_at_the_target():
+    """With check_every, a run with a target stops at the first check where every graph's best
+    reached it (here inside the first unlifted batch), and still returns the exact cut of its
+    vector; without it the run finishes its round."""
+    g = synth.barabasi_albert(2000, 3, 8)
+    G = deco.Graph(g)
+    r0 = deco.solve(G, B=64, K=8, l_max=2, rounds=2, evo_rounds=1, T_q=400, T_l=100, seed=2)
+    target = 0.98 * r0["best_cut"][0]
+    r = deco.solve(G, B=64, K=8, l_max=2, rounds=3, evo_rounds=1, T_q=400, T_l=100, seed=2, target_cut=[target],
+                   check_every=10)
+    assert r["rounds_done"] == 1 and r["steps_done"] < 400 and r["steps_done"] % 10 == 0
+    assert r["best_cut"][0] >= target
+    assert r["best_cut"][0] == oracle.cut(g, r["z"])
+    full = deco.solve(G, B=64, K=8, l_max=2, rounds=3, evo_rounds=1, T_q=400, T_l=100, seed=2, target_cut=[target])
+    assert full["rounds_done"] == 1 and full["steps_done"] == 500
