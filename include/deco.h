@@ -205,11 +205,12 @@ deco_status deco_set_schedule(deco_handle *h, const deco_schedule *s);
 /* ---------------------------------------------------------------------------------
  * Dense graphs (same method, Sec. 3.1 eq. (6)-(7) with a dense W): the gradient W X is a
  * GEMM on the bfloat16 matrix cores with float32 accumulation, and the exact cut comes from
- * the same GEMM against the sign matrix S = 2Z - 1: cut_b = 1/4 sum_v (d_w(v) - s_v (W s)_v),
- * exact for integer weights of magnitude <= 1024 (W s is then an exact float32 integer).
- * W: device bfloat16 n x n, row-major, symmetric, zero diagonal, caller-owned. Requires
- * n % 128 == 0, B % 128 == 0, l == 1 (unlifted), x_dtype == DECO_BF16; otherwise
- * DECO_E_UNSUPPORTED. The handle then works with deco_start (USER, UNIFORM and MEAN
+ * the same GEMM against the sign matrix S = 2Z - 1: cut_b = 1/4 sum_v (d_w(v) - s_v (W s)_v).
+ * The weights must be integers whose magnitudes sum to at most 2^24 in every row: then every
+ * entry of W s and d_w is an exact float32 integer, the per-column sums are formed in double,
+ * and the cut is exact. W: device bfloat16 n x n, row-major, symmetric, zero diagonal,
+ * caller-owned. Requires n % 128 == 0, B % 128 == 0, l == 1 (unlifted), x_dtype ==
+ * DECO_BF16 and the weight condition above; otherwise DECO_E_UNSUPPORTED. The handle then works with deco_start (USER, UNIFORM and MEAN
  * starts), deco_set_eta, deco_step, deco_round_score, deco_best, deco_read_x,
  * deco_set_trace and deco_destroy. deco_dense_init validates W on the device
  * (symmetry, diagonal, finiteness: DECO_E_INVAL / DECO_E_NONFINITE).
@@ -238,6 +239,10 @@ void deco_destroy(deco_handle *h);
  * memory. Outputs (HOST): best cut per graph [G], its bits z[n] (bytes in {0,1}),
  * per-round wall time since the start [rounds] and best cut per graph [rounds*G].
  * --------------------------------------------------------------------------------- */
+#define DECO_SOLVE_DECO 0      /* lift-and-project rounds: an unlifted then a lifted batch (Alg. 3) */
+#define DECO_SOLVE_UNLIFTED 1  /* unlifted batches only (pQUCO, Alg. 1, with the search) */
+#define DECO_SOLVE_LIFTED 2    /* lifted batches only (pLUCO, Alg. 2, with the search) */
+
 typedef struct deco_solve_params {
   int32_t B;            /* initialisations per graph (multiple of K) */
   int32_t K;            /* population size (column groups), >= 1 */
@@ -274,6 +279,9 @@ typedef struct deco_solve_params {
                            each) and the run ends as soon as every graph reached its target, in
                            the middle of a round if need be; 0: targets are checked after each
                            round */
+  int32_t mode;         /* DECO_SOLVE_DECO (default 0), DECO_SOLVE_UNLIFTED or DECO_SOLVE_LIFTED:
+                           which batches a round runs; the first batch of the run starts from
+                           init_kind, later ones from the previous batch's best vector */
 } deco_solve_params;
 
 typedef struct deco_solve_report {

@@ -963,7 +963,11 @@ deco_status deco_dense_init(deco_handle** out, int64_t n, const void* W, const d
     delete h;
     return DECO_E_NONFINITE;
   }
-  a.intw = (hflags & 16) ? 0 : 1;
+  if (hflags & (16 | 32)) {  // the exact score needs integer weights with row sums of |w| <= 2^24
+    delete h;
+    return DECO_E_UNSUPPORTED;
+  }
+  a.intw = 1;
   e = launch_fill_eta(const_cast<float*>(a.eta), p->B, p->eta, h->stream);
   if (e == hipSuccess) e = launch_reset(a, a.acc, 2LL * lay.R * p->B, p->score_every, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -1209,7 +1213,7 @@ deco_status deco_solver_create(deco_solver** out, const deco_graph* g, const dec
   if (sp->K < 1 || sp->B < 1 || sp->B % sp->K != 0 || sp->l_max < 1 || sp->l_max > kMaxL || sp->T_q < 0 ||
       sp->T_l < 0 || sp->evo_rounds < 0 || !(sp->scale > 0.0) || !(sp->sigma2 >= 0.0) || sp->T_min < 0 ||
       (sp->T_min > 0 && sp->T_min > sp->T_q) || sp->T_l_min < 0 || (sp->T_l_min > 0 && sp->T_l_min > sp->T_l) ||
-      sp->check_every < 0)
+      sp->check_every < 0 || sp->mode < DECO_SOLVE_DECO || sp->mode > DECO_SOLVE_LIFTED)
     return DECO_E_INVAL;
   if (sp->init_kind != DECO_INIT_IDI && sp->init_kind != DECO_INIT_DUI && sp->init_kind != DECO_INIT_UNIFORM &&
       !(sp->init_kind == DECO_INIT_LEARNED && sp->magnitude))
@@ -1324,36 +1328,42 @@ deco_status deco_solver_run(deco_solver* v, int32_t rounds, double* best_cut, ui
   for (int rr = 0; rr < rounds; ++rr) {
     const int r = v->round;
     std::fill(v->fitg.begin(), v->fitg.end(), -INFINITY);
-    // 1. unlifted batch (Alg. 1): member k's columns step with 10^eq[k]
-    for (int b = 0; b < B; ++b) v->eta[b] = (float)std::pow(10.0, v->eq[b / v->per]);
-    if ((st = deco_set_eta(v->hq, v->eta.data()))) return st;
+    // the first batch of the run starts from the chosen start, every later one is centred on
+    // the previous batch's best vector (Sec. 4.2)
+    bool first = r == 0;
     deco_start_args sa{};
-    sa.kind = r == 0 ? sp.init_kind : DECO_INIT_MEAN;
     sa.mean_z = v->mean_dev;
     sa.magnitude = sp.magnitude;
-    sa.scale = (sp.init_kind == DECO_INIT_UNIFORM && r == 0) ? 1.0 : sp.scale;
     sa.sigma2 = sp.sigma2;
     sa.beta = sp.beta;
-    sa.batch = v->batch++;
-    if ((st = deco_start(v->hq, &sa))) return st;
-    int tmax = 0;
     bool hit = false;
-    if ((st = run_counts(v, v->hq, v->eta, v->tq, &tmax, &hit))) return st;
-    if ((st = deco_round_score(v->hq, nullptr, nullptr))) return st;
-    if ((st = absorb(v, v->hq))) return st;
-    v->steps_done += tmax;
-    // edge updates of the members' own steps (a member past its count keeps still)
-    for (int k = 0; k < K; ++k) v->eu += (double)v->g.nnz * v->per * std::min(v->tq[k], tmax);
+    if (sp.mode != DECO_SOLVE_LIFTED) {
+      // 1. unlifted batch (Alg. 1): member k's columns step with 10^eq[k]
+      for (int b = 0; b < B; ++b) v->eta[b] = (float)std::pow(10.0, v->eq[b / v->per]);
+      if ((st = deco_set_eta(v->hq, v->eta.data()))) return st;
+      sa.kind = first ? sp.init_kind : DECO_INIT_MEAN;
+      sa.scale = (sp.init_kind == DECO_INIT_UNIFORM && first) ? 1.0 : sp.scale;
+      sa.batch = v->batch++;
+      if ((st = deco_start(v->hq, &sa))) return st;
+      first = false;
+      int tmax = 0;
+      if ((st = run_counts(v, v->hq, v->eta, v->tq, &tmax, &hit))) return st;
+      if ((st = deco_round_score(v->hq, nullptr, nullptr))) return st;
+      if ((st = absorb(v, v->hq))) return st;
+      v->steps_done += tmax;
+      // edge updates of the members' own steps (a member past its count keeps still)
+      for (int k = 0; k < K; ++k) v->eu += (double)v->g.nnz * v->per * std::min(v->tq[k], tmax);
+    }
     // 2. lift its best vector (Alg. 3 step 2) and run the lifted batch (Alg. 2); member k
     //    keeps lk[k] of the lmax components and steps with 10^el[k]; 3. project back
-    if (!hit) {
+    if (!hit && sp.mode != DECO_SOLVE_UNLIFTED) {
       for (int b = 0; b < B; ++b) {
         v->eta[b] = (float)std::pow(10.0, v->el[b / v->per]);
         v->lact[b] = v->lk[b / v->per];
       }
       if ((st = deco_set_eta(v->hl, v->eta.data()))) return st;
-      sa.kind = DECO_INIT_MEAN;
-      sa.scale = sp.scale;
+      sa.kind = first ? sp.init_kind : DECO_INIT_MEAN;
+      sa.scale = (sp.init_kind == DECO_INIT_UNIFORM && first) ? 1.0 : sp.scale;
       sa.batch = v->batch++;
       sa.l_active = v->lact.data();
       if ((st = deco_start(v->hl, &sa))) return st;

@@ -1132,8 +1132,9 @@ void k_step(StepArgs a) {
 // consecutive tiles, so the tiles sharing a W row panel meet in that XCD's L2. P finishes the
 // projected update; Q scores exactly: with s = 2z - 1,
 //   sum_u w_vu 1{z_u != z_v} = (d_w(v) - s_v (W s)_v) / 2,
-// and W s is exact in float32 for integer weights (integer sums below 2^24), so each tile
-// adds sum_v (d_w(v) - s_v (W s)_v) per column and the cut is 1/4 of the total. The epilogue
+// and W s is exact in float32 for integer weights whose row sums of |w| stay within 2^24
+// (checked when the handle is made), so each tile
+// adds sum_v (d_w(v) - s_v (W s)_v) per column (in double) and the cut is 1/4 of the total. The epilogue
 // stages the tile in LDS and writes X_t+1 and its transpose with 16-byte stores, the cut bits
 // and the fold of the previous step's improvements into best_bits.
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
@@ -1283,7 +1284,7 @@ __global__ __launch_bounds__(256) void k_dense_step(StepArgs a) {
     for (int j = 0; j < 2; ++j) {
       const int cl = wn * 64 + j * 32 + lo;
       const float eta = a.eta[col0 + cl];
-      float colsum = 0.0f;
+      double colsum = 0.0;  // 32 terms of up to 2^25 each: exact in double
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -1298,10 +1299,10 @@ __global__ __launch_bounds__(256) void k_dense_step(StepArgs a) {
             Ys[vl][cl] = (uint16_t)(pack_bf16(y, 0.0f) & 0xFFFFu);
           }
           const bool z = (hx & 0x8000u) == 0u && (hx & 0x7FFFu) != 0u;
-          colsum += s_dw[vl] - (z ? Q[i][j][r] : -Q[i][j][r]);
+          colsum += (double)s_dw[vl] - (double)(z ? Q[i][j][r] : -Q[i][j][r]);
         }
       if (do_score) {
-        double d = (double)colsum;
+        double d = colsum;
         d += __shfl_xor(d, 32);
         if (hi == 0) s_col[wm][cl] = d;
       }
@@ -1373,9 +1374,12 @@ __global__ void k_transpose_bf16(const uint16_t* __restrict__ X, uint16_t* __res
   for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) XT[(size_t)(c0 + (i >> 6)) * n + v0 + (i & 63)] = T[i & 63][i >> 6];
 }
 
+// Row v: symmetry, zero diagonal, finiteness (flags 2, 1, 4), non-integer weights (16) and a
+// weight magnitude sum above 2^24 (32: then W s or d_w could leave the float32 integers);
+// d_w(v) in double, stored as float32 (exact when the checks pass).
 __global__ void k_dense_validate(const uint16_t* W, int n, float* dw, int* flags) {
   const int v = blockIdx.x;
-  float s = 0.0f;
+  double s = 0.0, sa = 0.0;
   int f = 0;
   for (int u = threadIdx.x; u < n; u += blockDim.x) {
     const uint32_t h = W[(size_t)v * n + u];
@@ -1383,28 +1387,33 @@ __global__ void k_dense_validate(const uint16_t* W, int n, float* dw, int* flags
     if (!isfinite(w)) f |= 4;
     if (u == v && h != 0u && h != 0x8000u) f |= 1;
     if (W[(size_t)u * n + v] != h) f |= 2;
-    if (w != floorf(w) || fabsf(w) > 1024.0f) f |= 16;
-    s += w;
+    if (w != floorf(w)) f |= 16;
+    s += (double)w;
+    sa += fabs((double)w);
   }
   for (int o = 32; o > 0; o >>= 1) {
     s += __shfl_xor(s, o);
+    sa += __shfl_xor(sa, o);
     f |= __shfl_xor(f, o);
   }
-  __shared__ float ss[16];
+  __shared__ double ss[16], sb[16];
   __shared__ int sf[16];
   if ((threadIdx.x & 63) == 0) {
     ss[threadIdx.x >> 6] = s;
+    sb[threadIdx.x >> 6] = sa;
     sf[threadIdx.x >> 6] = f;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    float tot = 0.0f;
+    double tot = 0.0, tabs = 0.0;
     int ff = 0;
     for (int i = 0; i < (int)blockDim.x / 64; ++i) {
       tot += ss[i];
+      tabs += sb[i];
       ff |= sf[i];
     }
-    dw[v] = tot;
+    if (tabs > 16777216.0) ff |= 32;
+    dw[v] = (float)tot;
     if (ff) atomicOr(flags, ff);
   }
 }

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("DECO_LIBRARY", os.path.join(_HERE, "libdeco.so"))
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_NONFINITE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+SOLVE_DECO, SOLVE_UNLIFTED, SOLVE_LIFTED = 0, 1, 2
 GRAD_CUT, GRAD_LAPLACIAN = 0, 1
 F32, BF16 = 0, 1
 INIT_USER, INIT_UNIFORM, INIT_DUI, INIT_IDI, INIT_MEAN, INIT_LEARNED = 0, 1, 2, 3, 4, 5
@@ -52,7 +53,7 @@ class deco_solve_params(ct.Structure):
                 ("seed", ct.c_uint64), ("eq0", ct.c_void_p), ("el0", ct.c_void_p), ("l0", ct.c_void_p),
                 ("target_cut", ct.c_void_p), ("use_graph", ct.c_int32), ("autotune", ct.c_int32),
                 ("T_min", ct.c_int32), ("T_l_min", ct.c_int32), ("magnitude", ct.c_void_p),
-                ("check_every", ct.c_int32)]
+                ("check_every", ct.c_int32), ("mode", ct.c_int32)]
 
 
 class deco_schedule(ct.Structure):
@@ -448,7 +449,7 @@ def unpack_mpnn(vec) -> dict:
 def solve(graph: Graph, B=256, K=8, l_max=4, rounds=4, evo_rounds=2, T_q=500, T_l=200, grad_form=GRAD_CUT,
           x_dtype=F32, init_kind=INIT_IDI, beta=0.2, sigma2=0.8, scale=1e4, time_budget_s=0.0, seed=0,
           eq0=None, el0=None, l0=None, target_cut=None, use_graph=True, autotune=False, stream=None, T_min=0,
-          T_l_min=0, magnitude=None, check_every=0):
+          T_l_min=0, magnitude=None, check_every=0, mode=0):
     """Full pDECO with the evolutionary search; returns a dict of host results. T_min > 0
     also searches the unlifted step count per member in [T_min, T_q], T_l_min > 0 the lifted
     one in [T_l_min, T_l]. magnitude: device float32 [n] for init_kind=INIT_LEARNED."""
@@ -467,7 +468,7 @@ def solve(graph: Graph, B=256, K=8, l_max=4, rounds=4, evo_rounds=2, T_q=500, T_
                           scale, time_budget_s, seed, arr(eq0, np.float64), arr(el0, np.float64),
                           arr(l0, np.int32), arr(target_cut, np.float64), int(bool(use_graph)),
                           int(bool(autotune)), int(T_min), int(T_l_min),
-                          None if magnitude is None else magnitude.data_ptr(), int(check_every))
+                          None if magnitude is None else magnitude.data_ptr(), int(check_every), int(mode))
     G = graph.num_graphs
     best = np.zeros(G, np.float64)
     z = np.zeros(graph.n, np.uint8)
@@ -490,7 +491,7 @@ class Solver:
     def __init__(self, graph: Graph, B=256, K=8, l_max=4, evo_rounds=2, T_q=500, T_l=200, grad_form=GRAD_CUT,
                  x_dtype=F32, init_kind=INIT_IDI, beta=0.2, sigma2=0.8, scale=1e4, time_budget_s=0.0, seed=0,
                  eq0=None, el0=None, l0=None, target_cut=None, use_graph=True, autotune=False, stream=None,
-                 T_min=0, T_l_min=0, magnitude=None, check_every=0):
+                 T_min=0, T_l_min=0, magnitude=None, check_every=0, mode=0):
         import torch
         self.graph = graph
         # LEARNED starts read the device magnitudes at every run: keep the tensor alive
@@ -509,7 +510,8 @@ class Solver:
                               scale, time_budget_s, seed, arr(eq0, np.float64), arr(el0, np.float64),
                               arr(l0, np.int32), arr(target_cut, np.float64), int(bool(use_graph)),
                               int(bool(autotune)), int(T_min), int(T_l_min),
-                              None if self._magnitude is None else self._magnitude.data_ptr(), int(check_every))
+                              None if self._magnitude is None else self._magnitude.data_ptr(), int(check_every),
+                              int(mode))
         torch.cuda.synchronize()
         h = ct.c_void_p()
         _check(lib().deco_solver_create(ct.byref(h), ct.byref(graph.struct), ct.byref(p),

@@ -105,6 +105,50 @@ def test_dense_rejects_unsupported_and_invalid():
     assert e.value.status == deco.E_INVAL
 
 
+def test_dense_rejects_weights_without_an_exact_score():
+    """The exact score needs integer weights whose |w| sums stay within 2^24 per row."""
+    W = torch.zeros((128, 128), dtype=torch.bfloat16, device="cuda")
+    W[0, 1] = W[1, 0] = 0.5
+    with pytest.raises(deco.DecoError) as e:
+        deco.DenseHandle(W, B=128)
+    assert e.value.status == deco.E_UNSUPPORTED
+    W = torch.full((128, 128), 2.0 ** 18, dtype=torch.bfloat16, device="cuda")
+    W.fill_diagonal_(0.0)  # 127 x 2^18 > 2^24 per row
+    with pytest.raises(deco.DecoError) as e:
+        deco.DenseHandle(W, B=128)
+    assert e.value.status == deco.E_UNSUPPORTED
+    W = torch.full((128, 128), 2.0 ** 17, dtype=torch.bfloat16, device="cuda")
+    W.fill_diagonal_(0.0)  # 127 x 2^17 < 2^24: accepted
+    deco.DenseHandle(W, B=128).destroy()
+
+
+def test_dense_er8192_large_integer_weights_exact_cuts():
+    """ER(8192, 0.5) with integer weights of magnitude up to 2048 (k 2^j, k <= 8, exact in
+    bfloat16; row sums of |w| about 4e6, within 2^24), B = 512 on the MFMA path: the cuts of 64
+    sampled initialisations equal the oracle's eq. (1) cuts of the GPU's own sign vectors, bit
+    for bit, at three iterates. Each column sum reaches ~1e10, far past float32's exact
+    integers, so the double column sums are what keeps them exact."""
+    g = synth.erdos_renyi(8192, 0.5, 0)
+    rng = np.random.default_rng(4)
+    m = g.nnz // 2
+    w = (rng.integers(1, 9, m) * 2.0 ** rng.integers(0, 9, m) * rng.choice([-1.0, 1.0], m)).astype(np.float32)
+    g = synth.with_weights(g, w)
+    h = deco.DenseHandle(dense_bf16(g), B=512, eta=0.001, seed=1)
+    h.start(deco.INIT_UNIFORM, batch=0)
+    tr = h.set_trace(4)
+    xs = [to_np(h.read_x())]
+    for _ in range(2):
+        h.step(1)
+        xs.append(to_np(h.read_x()))
+    h.round_score()
+    cols = np.random.default_rng(3).choice(512, 64, replace=False)
+    trn = tr.cpu().numpy()
+    for t in range(3):
+        z = oracle.round_signs(np.ascontiguousarray(xs[t][:, cols].astype(np.float64)), 64)
+        assert np.array_equal(trn[t][0][cols], oracle.cut_batch(g, z)[0]), f"cut at step {t}"
+    h.destroy()
+
+
 def test_dense_er8192_half_B512_sampled():
     """ER(8192, 0.5), unit weights, B = 512 on the MFMA path: sampled rows against the oracle
     (star subgraphs) and exact cuts of 64 sampled initialisations, for two steps."""

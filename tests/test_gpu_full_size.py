@@ -388,3 +388,15 @@ def test_solver_stops_inside_a_batch_at_the_target():
     assert r["best_cut"][0] == oracle.cut(g, r["z"])
     full = deco.solve(G, B=64, K=8, l_max=2, rounds=3, evo_rounds=1, T_q=400, T_l=100, seed=2, target_cut=[target])
     assert full["rounds_done"] == 1 and full["steps_done"] == 500
+
+
+@pytest.mark.parametrize("mode,steps", [(deco.SOLVE_UNLIFTED, 2 * 100), (deco.SOLVE_LIFTED, 2 * 50)])
+def test_solve_unlifted_only_and_lifted_only(mode, steps):
+    """pQUCO-only and pLUCO-only runs (the two formulations with the search, without the
+    alternation): each round runs one batch of its kind; the returned cut is exact."""
+    g = synth.barabasi_albert(1500, 3, 11)
+    r = deco.solve(deco.Graph(g), B=48, K=6, l_max=2, rounds=2, evo_rounds=1, T_q=100, T_l=50, seed=4, mode=mode)
+    assert r["steps_done"] == steps
+    assert r["best_cut"][0] == oracle.cut(g, r["z"])
+    gb, _ = oracle.greedy(g, orders=2, seed=1)
+    assert r["best_cut"][0] > 0.9 * gb
