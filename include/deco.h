@@ -91,7 +91,11 @@ typedef struct deco_graph {
 
 typedef struct deco_params {
   int32_t B;            /* initialisations per graph: 1, 2, 4 or a multiple of 8 */
-  int32_t l;            /* components per initialisation, 1..8 (1 = unlifted) */
+  int32_t l;            /* components per initialisation (1 = unlifted), up to l*B < 2^24; at
+                           most 8 are held by one step kernel, more run as an unlifted handle
+                           over the l*B columns (the lifted update acts column by column)
+                           plus a lifted l = 1 handle scoring the float32 component sums, with
+                           identical results (the workspace holds both) */
   int32_t lifted;       /* 0: eq. (5) rounding (requires l == 1); 1: lifted rounding */
   int32_t grad_form;    /* DECO_GRAD_CUT or DECO_GRAD_LAPLACIAN */
   int32_t x_dtype;      /* DECO_F32 or DECO_BF16 storage of X (arithmetic is float32) */
@@ -246,7 +250,7 @@ void deco_destroy(deco_handle *h);
 typedef struct deco_solve_params {
   int32_t B;            /* initialisations per graph (multiple of K) */
   int32_t K;            /* population size (column groups), >= 1 */
-  int32_t l_max;        /* lifted components per initialisation, 1..8 */
+  int32_t l_max;        /* lifted components per initialisation, >= 1 (deco_params.l) */
   int32_t rounds;       /* maximum number of lift-and-project rounds */
   int32_t evo_rounds;   /* rounds during which the population evolves */
   int32_t T_q;          /* steps of every unlifted batch */

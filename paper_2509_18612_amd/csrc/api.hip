@@ -137,6 +137,13 @@ struct deco_handle {
   std::vector<int> rp_host;
   std::vector<int> goff_host;
   std::vector<int> lact_host;  // host copy of the step kernel's active-component counts
+  // More than kMaxL components per initialisation: the iterates live in cx, an unlifted handle
+  // over the l B columns (the lifted update acts column by column, Sec. 3.2), and the scores in
+  // cs, a lifted l = 1 handle over the B component sums (its step size is 0, so a step only
+  // scores and advances); k_sides refreshes cs's iterate from cx's before every scoring.
+  deco_handle* cx = nullptr;
+  deco_handle* cs = nullptr;
+  char* sbuf = nullptr;  // n x B sums for starts
   long long t_host = 0;
   double* trace = nullptr;
   int trace_cap = 0;
@@ -314,6 +321,7 @@ std::tuple<long long, long long, int, int, int, int, int> cache_key(const deco_h
 }
 
 bool schedule_cached(const deco_handle* h) {
+  if (h->cx) return schedule_cached(h->cx) && schedule_cached(h->cs);
   std::lock_guard<std::mutex> lk(g_cache_mu);
   return g_cache.count(cache_key(h)) != 0;
 }
@@ -333,7 +341,7 @@ deco_status check_params(const deco_params* p) {
   if (p->grad_form != DECO_GRAD_CUT && p->grad_form != DECO_GRAD_LAPLACIAN) return DECO_E_INVAL;
   if (!p->lifted && p->l != 1) return DECO_E_INVAL;
   if (!std::isfinite(p->eta)) return DECO_E_NONFINITE;
-  if (!supported_B(p->B) || p->l > kMaxL) return DECO_E_UNSUPPORTED;
+  if (!supported_B(p->B) || (long long)p->l * p->B >= (1LL << 24)) return DECO_E_UNSUPPORTED;
   return DECO_OK;
 }
 
@@ -349,8 +357,55 @@ deco_status launch_steps(deco_handle* h, int steps, int do_update, int force) {
   return DECO_OK;
 }
 
+// One step of a many-component handle: sums of X_t into the score handle, a scoring step of
+// the score handle (step size 0: it scores X_t's sides and advances), the step of the iterates.
+deco_status wide_launch_steps(deco_handle* h, int steps) {
+  for (int t = 0; t < steps; ++t) {
+    if (launch_sides(h->cx->args.x[0], h->cx->args.x[1], h->cs->args.x[0], h->cs->args.x[1], h->cx->args.ctrl,
+                     h->cs->args.ctrl, h->n, h->p.B, h->p.l, h->dtype, h->stream) != hipSuccess)
+      return poison(h, hipErrorLaunchFailure);
+    deco_status st = launch_steps(h->cs, 1, 1, 0);
+    if (!st) st = launch_steps(h->cx, 1, 1, 0);
+    if (st) {
+      h->poisoned = true;
+      return st;
+    }
+  }
+  return DECO_OK;
+}
+
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// The two parameter sets of a many-component handle (see deco_handle::cx).
+void wide_params(const deco_params* p, deco_params* px, deco_params* ps) {
+  *px = *p;
+  px->B = p->l * p->B;
+  px->l = 1;
+  px->lifted = 0;
+  px->score_every = 1 << 30;  // the iterate handle's own (unlifted) rounding is never used
+  *ps = *p;
+  ps->l = 1;
+  ps->lifted = 1;
+  ps->eta = 0.0f;
+}
+
+size_t wide_sum_bytes(long long n, const deco_params* p) { return align_up((size_t)n * p->B * elem_size(p->x_dtype)); }
+
+hipError_t wide_sides(deco_handle* h, bool into_start_buffer) {
+  deco_handle* x = h->cx;
+  deco_handle* c = h->cs;
+  if (into_start_buffer)
+    return launch_sides(x->args.x[x->t_host & 1], x->args.x[x->t_host & 1], h->sbuf, h->sbuf, nullptr, nullptr, h->n,
+                        h->p.B, h->p.l, h->dtype, h->stream);
+  return launch_sides(x->args.x[0], x->args.x[1], c->args.x[0], c->args.x[1], x->args.ctrl, c->args.ctrl, h->n,
+                      h->p.B, h->p.l, h->dtype, h->stream);
+}
+
+deco_status wide_poison(deco_handle* h, deco_status st) {
+  if (st == DECO_E_DEVICE || st == DECO_E_STATE) h->poisoned = true;
+  return st;
 }
 
 }  // namespace
@@ -375,6 +430,14 @@ deco_status deco_workspace_size(const deco_graph* g, const deco_params* p, size_
   if (st) return st;
   if ((st = check_params(p))) return st;
   if (!bytes) return DECO_E_INVAL;
+  if (p->l > kMaxL) {
+    deco_params px, ps;
+    wide_params(p, &px, &ps);
+    *bytes = align_up(layout_for(g->n, g->nnz, g->num_graphs, &px, g->w != nullptr).total) +
+             align_up(layout_for(g->n, g->nnz, g->num_graphs, &ps, g->w != nullptr).total) +
+             2 * wide_sum_bytes(g->n, p);
+    return DECO_OK;
+  }
   *bytes = layout_for(g->n, g->nnz, g->num_graphs, p, g->w != nullptr).total;
   return DECO_OK;
 }
@@ -388,6 +451,38 @@ deco_status deco_init(deco_handle** out, const deco_graph* g, const deco_params*
   if ((st = check_params(p))) return st;
   if (!X || !workspace) return DECO_E_INVAL;
   if (((uintptr_t)X % 16) != 0 || ((uintptr_t)workspace % kAlign) != 0) return DECO_E_INVAL;
+  if (p->l > kMaxL) {
+    size_t need = 0;
+    if ((st = deco_workspace_size(g, p, &need))) return st;
+    if (workspace_bytes < need) return DECO_E_NOMEM;
+    deco_params px, ps;
+    wide_params(p, &px, &ps);
+    const size_t wx = align_up(layout_for(g->n, g->nnz, g->num_graphs, &px, g->w != nullptr).total);
+    const size_t wsz = align_up(layout_for(g->n, g->nnz, g->num_graphs, &ps, g->w != nullptr).total);
+    char* base = reinterpret_cast<char*>(workspace);
+    char* xs = base + wx + wsz;  // the score handle's iterate (n x B)
+    deco_handle* h = new deco_handle();
+    h->g = *g;
+    h->p = *p;
+    h->stream = reinterpret_cast<hipStream_t>(stream);
+    h->n = g->n;
+    h->nnz = g->nnz;
+    h->G = g->num_graphs;
+    h->C = p->l * p->B;
+    h->NBY = nby_of(p->B);
+    h->dtype = p->x_dtype;
+    h->unit = g->w == nullptr;
+    h->X = X;
+    h->sbuf = xs + wide_sum_bytes(g->n, p);
+    if ((st = deco_init(&h->cx, g, &px, X, base, wx, stream)) || (st = deco_init(&h->cs, g, &ps, xs, base + wx, wsz,
+                                                                                  stream))) {
+      deco_destroy(h);
+      return st;
+    }
+    h->R = h->cs->R;
+    *out = h;
+    return DECO_OK;
+  }
   Layout lay = layout_for(g->n, g->nnz, g->num_graphs, p, g->w != nullptr);
   if (workspace_bytes < lay.total) return DECO_E_NOMEM;
 
@@ -543,6 +638,34 @@ deco_status deco_init(deco_handle** out, const deco_graph* g, const deco_params*
 
 deco_status deco_start(deco_handle* h, const deco_start_args* s) {
   if (!h || !s) return DECO_E_INVAL;
+  if (h->cx) {
+    if (h->poisoned) return DECO_E_STATE;
+    // iterates: the same start over the l B columns (the draws are per column); active
+    // components become per-column 0/1 counts
+    deco_start_args a = *s;
+    std::vector<int32_t> lc;
+    if (s->l_active) {
+      lc.resize((size_t)h->C);
+      for (int b = 0; b < h->p.B; ++b) {
+        if (s->l_active[b] < 0 || s->l_active[b] > h->p.l) return DECO_E_INVAL;
+        for (int i = 0; i < h->p.l; ++i) lc[(size_t)i * h->p.B + b] = i < s->l_active[b] ? 1 : 0;
+      }
+      a.l_active = lc.data();
+    }
+    deco_status st = deco_start(h->cx, &a);
+    if (st) return wide_poison(h, st);
+    // scores: the component sums of the start
+    if (wide_sides(h, true) != hipSuccess) return wide_poison(h, DECO_E_DEVICE);
+    deco_start_args b{};
+    b.kind = DECO_INIT_USER;
+    b.x0 = h->sbuf;
+    b.scale = 1.0;
+    if ((st = deco_start(h->cs, &b))) return wide_poison(h, st);
+    h->t_host = 0;
+    for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+    return DECO_OK;
+  }
   if (h->poisoned) return DECO_E_STATE;
   if (s->kind < DECO_INIT_USER || s->kind > DECO_INIT_LEARNED) return DECO_E_INVAL;
   if (s->kind == DECO_INIT_LEARNED && !s->magnitude) return DECO_E_INVAL;
@@ -645,6 +768,12 @@ deco_status deco_start(deco_handle* h, const deco_start_args* s) {
 deco_status deco_set_eta(deco_handle* h, const float* eta_host) {
   if (!h || !eta_host) return DECO_E_INVAL;
   if (h->poisoned) return DECO_E_STATE;
+  if (h->cx) {
+    std::vector<float> e((size_t)h->C);
+    for (int i = 0; i < h->p.l; ++i)
+      for (int b = 0; b < h->p.B; ++b) e[(size_t)i * h->p.B + b] = eta_host[b];
+    return wide_poison(h, deco_set_eta(h->cx, e.data()));
+  }
   for (int b = 0; b < h->p.B; ++b)
     if (!std::isfinite(eta_host[b])) return DECO_E_NONFINITE;
   HIP_TRY(h, hipMemcpyAsync(const_cast<float*>(h->args.eta), eta_host, sizeof(float) * h->p.B,
@@ -656,6 +785,11 @@ deco_status deco_set_eta(deco_handle* h, const float* eta_host) {
 deco_status deco_set_momentum(deco_handle* h, float mu, float* velocity) {
   if (!h) return DECO_E_INVAL;
   if (h->poisoned) return DECO_E_STATE;
+  if (h->cx) {
+    for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+    return wide_poison(h, deco_set_momentum(h->cx, mu, velocity));
+  }
   if (h->dense) return DECO_E_UNSUPPORTED;
   if (!std::isfinite(mu)) return DECO_E_NONFINITE;
   h->args.vel = velocity;
@@ -674,7 +808,7 @@ deco_status deco_step(deco_handle* h, int32_t steps, int32_t use_graph) {
   if (h->poisoned) return DECO_E_STATE;
   if (steps == 0) return DECO_OK;
   if (!use_graph) {
-    deco_status st = launch_steps(h, steps, 1, 0);
+    deco_status st = h->cx ? wide_launch_steps(h, steps) : launch_steps(h, steps, 1, 0);
     if (st) return st;
   } else {
     if (h->stream == nullptr) return DECO_E_INVAL;
@@ -682,7 +816,7 @@ deco_status deco_step(deco_handle* h, int32_t steps, int32_t use_graph) {
     if (it == h->graphs.end()) {
       hipGraph_t graph;
       HIP_TRY(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-      deco_status st = launch_steps(h, steps, 1, 0);
+      deco_status st = h->cx ? wide_launch_steps(h, steps) : launch_steps(h, steps, 1, 0);
       hipError_t e = hipStreamEndCapture(h->stream, &graph);
       if (st) return st;
       HIP_TRY(h, e);
@@ -695,6 +829,13 @@ deco_status deco_step(deco_handle* h, int32_t steps, int32_t use_graph) {
     HIP_TRY(h, hipGraphLaunch(it->second, h->stream));
   }
   h->t_host += steps;
+  if (h->cx) {
+    for (deco_handle* c : {h->cx, h->cs}) {
+      c->t_host += steps;
+      HIP_TRY(h, launch_drain(c->args, c->n, reinterpret_cast<int*>(c->ws + c->lay.goff), c->stream));
+    }
+    return DECO_OK;
+  }
   HIP_TRY(h, launch_drain(h->args, h->n, reinterpret_cast<int*>(h->ws + h->lay.goff), h->stream));
   return DECO_OK;
 }
@@ -702,6 +843,10 @@ deco_status deco_step(deco_handle* h, int32_t steps, int32_t use_graph) {
 deco_status deco_round_score(deco_handle* h, double* cut_out, uint8_t* bits_out) {
   if (!h) return DECO_E_INVAL;
   if (h->poisoned) return DECO_E_STATE;
+  if (h->cx) {
+    if (wide_sides(h, false) != hipSuccess) return wide_poison(h, DECO_E_DEVICE);
+    return wide_poison(h, deco_round_score(h->cs, cut_out, bits_out));
+  }
   deco_status st = launch_steps(h, 1, 0, 1);
   if (st) return st;
   HIP_TRY(h, launch_drain(h->args, h->n, reinterpret_cast<int*>(h->ws + h->lay.goff), h->stream));
@@ -717,6 +862,7 @@ deco_status deco_round_score(deco_handle* h, double* cut_out, uint8_t* bits_out)
 deco_status deco_best(deco_handle* h, double* best_cut, int32_t* best_step, uint8_t* best_bits) {
   if (!h || !best_cut) return DECO_E_INVAL;
   if (h->poisoned) return DECO_E_STATE;
+  if (h->cx) return wide_poison(h, deco_best(h->cs, best_cut, best_step, best_bits));
   const size_t gb = (size_t)h->G * h->p.B;
   const int* goff_dev = reinterpret_cast<int*>(h->ws + h->lay.goff);
   HIP_TRY(h, launch_drain(h->args, h->n, goff_dev, h->stream));
@@ -732,6 +878,7 @@ deco_status deco_best(deco_handle* h, double* best_cut, int32_t* best_step, uint
 deco_status deco_read_x(deco_handle* h, void* dst) {
   if (!h || !dst) return DECO_E_INVAL;
   if (h->poisoned) return DECO_E_STATE;
+  if (h->cx) return wide_poison(h, deco_read_x(h->cx, dst));
   HIP_TRY(h, hipMemcpyAsync(dst, h->args.x[h->t_host & 1], (size_t)h->n * h->C * elem_size(h->dtype),
                             hipMemcpyDeviceToDevice, h->stream));
   return DECO_OK;
@@ -739,6 +886,10 @@ deco_status deco_read_x(deco_handle* h, void* dst) {
 
 deco_status deco_set_trace(deco_handle* h, double* trace, int32_t capacity) {
   if (!h || (trace && capacity < 1)) return DECO_E_INVAL;
+  if (h->cx) {
+    deco_status st = deco_set_trace(h->cs, trace, capacity);
+    if (st) return st;
+  }
   h->args.trace = trace;
   h->args.trace_cap = trace ? capacity : 1;
   for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -751,6 +902,13 @@ int64_t deco_current_step(const deco_handle* h) { return h ? h->t_host : -1; }
 deco_status deco_autotune(deco_handle* h, int32_t steps) {
   if (!h || steps < 1) return DECO_E_INVAL;
   if (h->poisoned) return DECO_E_STATE;
+  if (h->cx) {
+    deco_status st = deco_autotune(h->cx, steps);
+    if (!st) st = deco_autotune(h->cs, steps);
+    for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+    return wide_poison(h, st);
+  }
   if (h->dense) return DECO_OK;  // one fixed tiling
   const Schedule base = default_schedule(h);
   std::vector<Schedule> cand;
@@ -830,6 +988,11 @@ deco_status deco_autotune(deco_handle* h, int32_t steps) {
 deco_status deco_set_schedule(deco_handle* h, const deco_schedule* q) {
   if (!h || !q) return DECO_E_INVAL;
   if (h->poisoned) return DECO_E_STATE;
+  if (h->cx) {  // the iterate handle's schedule (the score handle keeps its own)
+    for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+    return wide_poison(h, deco_set_schedule(h->cx, q));
+  }
   if (h->dense) return DECO_E_UNSUPPORTED;
   if (q->lanes_per_row < 1 || (q->lanes_per_row & (q->lanes_per_row - 1)) ||
       q->blocks_per_xcd < 1 || q->blocks_per_xcd > kMaxBlocksPerXcd || q->nnz_per_item < kMinItemSlots ||
@@ -854,6 +1017,13 @@ deco_status deco_set_schedule(deco_handle* h, const deco_schedule* q) {
 
 deco_status deco_schedule_string(const deco_handle* h, char* buf, int32_t cap) {
   if (!h || !buf || cap < 1) return DECO_E_INVAL;
+  if (h->cx) {
+    char a[256], b[256];
+    deco_schedule_string(h->cx, a, sizeof(a));
+    deco_schedule_string(h->cs, b, sizeof(b));
+    std::snprintf(buf, (size_t)cap, "l=%d over %d columns: %s | sums: %s", h->p.l, h->C, a, b);
+    return DECO_OK;
+  }
   if (h->dense) {
     std::snprintf(buf, (size_t)cap, "dense bf16 MFMA 32x32x16: tiles 128x128x64, grid=%lld, R=%d",
                   (long long)(h->n / 128) * (2 * h->C / 128), h->R);
@@ -982,6 +1152,8 @@ deco_status deco_dense_init(deco_handle** out, int64_t n, const void* W, const d
 void deco_destroy(deco_handle* h) {
   if (!h) return;
   for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (h->cx) deco_destroy(h->cx);
+  if (h->cs) deco_destroy(h->cs);
   delete h;
 }
 
@@ -1210,7 +1382,7 @@ deco_status deco_solver_create(deco_solver** out, const deco_graph* g, const dec
   deco_status st = check_graph_args(g);
   if (st) return st;
   if (!sp) return DECO_E_INVAL;
-  if (sp->K < 1 || sp->B < 1 || sp->B % sp->K != 0 || sp->l_max < 1 || sp->l_max > kMaxL || sp->T_q < 0 ||
+  if (sp->K < 1 || sp->B < 1 || sp->B % sp->K != 0 || sp->l_max < 1 || sp->T_q < 0 ||
       sp->T_l < 0 || sp->evo_rounds < 0 || !(sp->scale > 0.0) || !(sp->sigma2 >= 0.0) || sp->T_min < 0 ||
       (sp->T_min > 0 && sp->T_min > sp->T_q) || sp->T_l_min < 0 || (sp->T_l_min > 0 && sp->T_l_min > sp->T_l) ||
       sp->check_every < 0 || sp->mode < DECO_SOLVE_DECO || sp->mode > DECO_SOLVE_LIFTED)

@@ -30,7 +30,8 @@ struct DevCtrl {
 // Work-item limits of the step kernel (LDS staging of one item's slot list).
 constexpr int kEmax = 2048;  // slots staged at a time
 constexpr int kRmax = 512;   // rows of a normal item
-constexpr int kMaxL = 8;     // lifted components per initialisation
+constexpr int kMaxL = 8;     // lifted components per initialisation held by one step kernel
+                             // (more run as a pair of handles, see api.hip)
 
 // Slot list: row v occupies positions [row_ptr[v] + v, row_ptr[v+1] + v + 1): its own
 // index with the top bit set, then its neighbours in CSR order. The slot weights (weighted
@@ -113,6 +114,9 @@ hipError_t launch_drain(StepArgs a, long long n, const int* goff, hipStream_t s)
 // Workgroups that complete one step's G * B cuts (256 each, at most 64).
 int completion_blocks(long long GB);
 hipError_t launch_fill_eta(float* eta, int B, float v, hipStream_t s);
+// Component sums of a many-component batch (l > kMaxL) into the score handle's iterate.
+hipError_t launch_sides(const void* x0, const void* x1, void* s0, void* s1, const DevCtrl* cx, const DevCtrl* cs,
+                        long long n, int B, int l, int dtype, hipStream_t s);
 
 struct InitArgs {
   long long n;

@@ -1854,6 +1854,42 @@ hipError_t launch_merge(StepArgs a, long long n, const int* goff, hipStream_t s)
   return hipGetLastError();
 }
 
+// Sides of a batch with many components per initialisation (l above kMaxL, run as an
+// unlifted handle over the l B columns plus a lifted l = 1 handle over the B sums): S[v, b] =
+// sum_{i<l} X[v, i B + b] in float32, component order i = 0..l-1 (the lifted rounding of
+// Sec. 3.2 takes its sign), stored in the storage type (round to nearest even keeps the
+// sign; -0 and +0 both give side 1). With control blocks the iterate is x[tx & 1] and the sums
+// go to s[ts & 1] (tx, ts: the two handles' step counters, read on the device so a captured
+// graph replays correctly); without them x0 and s0 are used.
+__global__ void k_sides(const void* x0, const void* x1, void* s0, void* s1, const DevCtrl* cx, const DevCtrl* cs,
+                        long long n, int B, int l, int dtype) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * B) return;
+  const long long v = i / B;
+  const int b = (int)(i % B);
+  const void* X = (cx && (cx->t & 1)) ? x1 : x0;
+  void* S = (cs && (cs->t & 1)) ? s1 : s0;
+  const size_t base = (size_t)v * B * l + b;
+  float sum = 0.0f;
+  if (dtype == 0) {
+    const float* x = reinterpret_cast<const float*>(X) + base;
+    for (int c = 0; c < l; ++c) sum = sum + x[(size_t)c * B];
+    reinterpret_cast<float*>(S)[i] = sum;
+  } else {
+    const uint16_t* x = reinterpret_cast<const uint16_t*>(X) + base;
+    for (int c = 0; c < l; ++c) sum = sum + bf2f(x[(size_t)c * B]);
+    reinterpret_cast<uint16_t*>(S)[i] = (uint16_t)(pack_bf16(sum, 0.0f) & 0xFFFFu);
+  }
+}
+
+hipError_t launch_sides(const void* x0, const void* x1, void* s0, void* s1, const DevCtrl* cx, const DevCtrl* cs,
+                        long long n, int B, int l, int dtype, hipStream_t s) {
+  const long long m = n * B;
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sides, dim3(blocks_for(m, 256)), dim3(256), 0, s, x0, x1, s0, s1, cx, cs, n, B, l, dtype);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_eta(float* eta, int B, float v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3(blocks_for(B, 256)), dim3(256), 0, s, eta, B, v);
   return hipGetLastError();

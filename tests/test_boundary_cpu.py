@@ -164,7 +164,7 @@ def test_workspace_size_and_argument_errors_without_device():
     p = deco.deco_params(16, 1, 0, 0, 0, 1, 0.1, 0)
     assert deco.lib().deco_workspace_size(ct.byref(g), ct.byref(p), ct.byref(nb)) == 0 and nb.value > 0
     bad = [deco.deco_params(3, 1, 0, 0, 0, 1, 0.1, 0),   # B = 3 unsupported
-           deco.deco_params(16, 9, 1, 0, 0, 1, 0.1, 0),  # l = 9 unsupported
+           deco.deco_params(16, 1 << 20, 1, 0, 0, 1, 0.1, 0),  # l B = 2^24 columns unsupported
            deco.deco_params(16, 2, 0, 0, 0, 1, 0.1, 0),  # l > 1 needs lifted rounding
            deco.deco_params(16, 1, 0, 7, 0, 1, 0.1, 0),  # bad gradient form
            deco.deco_params(16, 1, 0, 0, 0, 0, 0.1, 0),  # score_every = 0
@@ -172,6 +172,14 @@ def test_workspace_size_and_argument_errors_without_device():
     want = [deco.E_UNSUPPORTED, deco.E_UNSUPPORTED, deco.E_INVAL, deco.E_INVAL, deco.E_INVAL, deco.E_NONFINITE]
     for q, w in zip(bad, want):
         assert deco.lib().deco_workspace_size(ct.byref(g), ct.byref(q), ct.byref(nb)) == w
+    # more than 8 components: the workspace holds the column handle, the sum handle and two
+    # n x B sum buffers
+    w8, w9 = ct.c_size_t(0), ct.c_size_t(0)
+    assert deco.lib().deco_workspace_size(ct.byref(g), ct.byref(deco.deco_params(16, 8, 1, 0, 0, 1, 0.1, 0)),
+                                          ct.byref(w8)) == 0
+    assert deco.lib().deco_workspace_size(ct.byref(g), ct.byref(deco.deco_params(16, 9, 1, 0, 0, 1, 0.1, 0)),
+                                          ct.byref(w9)) == 0
+    assert w9.value > w8.value > 0
     big = deco.deco_graph(100, 2 ** 31, 1, 1, None, 1, None)
     assert deco.lib().deco_workspace_size(ct.byref(big), ct.byref(p), ct.byref(nb)) == deco.E_UNSUPPORTED
     empty = deco.deco_graph(0, 0, 1, 1, None, 1, None)

@@ -131,7 +131,8 @@ def test_er800_uniform_start_200_steps():
     h.destroy()
 
 
-@pytest.mark.parametrize("dtype,l", [(deco.F32, 1), (deco.BF16, 1), (deco.F32, 4), (deco.BF16, 2), (deco.BF16, 8)])
+@pytest.mark.parametrize("dtype,l", [(deco.F32, 1), (deco.BF16, 1), (deco.F32, 4), (deco.BF16, 2), (deco.BF16, 8),
+                                     (deco.BF16, 12)])
 def test_ba10k_B256_full_rows(dtype, l):
     """BA(10^4, 4), B = 256 (the bench's graph and batch), uniform starts in [-1, 1], eta =
     0.05, 12 teacher-forced steps on every row and column: each element within the float32
@@ -272,7 +273,7 @@ def test_regular3_million_pm1_B128():
     h.destroy()
 
 
-@pytest.mark.parametrize("l_max", [4, 8])
+@pytest.mark.parametrize("l_max", [4, 8, 12])
 def test_solve_small_graph_bounded_by_brute_force(l_max):
     g = synth.erdos_renyi(18, 0.4, 3)
     opt = oracle.brute_force(g)[0]

@@ -100,6 +100,14 @@ CASES = {
     "lifted_l8_active_B16": (lambda: synth.erdos_renyi(300, 0.05, 21), 16,
                              dict(l=8, lifted=True, l_active=np.array([1 + (5 * b) % 8 for b in range(16)],
                                                                       np.int32))),
+    # more than 8 components: iterates as an unlifted batch over the l B columns, scores from
+    # the float32 component sums
+    "lifted_l12_B8": (lambda: synth.barabasi_albert(300, 3, 22), 8, dict(l=12, lifted=True)),
+    "lifted_l16_active_B16": (lambda: synth.erdos_renyi(250, 0.06, 23), 16,
+                              dict(l=16, lifted=True, l_active=np.array([1 + (7 * b) % 16 for b in range(16)],
+                                                                        np.int32))),
+    # l = n (the largest lift of Table 2)
+    "lifted_l_eq_n_B8": (lambda: synth.erdos_renyi(48, 0.2, 24), 8, dict(l=48, lifted=True)),
     "B1": (lambda: synth.erdos_renyi(200, 0.05, 10), 1, {}),
     "B2": (lambda: synth.erdos_renyi(200, 0.05, 11), 2, {}),
     "B4_lifted": (lambda: synth.erdos_renyi(200, 0.05, 12), 4, dict(l=2, lifted=True)),
@@ -128,7 +136,7 @@ def test_fp32_teacher_forced_parity(name):
 
 
 @pytest.mark.parametrize("name", ["er_unit_B16", "ba_hubs_B64", "lifted_l2_B16", "er_pm1_B24_tiles",
-                                  "laplacian_B16", "lifted_l8_B16", "lifted_l4_active_B32"])
+                                  "laplacian_B16", "lifted_l8_B16", "lifted_l4_active_B32", "lifted_l12_B8"])
 def test_bf16_teacher_forced_parity(name):
     make, B, kw = CASES[name]
     g = make()
@@ -471,8 +479,8 @@ def test_workspace_too_small():
     assert st == deco.E_NOMEM and not h.value
 
 
-@pytest.mark.parametrize("lifted", [False, True])
-def test_step_calls_split_and_replayed_agree_bitwise(lifted):
+@pytest.mark.parametrize("lifted,l", [(False, 1), (True, 2), (True, 10)])
+def test_step_calls_split_and_replayed_agree_bitwise(lifted, l):
     """A step's cuts are completed by the next launch and every call ends with a drain: the
     same 12 steps (scored every step) taken as one call, as 12 calls and as two graph replays
     give the same iterates, traces, running best (cuts, steps, bits) and round score; reading
@@ -480,7 +488,7 @@ def test_step_calls_split_and_replayed_agree_bitwise(lifted):
     gs = [synth.barabasi_albert(700, 3, 11), synth.erdos_renyi(300, 0.05, 12)]
     g = synth.block_diagonal(gs)
     G = deco.Graph(g)
-    B, l = 32, (2 if lifted else 1)
+    B = 32
     x0 = torch.from_numpy(synth.uniform_batch(g.n, l * B, 4)).to(torch.bfloat16).cuda()
     runs = []
     for mode in ("one", "each", "graph"):
