@@ -203,6 +203,14 @@ deco_status deco_autotune(deco_handle *h, int32_t steps);
  * Synchronous (uploads the work list). */
 typedef struct deco_schedule {
   int32_t lanes_per_row, long_row, xcd_mode, blocks_per_xcd, nnz_per_item, lane_elems;
+  int32_t resident_cols; /* > 0: resident steps (unlifted or l = 1 handles): every step of a
+                            deco_step call in one launch, one workgroup per (graph, tile of
+                            resident_cols columns) holding that tile of the graph's rows in
+                            LDS for all the steps (1, 2, 4, 8 or 16 dividing B; the graph's
+                            rows times the tile, two buffers, must fit one workgroup's LDS,
+                            else DECO_E_UNSUPPORTED); score-only passes and momentum steps
+                            keep the step kernel with its default schedule (the other fields
+                            are not used then). 0: the step kernel with the fields above */
 } deco_schedule;
 deco_status deco_set_schedule(deco_handle *h, const deco_schedule *s);
 

@@ -7,8 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = [os.path.join(HERE, "csrc", f)
-           for f in ("kernels.hip", "step_momentum.hip", "step_wide.hip", "step_wide_momentum.hip", "api.hip",
-                     "mpnn.hip")]
+           for f in ("kernels.hip", "step_momentum.hip", "step_wide.hip", "step_wide_momentum.hip", "resident.hip",
+                     "api.hip", "mpnn.hip")]
 LIB = os.path.join(HERE, "libdeco.so")
 
 FLAGS = [

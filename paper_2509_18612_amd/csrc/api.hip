@@ -45,11 +45,31 @@ struct Schedule {
   int nitems = 0;
   std::vector<int4> items;  // {first row, end row, graph, tile | long << 16}
   int seg[9] = {0};
+  // resident schedule (resident.hip): rbt columns of a graph's rows per workgroup, all steps of
+  // a call in one launch; 0 = the step kernel
+  int rbt = 0;
+  int rmax_rows = 0;
+  std::vector<int4> ritems;  // {graph, first row, end row, first column}
 };
+
+// LDS a workgroup may use (queried once; gfx950 allows up to 160 KB per workgroup).
+int lds_limit() {
+  static int v = [] {
+    int dev = 0, bytes = 65536;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      bytes = 65536;
+    return bytes;
+  }();
+  return v;
+}
+
+// LDS left for the resident kernel's dynamic part (its static arrays take at most ~2 KB).
+constexpr int kResidentStaticLds = 2048;
 
 struct Layout {
   size_t xalt, bits0, bits1, bits2, best_bits, mask, acc, cur_cut, best_cut, best_step, ctrl, dw, eta,
-      slots, sw, items, seg, goff, thr, delta, l_active, flags, xt0, xt1, total;
+      slots, sw, items, seg, goff, thr, delta, l_active, flags, xt0, xt1, ritems, total;
   long long items_cap;
   int R;
 };
@@ -114,6 +134,8 @@ Layout layout_for(long long n, long long nnz, int G, const deco_params* p, bool 
   // dense path: transposed ping-pong iterates
   L.xt0 = take(dense ? (size_t)n * C * elem_size(p->x_dtype) : 0);
   L.xt1 = take(dense ? (size_t)n * C * elem_size(p->x_dtype) : 0);
+  // resident schedule: one work item per (graph, column) at most
+  L.ritems = take(dense || p->l != 1 ? 0 : sizeof(int4) * (size_t)G * p->B);
   L.total = off;
   return L;
 }
@@ -217,6 +239,27 @@ std::vector<int> balance(const std::vector<int4>& ch, const std::vector<int>& rp
 
 bool build_schedule(deco_handle* h, Schedule& s) {
   const int B = h->p.B;
+  if (s.rbt > 0) {
+    // every graph's rows times rbt columns, two buffers, in one workgroup's LDS
+    if (h->dense || h->p.l != 1 || B % s.rbt != 0 || (s.rbt & (s.rbt - 1)) || s.rbt > 16) return false;
+    const std::vector<int>& goff = h->goff_host;
+    int maxr = 1;
+    for (int g = 0; g < h->G; ++g) maxr = std::max(maxr, goff[g + 1] - goff[g]);
+    if (resident_lds_bytes(maxr, s.rbt, h->dtype) + kResidentStaticLds > (size_t)lds_limit()) return false;
+    // largest graphs first: the dispatcher hands the long items out first
+    std::vector<int> order(h->G);
+    for (int g = 0; g < h->G; ++g) order[g] = g;
+    const std::vector<int>& rp = h->rp_host;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      return (long long)(rp[goff[x + 1]] - rp[goff[x]]) + (goff[x + 1] - goff[x]) >
+             (long long)(rp[goff[y + 1]] - rp[goff[y]]) + (goff[y + 1] - goff[y]);
+    });
+    s.ritems.clear();
+    for (int g : order)
+      for (int c0 = 0; c0 < B; c0 += s.rbt) s.ritems.push_back(make_int4(g, goff[g], goff[g + 1], c0));
+    s.rmax_rows = maxr;
+    // the step kernel's work list is built too: score-only passes and momentum steps use it
+  }
   const int Bt = s.Wc * s.vec;
   if (Bt <= 0 || Bt > 256 || B % Bt != 0 || (B >= 8 && Bt % 8 != 0)) return false;
   if (B % kMinTile == 0 && Bt < kMinTile) return false;
@@ -262,6 +305,11 @@ bool build_schedule(deco_handle* h, Schedule& s) {
 
 deco_status upload_schedule(deco_handle* h) {
   char* ws = h->ws;
+  if (h->sched.rbt > 0) {
+    HIP_TRY(h, hipMemcpyAsync(ws + h->lay.ritems, h->sched.ritems.data(), sizeof(int4) * h->sched.ritems.size(),
+                              hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, prepare_resident(h->args, h->dtype, h->sched.rbt, h->sched.rmax_rows));
+  }
   // device form: {x, y, first slot, end slot}, {graph, tile, long-row flag, 0}
   const std::vector<int>& rp = h->rp_host;
   std::vector<int4> dev(2 * h->sched.items.size());
@@ -349,6 +397,11 @@ deco_status launch_steps(deco_handle* h, int steps, int do_update, int force) {
   StepArgs a = h->args;
   a.do_update = do_update;
   a.force_score = force;
+  if (h->sched.rbt > 0 && do_update && !force && a.vel == nullptr && !h->dense) {
+    const hipError_t e = launch_resident(a, h->dtype, h->sched.rbt, reinterpret_cast<const int4*>(h->ws + h->lay.ritems),
+                                         (int)h->sched.ritems.size(), h->sched.rmax_rows, steps, h->stream);
+    return e == hipSuccess ? DECO_OK : poison(h, e);
+  }
   for (int s = 0; s < steps; ++s) {
     const hipError_t e = h->dense ? launch_dense_step(a, h->stream)
                                   : launch_step(a, h->dtype, h->sched.vec, h->sched.grid, h->stream);
@@ -937,6 +990,14 @@ deco_status deco_autotune(deco_handle* h, int32_t steps) {
       }
     }
   }
+  // resident schedules (all steps of a call in one launch, each workgroup's tile in LDS) for
+  // every tile width that fits
+  if (h->p.l == 1)
+    for (int bt : {1, 2, 4, 8, 16}) {
+      Schedule s = base;
+      s.rbt = bt;
+      cand.push_back(s);
+    }
   hipEvent_t e0, e1;
   HIP_TRY(h, hipEventCreate(&e0));
   HIP_TRY(h, hipEventCreate(&e1));
@@ -980,6 +1041,7 @@ deco_status deco_autotune(deco_handle* h, int32_t steps) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     Schedule keep = h->sched;
     keep.items.clear();
+    keep.ritems.clear();
     g_cache[cache_key(h)] = keep;
   }
   return deco_start(h, &sa);
@@ -1010,7 +1072,12 @@ deco_status deco_set_schedule(deco_handle* h, const deco_schedule* q) {
   s.xcd_mode = q->xcd_mode;
   s.blocks_per_xcd = q->blocks_per_xcd;
   s.nnz_per_item = q->nnz_per_item;
-  if (!build_schedule(h, s)) return DECO_E_INVAL;
+  if (q->resident_cols < 0) return DECO_E_INVAL;
+  if (q->resident_cols > 0) {
+    s = default_schedule(h);  // the step kernel's part (score-only passes, momentum) as by default
+    s.rbt = q->resident_cols;
+  }
+  if (!build_schedule(h, s)) return s.rbt > 0 ? DECO_E_UNSUPPORTED : DECO_E_INVAL;
   h->sched = std::move(s);
   return upload_schedule(h);
 }
@@ -1030,6 +1097,12 @@ deco_status deco_schedule_string(const deco_handle* h, char* buf, int32_t cap) {
     return DECO_OK;
   }
   const Schedule& s = h->sched;
+  if (s.rbt > 0) {
+    std::snprintf(buf, (size_t)cap, "resident cols=%d items=%d max_rows=%d lds=%zu | vec=%d Wc=%d R=%d", s.rbt,
+                  (int)s.ritems.size(), s.rmax_rows, resident_lds_bytes(s.rmax_rows, s.rbt, h->dtype), s.vec, s.Wc,
+                  h->R);
+    return DECO_OK;
+  }
   std::snprintf(buf, (size_t)cap,
                 "vec=%d Wc=%d dlong=%d tile=%d tiles=%d xcd_mode=%d grid=%d items=%d "
                 "rows_per_item=%d nnz_per_item=%d R=%d",

@@ -114,6 +114,14 @@ hipError_t launch_drain(StepArgs a, long long n, const int* goff, hipStream_t s)
 // Workgroups that complete one step's G * B cuts (256 each, at most 64).
 int completion_blocks(long long GB);
 hipError_t launch_fill_eta(float* eta, int B, float v, hipStream_t s);
+// Resident steps (resident.hip): 'steps' steps of an unlifted (or l = 1) batch in one launch,
+// one workgroup per item {graph, first row, end row, first column} holding bt columns of the
+// graph's rows in LDS; then the step counter advances by 'steps'. prepare_resident raises the
+// kernels' LDS limit once per schedule (outside stream capture).
+size_t resident_lds_bytes(int max_rows, int bt, int dtype);
+hipError_t prepare_resident(const StepArgs& a, int dtype, int bt, int max_rows);
+hipError_t launch_resident(const StepArgs& a, int dtype, int bt, const int4* items, int nitems, int max_rows,
+                           int steps, hipStream_t s);
 // Component sums of a many-component batch (l > kMaxL) into the score handle's iterate.
 hipError_t launch_sides(const void* x0, const void* x1, void* s0, void* s1, const DevCtrl* cx, const DevCtrl* cs,
                         long long n, int B, int l, int dtype, hipStream_t s);

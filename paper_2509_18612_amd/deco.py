@@ -59,7 +59,7 @@ class deco_solve_params(ct.Structure):
 class deco_schedule(ct.Structure):
     _fields_ = [("lanes_per_row", ct.c_int32), ("long_row", ct.c_int32),
                 ("xcd_mode", ct.c_int32), ("blocks_per_xcd", ct.c_int32), ("nnz_per_item", ct.c_int32),
-                ("lane_elems", ct.c_int32)]
+                ("lane_elems", ct.c_int32), ("resident_cols", ct.c_int32)]
 
 
 class deco_solve_report(ct.Structure):
@@ -316,8 +316,9 @@ class Handle:
         _check(lib().deco_autotune(self.h, int(steps)), "deco_autotune")
 
     def set_schedule(self, lanes_per_row, long_row=64, xcd_mode=0, blocks_per_xcd=128, nnz_per_item=2048,
-                     lane_elems=0):
-        q = deco_schedule(lanes_per_row, long_row, xcd_mode, blocks_per_xcd, nnz_per_item, lane_elems)
+                     lane_elems=0, resident_cols=0):
+        q = deco_schedule(lanes_per_row, long_row, xcd_mode, blocks_per_xcd, nnz_per_item, lane_elems,
+                          resident_cols)
         _check(lib().deco_set_schedule(self.h, ct.byref(q)), "deco_set_schedule")
 
     def schedule(self) -> str:

@@ -401,3 +401,54 @@ def test_solve_unlifted_only_and_lifted_only(mode, steps):
     assert r["best_cut"][0] == oracle.cut(g, r["z"])
     gb, _ = oracle.greedy(g, orders=2, seed=1)
     assert r["best_cut"][0] > 0.9 * gb
+
+
+def test_uneven_512_graph_batch_resident():
+    """The 512-graph uneven batch on the resident schedule (16 columns of a graph per
+    workgroup, all steps of a call in one launch), bfloat16, uniform starts, eta = 0.02: 10
+    teacher-forced steps with exact cuts of all 512 x 64 pairs at every iterate and every row
+    of 16 whole graphs against the oracle's step (per-row float32 bound plus one bfloat16
+    ulp), the best bits' cuts, and then 10 steps in one launch equal to 10 launches of one
+    step, bit for bit."""
+    g = synth.uneven_batch(512, 7)
+    G = deco.Graph(g)
+    B, T, eta = 64, 10, 0.02
+    h = deco.Handle(G, B=B, x_dtype=deco.BF16, eta=eta, seed=1)
+    h.set_schedule(64, 1 << 30, 0, 128, 2048, 0, 16)
+    h.start(deco.INIT_UNIFORM, batch=0)
+    tr = h.set_trace(T + 1)
+    goff = g.graph_row_offset
+    blocks = [block_of(g, i) for i in range(16)]
+    x = to_np(h.read_x()).astype(np.float64)
+    moved = checked = 0
+    for t in range(T):
+        h.step(1, use_graph=True)
+        xn = to_np(h.read_x()).astype(np.float64)
+        assert np.array_equal(tr.cpu().numpy()[t], oracle_cuts(g, x, B, 1, False)[0])
+        for i, bg in enumerate(blocks):
+            r0, r1 = goff[i], goff[i + 1]
+            want = oracle.step(bg, x[r0:r1], eta)
+            cmp, tol = step_tol(bg, x[r0:r1], want, eta, deco.BF16)
+            d = np.abs(xn[r0:r1] - cmp)
+            assert np.all(d <= tol), f"step {t} graph {i}: {(d > tol).sum()} off, max {d.max():.3e}"
+            mv = np.abs(want - x[r0:r1]) > tol
+            moved += int(mv.sum())
+            checked += mv.size
+        x = xn
+    h.round_score()
+    bc, bs, bb = h.best()
+    assert np.array_equal(oracle.cut_batch(g, deco.bits_to_z(bb, B)), bc)
+    assert moved > 0.3 * checked
+    # one launch for 10 more steps equals 10 launches of one step
+    x_mid = h.read_x().clone()
+    h.step(10)
+    one = to_np(h.read_x())
+    h2 = deco.Handle(G, B=B, x_dtype=deco.BF16, eta=eta, seed=1)
+    h2.set_schedule(64, 1 << 30, 0, 128, 2048, 0, 16)
+    h2.start(deco.INIT_USER, x0=x_mid)
+    for _ in range(10):
+        h2.step(1)
+    assert np.array_equal(one, to_np(h2.read_x()))
+    print(f"uneven batch resident: {h.schedule()}")
+    h.destroy()
+    h2.destroy()

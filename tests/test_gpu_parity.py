@@ -601,3 +601,124 @@ def test_momentum_with_captured_graphs_and_errors():
         h.set_momentum(float("nan"))
     ref.destroy()
     h.destroy()
+
+
+# Resident schedule: every step of a call in one launch, each workgroup holding a tile of
+# columns of one graph's rows in LDS (set_schedule resident_cols).
+def resident(bt):
+    return (64, 1 << 30, 0, 128, 2048, 0, bt)
+
+
+RESIDENT = {
+    "er_unit_B16_bt16": ("er_unit_B16", 16, deco.F32),
+    "er_unit_B16_bt1": ("er_unit_B16", 1, deco.F32),
+    "ba_hubs_B64_bt8": ("ba_hubs_B64", 8, deco.F32),
+    "ba_hubs_B64_bt16_bf16": ("ba_hubs_B64", 16, deco.BF16),
+    "er_pm1_B24_bt8": ("er_pm1_B24_tiles", 8, deco.F32),
+    "er_pm1_B24_bt4_bf16": ("er_pm1_B24_tiles", 4, deco.BF16),
+    "laplacian_B16_bt4": ("laplacian_B16", 4, deco.F32),
+    "lifted_l1_B16_bt16": ("unlifted_as_l1_lifted", 16, deco.F32),
+    "intw_B8_bt8": ("er_intw_B8", 8, deco.F32),
+    "per_init_eta_bt2": ("per_init_eta", 2, deco.F32),
+    "B1_bt1": ("B1", 1, deco.F32),
+    "B2_bt2_bf16": ("B2", 2, deco.BF16),
+}
+
+
+@pytest.mark.parametrize("name", sorted(RESIDENT))
+def test_resident_teacher_forced_parity(name):
+    """The resident kernel, one step per call: teacher-forced iterates (float32: 1e-5 or the
+    summation bound; bfloat16: one ulp plus the bound), exact cuts of every iterate, the
+    running best and its bits, against the oracle."""
+    case, bt, dtype = RESIDENT[name]
+    make, B, kw = CASES[case]
+    g = make()
+    worst, _, s = check_run(g, B, 30, dtype=dtype, schedule=resident(bt), **kw)
+    assert s.startswith(f"resident cols={bt}")
+    print(f"{name}: max |dX| = {worst:.2e}, schedule: {s}")
+
+
+def test_resident_multi_graph_batch_and_real_weights():
+    """Resident steps on a block-diagonal batch (a workgroup per graph and tile; the largest
+    graphs first) and on real weights (double cut partials: within the float32-to-double
+    bound of the step kernel, here much tighter)."""
+    gs = [synth.erdos_renyi(150, 0.1, 1), synth.barabasi_albert(220, 3, 2), synth.cycle(9), synth.star(40),
+          synth.erdos_renyi(90, 0.2, 3), synth.edgeless(5)]
+    bd = synth.block_diagonal(gs)
+    worst, _, s = check_run(bd, 8, 25, schedule=resident(8))
+    assert s.startswith("resident cols=8")
+    g = synth.erdos_renyi(300, 0.06, 21)
+    m = g.nnz // 2
+    g = synth.with_weights(g, np.random.default_rng(3).uniform(0.1, 2.0, m).astype(np.float32))
+    r = run_teacher_forced(g, 16, 10, schedule=resident(16))
+    for t, X in enumerate(r["xs"]):
+        cuts, _ = oracle_cuts(g, X, 16, 1, False)
+        if t < 10:
+            # scored by the resident kernel (double partials)
+            tol = np.abs(g.w.astype(np.float64)).sum() * 2.0 ** -40
+        else:
+            # the last iterate is scored by the step kernel's score pass (float32 partials)
+            tol = 0.5 * np.abs(g.w.astype(np.float64)).sum() * 2048 * 2.0 ** -24
+        assert np.all(np.abs(r["trace"][t] - cuts) <= tol), f"cut at step {t}"
+        if t < 10:
+            assert np.abs(r["xs"][t + 1] - oracle.step(g, X, 0.1)).max() <= 1e-5
+    r["handle"].destroy()
+
+
+@pytest.mark.parametrize("bt,dtype", [(16, deco.BF16), (1, deco.F32), (4, deco.F32)])
+def test_resident_one_launch_equals_step_calls(bt, dtype):
+    """Many steps in one resident launch give bit for bit the iterates, traces, running best
+    (cuts, steps, bits) and round score of one launch per step and of graph replays (odd and
+    even step counts, so the final iterate lands in either buffer)."""
+    gs = [synth.barabasi_albert(700, 3, 11), synth.erdos_renyi(300, 0.05, 12)]
+    g = synth.block_diagonal(gs)
+    G = deco.Graph(g)
+    B = 32
+    tdt = torch.float32 if dtype == deco.F32 else torch.bfloat16
+    x0 = torch.from_numpy(synth.uniform_batch(g.n, B, 4)).to(tdt).cuda()
+    runs = []
+    for mode in ("one", "each", "graph"):
+        h = deco.Handle(G, B=B, x_dtype=dtype, eta=0.05, seed=3)
+        h.set_schedule(*resident(bt))
+        h.start(deco.INIT_USER, x0=x0)
+        tr = h.set_trace(24)
+        if mode == "one":
+            h.step(13)
+            h.step(8)
+        elif mode == "each":
+            for _ in range(21):
+                h.step(1)
+        else:
+            h.step(13, use_graph=True)
+            h.step(8, use_graph=True)
+        cut_T, bits_T = h.round_score()
+        best = h.best()
+        runs.append((to_np(h.read_x()), tr.cpu().numpy(), best, to_np(cut_T), to_np(bits_T)))
+        h.destroy()
+    ref = runs[0]
+    assert np.array_equal(ref[1][21], oracle_cuts(g, ref[0].astype(np.float64), B, 1, False)[0])
+    zb = deco.bits_to_z(ref[2][2], B)
+    assert np.array_equal(oracle.cut_batch(g, zb), ref[2][0])
+    for other in runs[1:]:
+        assert np.array_equal(ref[0], other[0])
+        assert np.array_equal(ref[1][:22], other[1][:22])
+        for u, v in zip(ref[2], other[2]):
+            assert np.array_equal(u, v)
+        assert np.array_equal(ref[3], other[3]) and np.array_equal(ref[4], other[4])
+
+
+def test_resident_rejects_tiles_that_do_not_fit():
+    g = synth.barabasi_albert(3000, 3, 5)
+    h = deco.Handle(deco.Graph(g), B=32, x_dtype=deco.F32, eta=0.05)
+    with pytest.raises(deco.DecoError) as e:
+        h.set_schedule(*resident(16))  # 2 x 3000 x 16 x 4 bytes does not fit
+    assert e.value.status == deco.E_UNSUPPORTED
+    with pytest.raises(deco.DecoError):
+        h.set_schedule(*resident(3))  # not a power of two
+    h.set_schedule(*resident(2))
+    h.destroy()
+    hl = deco.Handle(deco.Graph(g), B=8, l=2, lifted=True, eta=0.05)
+    with pytest.raises(deco.DecoError) as e:
+        hl.set_schedule(*resident(1))  # lifted l > 1 keeps the step kernel
+    assert e.value.status == deco.E_UNSUPPORTED
+    hl.destroy()
