@@ -37,10 +37,11 @@ def log(msg):
     print(f"# {msg}", file=sys.stderr, flush=True)
 
 
-def measured_traffic(which):
+def measured_traffic(which, schedule):
     """Fabric bytes per launch of a step-kernel shape from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by the factor a copy of known size gives), or
-    None when the kernel source has changed since the counters were taken."""
+    None when the kernel source has changed since the counters were taken or the counters
+    were taken on another schedule than the one timed here."""
     import hashlib
     try:
         lines = open(TRAFFIC_SUMMARY).read().splitlines()
@@ -52,7 +53,7 @@ def measured_traffic(which):
             k, v = ln[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
     sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if vals.get("kernels.hip sha256") != sha:
+    if vals.get("kernels.hip sha256") != sha or vals.get(f"schedule ({which})") != schedule:
         return None
     v = vals.get(f"traffic bytes per launch ({which})")
     return int(v) if v else None
@@ -471,7 +472,7 @@ def main():
     dk = k32[dom]
     achieved = dk["bytes"] / (dk["us"] * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(f"f32 {dom}"),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(f"f32 {dom}", dk["schedule"]),
                 "kernel": f"k_step {dom} f32" + (f" l={l_max} ({l_act} active)" if dom == "lifted" else ""),
                 "bytes_per_launch": dk["bytes"], "us_per_launch": round(dk["us"], 3),
                 "schedule": dk["schedule"]}

@@ -193,7 +193,7 @@ deco_status deco_autotune(deco_handle *h, int32_t steps);
  * lanes_per_row: lanes of one row team, which holds one row's initialisation tile (power
  * of two <= 64; the tile is lanes_per_row * (16 bytes / element size) columns, 8 bytes for
  * lifted bfloat16; it must divide B, hold at most 256 columns, and at least 64 when 64
- * divides B); long_row: rows with more neighbours get a work item of their own (>= 16; rows
+ * divides B for unlifted handles, 16 when 16 divides B for lifted ones); long_row: rows with more neighbours get a work item of their own (>= 16; rows
  * with more slots than nnz_per_item always do); xcd_mode: 0 = each XCD owns a row range
  * for every tile, 1 = each XCD owns tiles; blocks_per_xcd: workgroups per XCD (1..4096;
  * with more items than workgroups a workgroup walks several); nnz_per_item: target slots

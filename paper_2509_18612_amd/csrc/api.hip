@@ -28,7 +28,17 @@ using namespace deco;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kMinTile = 64;       // narrowest initialisation tile when B >= 64
+constexpr int kMinTile = 64;       // narrowest initialisation tile when B >= 64 (unlifted)
+constexpr int kMinTileLifted = 16; // lifted rows carry l values per initialisation: narrower tiles
+
+// Narrowest initialisation tile of a handle: unlifted tiles of at least 64 when 64 divides B
+// (narrower ones multiply the per-slot work without shrinking it); lifted rows hold l values
+// per initialisation, so tiles down to 16 keep a lane's gathers wide and let each XCD own a
+// tile small enough for its L2.
+int min_tile(int B, int l) {
+  if (l >= 2) return B % kMinTileLifted == 0 ? kMinTileLifted : (B >= 8 ? 8 : B);
+  return B % kMinTile == 0 ? kMinTile : (B >= 8 ? 8 : B);
+}
 constexpr int kMinItemSlots = 128; // smallest nnz_per_item
 constexpr int kMaxBlocksPerXcd = 4096;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -99,7 +109,7 @@ Layout layout_for(long long n, long long nnz, int G, const deco_params* p, bool 
   // and the row after it hold more than nnz_per_item >= kMinItemSlots slots, or the chunk
   // holds kRmax rows, or ends a graph, or precedes a row isolated by the neighbour limit
   // (at least 17 neighbours)
-  const long long nbt_max = p->B % kMinTile == 0 ? p->B / kMinTile : (p->B >= 8 ? p->B / 8 : 1);
+  const long long nbt_max = std::max(1, p->B / min_tile(p->B, p->l));
   (void)vec;
   L.R = G >= 16 ? 1 : 16;
   L.items_cap = nbt_max * (2 * (n + nnz) / kMinItemSlots + n / kRmax + 2 * (nnz / 17) + (long long)G + 8);
@@ -262,7 +272,7 @@ bool build_schedule(deco_handle* h, Schedule& s) {
   }
   const int Bt = s.Wc * s.vec;
   if (Bt <= 0 || Bt > 256 || B % Bt != 0 || (B >= 8 && Bt % 8 != 0)) return false;
-  if (B % kMinTile == 0 && Bt < kMinTile) return false;
+  if (B >= 8 && Bt < min_tile(B, h->p.l)) return false;
   if (s.Wc > 64) return false;
   if (s.dlong < 16 || s.nnz_per_item < kMinItemSlots || s.nnz_per_item > kEmax) return false;
   const int nbt = B / Bt;
@@ -343,7 +353,7 @@ Schedule default_schedule(deco_handle* h) {
   // lifted rows: half-width tiles (twice the teams) when the tile stays wide enough
   if (h->p.l > 1 && s.Wc > 1) {
     const int bt = (s.Wc / 2) * s.vec;
-    if (bt >= (h->p.B % kMinTile == 0 ? kMinTile : 8) && bt % 8 == 0) s.Wc /= 2;
+    if (bt >= std::max(min_tile(h->p.B, 1), 8) && bt % 8 == 0) s.Wc /= 2;
   }
   s.dlong = 1 << 30;  // rows are isolated only by the item size
   s.xcd_mode = 0;
@@ -966,14 +976,17 @@ deco_status deco_autotune(deco_handle* h, int32_t steps) {
   const Schedule base = default_schedule(h);
   std::vector<Schedule> cand;
   const int vec = base.vec;
-  const int min_tile = h->p.B % kMinTile == 0 ? kMinTile : std::min(8, h->p.B);
+  // tiles of a quarter of the widest and up (narrower lifted tiles, each XCD owning its own,
+  // were measured slower at BA(10^4, 4), B = 256: set_schedule still accepts them)
+  const int mt = min_tile(h->p.B, h->p.l);
+  const int wspan = 4;
   // lane widths: the native one, and 4 bfloat16 per lane for unlifted bfloat16 rows (twice the
   // lanes per tile: one row team per wave at B = 256)
   std::vector<int> vecs{vec};
   if (h->dtype == DECO_BF16 && vec == 8) vecs.push_back(4);
   for (int vw : vecs) {
     const int wmax_v = max_wc(vw, h->p.B);
-    for (int Wc = wmax_v; Wc >= 1 && Wc * vw >= min_tile && Wc * 4 >= wmax_v; Wc /= 2) {
+    for (int Wc = wmax_v; Wc >= 1 && Wc * vw >= mt && Wc * wspan >= wmax_v; Wc /= 2) {
       for (int npi : {128, 256, 512, 1024, 2048}) {
         for (int mode = 0; mode < 2; ++mode) {
           if (mode == 1 && h->p.B / (Wc * vw) < 2) continue;
