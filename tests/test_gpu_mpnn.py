@@ -118,42 +118,27 @@ def test_training_on_deco_labels_decreases_loss_and_learned_start():
     h.destroy()
 
 
-def steps_to_target(G, B, kind, target, T, seed, y=None, eta=0.05):
-    h = deco.Handle(G, B=B, eta=eta, seed=seed)
-    h.start(kind, scale=1e4, sigma2=0.8, batch=0, magnitude=y)
-    tr = h.set_trace(T + 1)
-    h.step(T, use_graph=True)
-    h.round_score()
-    best = np.maximum.accumulate(tr.cpu().numpy()[:, 0, :].max(axis=1))
-    h.destroy()
-    hit = np.nonzero(best >= target)[0]
-    return int(hit[0]) if hit.size else None, float(best[-1])
-
-
 def test_learned_start_gain_steps_to_target():
-    """Trains on DECO labels of 24 BA graphs, then compares steps to 0.995 of a reference
-    best cut for the learned start and the importance-based start on held-out BA graphs
-    (paired seeds). The gain is reported; no sign is asserted (parity unpinned)."""
-    rng = np.random.default_rng(1)
-    graphs = []
-    for i in range(6):
-        parts = [synth.barabasi_albert(int(rng.integers(500, 3000)), int(rng.integers(2, 7)), 500 + 4 * i + j)
-                 for j in range(4)]
-        G = deco.Graph(synth.block_diagonal(parts))
-        r = deco.solve(G, B=64, K=8, l_max=2, rounds=2, evo_rounds=1, T_q=300, T_l=100, seed=i)
-        graphs.append((G, deco.Mpnn().labels(G, r["z"])))
-    net = deco.Mpnn(deco.pack_mpnn(ompnn.init_params(1)))
-    train(net, graphs, 300)
-    rows = []
-    for k in range(4):
-        g = synth.barabasi_albert(5000, int(rng.integers(2, 7)), 9000 + k)
-        G = deco.Graph(g)
-        ref = deco.solve(G, B=128, K=8, l_max=2, rounds=2, evo_rounds=1, T_q=400, T_l=100, seed=50 + k)
-        target = 0.995 * ref["best_cut"][0]
-        y = net.forward(G)
-        s_idi, b_idi = steps_to_target(G, 128, deco.INIT_IDI, target, 600, 7 + k)
-        s_lrn, b_lrn = steps_to_target(G, 128, deco.INIT_LEARNED, target, 600, 7 + k, y)
-        rows.append((s_idi, s_lrn, b_idi, b_lrn, target))
-    for r in rows:
-        print(f"steps to target: IDI {r[0]}  learned {r[1]}  (best {r[2]:.0f} vs {r[3]:.0f}, target {r[4]:.0f})")
-    assert all(r[3] > 0 for r in rows)
+    """The learned-start protocol of paper_2509_18612_amd.learned at a test's size: train on DECO
+    labels of 40 BA graphs, evaluate 8 held-out BA(5000) graphs (paired seeds, steps of the
+    unlifted batch to 0.995 of the best of a long unlifted batch). The full-size protocol
+    (2,000 training graphs, 200 BA(20000) + 200 ER(5000, 0.002) graphs) measured no gain over
+    the importance-based start (paper_2509_18612_amd/data/mpnn_ba_report.json), so the
+    criterion asserted here is non-regression: on average the learned start needs at most 10%
+    more steps than IDI, and both reach the target on every graph. Parity unpinned (no closed
+    form or published number for the gain)."""
+    from paper_2509_18612_amd import learned
+    graphs = [synth.barabasi_albert(n, m, 700 + i) for i, (n, m, _) in enumerate(learned.training_specs(40, 3))]
+    batches = learned.label_batches(graphs, 10, seed=11)
+    net = deco.Mpnn(learned.glorot_params(3))
+    losses = learned.train(net, batches, 5, 2e-3, log=lambda _: None)
+    assert losses[-1] < losses[0]
+    rng = np.random.default_rng(4)
+    held = [synth.barabasi_albert(5000, int(rng.integers(2, 7)), 9000 + k) for k in range(8)]
+    rows = learned.evaluate(net, held, 8, 128, 600, 10 ** -1.5, 77, log=lambda _: None)
+    summ = learned.summarise(rows, 600)
+    b = summ["batch"]
+    print("learned start, 8 BA(5000):", b)
+    assert b["learned_fewer"] + b["learned_more"] + b["ties"] == b["graphs"] == 8
+    assert b["reached_idi"] == 8 and b["reached_learned"] == 8
+    assert b["steps_saved_when_both_reach"]["mean"] >= -0.1 * b["median_steps_idi"]
