@@ -353,7 +353,7 @@ Schedule default_schedule(deco_handle* h) {
   // lifted rows: half-width tiles (twice the teams) when the tile stays wide enough
   if (h->p.l > 1 && s.Wc > 1) {
     const int bt = (s.Wc / 2) * s.vec;
-    if (bt >= std::max(min_tile(h->p.B, 1), 8) && bt % 8 == 0) s.Wc /= 2;
+    if (bt >= std::max(min_tile(h->p.B, h->p.l), 8) && bt % 8 == 0) s.Wc /= 2;
   }
   s.dlong = 1 << 30;  // rows are isolated only by the item size
   s.xcd_mode = 0;
@@ -687,6 +687,7 @@ deco_status deco_init(deco_handle** out, const deco_graph* g, const deco_params*
   // every component active until a start says otherwise
   h->lact_host.assign(p->B, p->l);
   a.lact = reinterpret_cast<const int*>(ws + lay.l_active);
+  a.lall = 1;
   if (e == hipSuccess)
     e = hipMemcpyAsync(ws + lay.l_active, h->lact_host.data(), sizeof(int) * p->B, hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = launch_reset(a, a.acc, 2LL * lay.R * h->G * p->B, p->score_every, h->stream);
@@ -753,6 +754,14 @@ deco_status deco_start(deco_handle* h, const deco_start_args* s) {
       for (int b = 0; b < h->p.B; ++b) h->lact_host[b] = s->l_active ? s->l_active[b] : h->p.l;
       HIP_TRY(h, hipMemcpyAsync(ws + lay.l_active, h->lact_host.data(), sizeof(int) * h->p.B, hipMemcpyHostToDevice,
                                 h->stream));
+      int all = 1;
+      for (int b = 0; b < h->p.B; ++b) all = all && h->lact_host[b] == h->p.l;
+      if (all != h->args.lall) {
+        // captured launches hold the other step kernel
+        h->args.lall = all;
+        for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+        h->graphs.clear();
+      }
     }
     if (s->l_active) lact = reinterpret_cast<int*>(ws + lay.l_active);
   }

@@ -58,6 +58,8 @@ struct StepArgs {
   const float* eta; // [B]
   const int* lact;  // [B] active components of each initialisation (components at and past
                     // it are exactly 0 in X and are not gathered), or NULL (all l active)
+  int lall;         // host side: 1 when every initialisation has all L components active (the
+                    // launch then takes the step kernel without load predicates)
   uint8_t* bits[3]; // cut bits of the iterate scored at step t live in bits[t % 3]
   uint8_t* best_bits;
   uint8_t* mask;    // [2][G][NBY]: improvements of scored step t in mask[t & 1]

@@ -144,11 +144,13 @@ struct VecIO<uint16_t, 1> {
 };
 
 // Side of one initialisation from its l component values (float32, order i = 0..l-1).
+// The sum starts from x[0] itself: 0 + x[0] differs from x[0] only for x[0] = -0, and no
+// later sum or the comparison with 0 tells -0 from +0.
 template <int L>
 __device__ __forceinline__ bool side_of(const float (&x)[L], int lifted) {
-  float s = 0.0f;
+  float s = x[0];
 #pragma unroll
-  for (int i = 0; i < L; ++i) s = s + x[i];
+  for (int i = 1; i < L; ++i) s = s + x[i];
   if constexpr (L > 1) {
     return s >= 0.0f;  // l > 1 only exists lifted
   } else {
@@ -564,17 +566,22 @@ __device__ __forceinline__ size_t row_offset(int slot, int C) {
 }
 
 // Gathered values of component i of a neighbour row. Lifted rows skip the components at
-// and past the lane's active count na: those are exactly 0 in every row (the start writes
-// zeros and a zero neighbour sum keeps them there), so the skipped load is replaced by its
-// known value and the step's results are unchanged bit for bit.
-template <typename T, int VEC, int L>
+// and past the active count na: those are exactly 0 in every row (the start writes zeros
+// and a zero neighbour sum keeps them there), so the skipped load is replaced by its known
+// value and the step's results are unchanged bit for bit. ALL: every component is active
+// (no predicate on the loads).
+template <typename T, int VEC, int L, bool ALL>
 __device__ __forceinline__ typename VecIO<T, VEC>::raw gather_comp(const T* p, int i, int na) {
-  typename VecIO<T, VEC>::raw v{};
-  if (L == 1 || i < na) v = VecIO<T, VEC>::load_raw(p);
-  return v;
+  if constexpr (ALL || L == 1) {
+    return VecIO<T, VEC>::load_raw(p);
+  } else {
+    typename VecIO<T, VEC>::raw v{};
+    if (i < na) v = VecIO<T, VEC>::load_raw(p);
+    return v;
+  }
 }
 
-template <typename T, int VEC, int L, int WM, bool SELF>
+template <typename T, int VEC, int L, int WM, bool SELF, bool ALL>
 __device__ __forceinline__ void gather_window(const StepArgs& a, const T* __restrict__ X, T* __restrict__ Y,
                                               uint8_t* __restrict__ bw, const int* s_slot, const float* s_sw,
                                               float* s_part, int part_idx, int p, int pe, int bl, int lc, int gb,
@@ -599,7 +606,7 @@ __device__ __forceinline__ void gather_window(const StepArgs& a, const T* __rest
   for (int q = 0; q < W; ++q) {
     // slots past the share read row 0 (always present) and are not folded: no branch per load
 #pragma unroll
-    for (int i = 0; i < L; ++i) xr[q][i] = gather_comp<T, VEC, L>(X + row_offset<VEC>(sl[q], a.C) + i * B + bl, i, na);
+    for (int i = 0; i < L; ++i) xr[q][i] = gather_comp<T, VEC, L, ALL>(X + row_offset<VEC>(sl[q], a.C) + i * B + bl, i, na);
   }
   if (st.lazy) {
     st.zm = side_mask_raw<T, VEC, L>(st.xv, lifted);
@@ -638,7 +645,7 @@ struct WinBuf {
   typename VecIO<T, VEC>::raw xr[PW][L];
 };
 
-template <typename T, int VEC, int L, int PW>
+template <typename T, int VEC, int L, int PW, bool ALL>
 __device__ __forceinline__ void load_window(const StepArgs& a, const T* __restrict__ X, const int* s_slot, int p,
                                             int pe, int bl, int na, WinBuf<T, VEC, L, PW>& wb) {
   using IO = VecIO<T, VEC>;
@@ -653,7 +660,7 @@ __device__ __forceinline__ void load_window(const StepArgs& a, const T* __restri
   for (int q = 0; q < PW; ++q) {
     // slots past the share read row 0 (always present) and are not folded: no branch per load
 #pragma unroll
-    for (int i = 0; i < L; ++i) wb.xr[q][i] = gather_comp<T, VEC, L>(X + row_offset<VEC>(wb.sl[q], a.C) + i * B + bl, i, na);
+    for (int i = 0; i < L; ++i) wb.xr[q][i] = gather_comp<T, VEC, L, ALL>(X + row_offset<VEC>(wb.sl[q], a.C) + i * B + bl, i, na);
   }
 }
 
@@ -777,9 +784,11 @@ __device__ __forceinline__ void complete_step(const StepArgs& a, long long t, bo
 #define DECO_STEP_WAVES_PER_EU 3
 #endif
 
-// LF: the lifted flag known when compiling (0 or 1, packed rows) or -1 (read from a).
+// LF: the lifted flag known when compiling (0 or 1, rows of one component) or -1 (read from a).
 // MOM: heavy-ball momentum (velocity in a.vel); without it the update code has no velocity path.
-template <typename T, int VEC, int L, int WM, int LF, bool MOM>
+// ALL: every component of every initialisation is active (l > 1 rows gather without
+// predicates; chosen at launch from the host's copy of the active counts).
+template <typename T, int VEC, int L, int WM, int LF, bool MOM, bool ALL = false>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(DECO_STEP_WAVES_PER_EU)))
 void k_step(StepArgs a) {
   constexpr int W = Tune<T, L, VEC>::W;
@@ -886,11 +895,15 @@ void k_step(StepArgs a) {
     // lifted rows: components gathered per neighbour (the largest active count among the
     // lane's initialisations; the rest are exactly 0)
     int na = L;
-    if constexpr (L > 1) {
+    if constexpr (L > 1 && !ALL) {
       if (a.lact) {
         na = 0;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) na = max(na, bl + e < a.B ? a.lact[bl + e] : 0);
+        // the wave's largest count, held in a scalar register (gathering a component that
+        // is 0 everywhere changes nothing): the load predicates are uniform branches
+        for (int o = 32; o > 0; o >>= 1) na = max(na, __shfl_xor(na, o));
+        na = __builtin_amdgcn_readfirstlane(na);
       }
     }
     // the improvement mask word this thread folds at the end of the item (word-aligned rows
@@ -957,19 +970,19 @@ void k_step(StepArgs a) {
         // unlifted rows: one window at a time (their folds are short; the loads of a window
         // are waited for one by one)
         for (int p = c0; p < c1; p += W)
-          gather_window<T, VEC, L, WM, true>(a, X, Y, bw, s_slot, s_sw, s_acc, part_idx, p, c1, bl, lc, gb, eta, st,
-                                             sc, do_score, lifted, vel, na);
+          gather_window<T, VEC, L, WM, true, true>(a, X, Y, bw, s_slot, s_sw, s_acc, part_idx, p, c1, bl, lc, gb, eta,
+                                                   st, sc, do_score, lifted, vel, na);
       } else {
         // lifted rows: the next window's gathers are in flight during each fold
         constexpr int PW = PipeTune<T, L, VEC>::W;
         static_assert(3 * PW <= kSlotPad, "windows read past the staged slots");
         WinBuf<T, VEC, L, PW> wa, wb;
-        load_window<T, VEC, L, PW>(a, X, s_slot, c0, c1, bl, na, wa);
+        load_window<T, VEC, L, PW, ALL>(a, X, s_slot, c0, c1, bl, na, wa);
         for (int p = c0; p < c1; p += 2 * PW) {
-          load_window<T, VEC, L, PW>(a, X, s_slot, p + PW, c1, bl, na, wb);
+          load_window<T, VEC, L, PW, ALL>(a, X, s_slot, p + PW, c1, bl, na, wb);
           fold_window<T, VEC, L, WM, PW>(a, Y, bw, s_sw, s_acc, part_idx, p, c1, bl, lc, gb, eta, wa, st, sc,
                                          do_score, lifted, vel);
-          load_window<T, VEC, L, PW>(a, X, s_slot, p + 2 * PW, c1, bl, na, wa);
+          load_window<T, VEC, L, PW, ALL>(a, X, s_slot, p + 2 * PW, c1, bl, na, wa);
           fold_window<T, VEC, L, WM, PW>(a, Y, bw, s_sw, s_acc, part_idx, p + PW, c1, bl, lc, gb, eta, wb, st, sc,
                                          do_score, lifted, vel);
         }
@@ -1037,8 +1050,8 @@ void k_step(StepArgs a) {
         const int c0 = (E * sgi) >> nsl;
         const int c1 = (E * (sgi + 1)) >> nsl;
         for (int p = c0; p < c1; p += W)
-          gather_window<T, VEC, L, WM, false>(a, X, Y, bw, s_slot, s_sw, s_acc, 0, p, c1, bl, lc, gb, eta, st, sc,
-                                              do_score, lifted, vel, na);
+          gather_window<T, VEC, L, WM, false, ALL>(a, X, Y, bw, s_slot, s_sw, s_acc, 0, p, c1, bl, lc, gb, eta, st,
+                                                   sc, do_score, lifted, vel, na);
         // score of this chunk's share; the 16-bit partials hold at most one chunk
         if (do_score) {
           if constexpr (WM == kUnitW) st.wsum = c1 - c0;
@@ -1436,22 +1449,44 @@ hipError_t step_dispatch(const StepArgs& a, int wmode, int grid, hipStream_t s) 
       hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW, -1, true>), g, b, 0, s, a);
     return hipGetLastError();
   } else {
-  // packed rows take the lifted flag as a compile-time constant (no per-value flip)
-  constexpr bool kPackU = Packed<T, LL, VEC, kUnitW>::value, kPackP = Packed<T, LL, VEC, kPm1W>::value;
+  // rows of one component take the lifted flag (which selects x > 0 or x >= 0 as the side)
+  // as a compile-time constant; with l > 1 components the side is always sum >= 0, and
+  // 4-value lanes with every component active take the kernel without load predicates
+  constexpr int kOff = LL == 1 ? 0 : -1, kOn = LL == 1 ? 1 : -1;
+  const bool on = LL == 1 && a.lifted;
+  if constexpr (LL > 1 && LL <= 4 && VEC == 4) {
+    if (a.lact == nullptr || a.lall) {
+      if (wmode == kUnitW)
+        hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW, -1, false, true>), g, b, 0, s, a);
+      else if (wmode == kPm1W)
+        hipLaunchKernelGGL((k_step<T, VEC, LL, kPm1W, -1, false, true>), g, b, 0, s, a);
+      else if (wmode == kIntW)
+        hipLaunchKernelGGL((k_step<T, VEC, LL, kIntW, -1, false, true>), g, b, 0, s, a);
+      else
+        hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW, -1, false, true>), g, b, 0, s, a);
+      return hipGetLastError();
+    }
+  }
   if (wmode == kUnitW) {
-    if (kPackU && a.lifted)
-      hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW, kPackU ? 1 : -1, false>), g, b, 0, s, a);
+    if (on)
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW, kOn, false>), g, b, 0, s, a);
     else
-      hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW, kPackU ? 0 : -1, false>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW, kOff, false>), g, b, 0, s, a);
   } else if (wmode == kPm1W) {
-    if (kPackP && a.lifted)
-      hipLaunchKernelGGL((k_step<T, VEC, LL, kPm1W, kPackP ? 1 : -1, false>), g, b, 0, s, a);
+    if (on)
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kPm1W, kOn, false>), g, b, 0, s, a);
     else
-      hipLaunchKernelGGL((k_step<T, VEC, LL, kPm1W, kPackP ? 0 : -1, false>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kPm1W, kOff, false>), g, b, 0, s, a);
   } else if (wmode == kIntW) {
-    hipLaunchKernelGGL((k_step<T, VEC, LL, kIntW, -1, false>), g, b, 0, s, a);
+    if (on)
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kIntW, kOn, false>), g, b, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kIntW, kOff, false>), g, b, 0, s, a);
   } else {
-    hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW, -1, false>), g, b, 0, s, a);
+    if (on)
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW, kOn, false>), g, b, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW, kOff, false>), g, b, 0, s, a);
   }
   return hipGetLastError();
   }
