@@ -182,6 +182,31 @@ def kernel_only(deco, torch, G, B, args):
         print(f"# copied {a.numel() * 4} bytes x {args.kernel_steps}", flush=True)
         return
     import numpy as np
+    if args.kernel_only in ("reg3", "uneven"):
+        # the other workload shapes, bfloat16 X as in their bench entries: the tuned schedule
+        # unless pinned (--pin; a resident schedule with --resident-cols)
+        from paper_2509_18612_amd import synth
+        if args.kernel_only == "reg3":
+            g = synth.with_rademacher_weights(synth.random_regular3(1_000_000, 0), 3)
+            h = deco.Handle(deco.Graph(g), B=128, x_dtype=deco.BF16, eta=0.01)
+        else:
+            g = synth.uneven_batch(512, 7)
+            h = deco.Handle(deco.Graph(g), B=64, x_dtype=deco.BF16, eta=0.01)
+        if args.pin or args.resident_cols:
+            pin = [int(v) for v in args.pin.split(",")] if args.pin else [16]
+            h.set_schedule(*pin, resident_cols=args.resident_cols)
+        else:
+            h.autotune(5)
+        if args.kernel_only == "reg3":
+            h.start(deco.INIT_UNIFORM)
+        else:
+            h.start(deco.INIT_IDI, scale=1e4, sigma2=0.8)
+        h.synchronize()
+        h.step(args.kernel_steps)
+        h.synchronize()
+        print(f"# {args.kernel_only}: {args.kernel_steps} steps, schedule {h.schedule()}", flush=True)
+        h.destroy()
+        return
     dtype = deco.BF16 if args.storage == "bf16" else deco.F32
     l = 1 if args.kernel_only == "unlifted" else args.l
     la = None
@@ -414,9 +439,11 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=200)
     ap.add_argument("--others", default="er800,uneven,reg3,dense",
                     help="comma list of other workload shapes to time (empty: none)")
-    ap.add_argument("--kernel-only", choices=["unlifted", "lifted", "copy"], default=None,
+    ap.add_argument("--kernel-only", choices=["unlifted", "lifted", "copy", "reg3", "uneven"], default=None,
                     help="run only the step kernel of that shape for --kernel-steps launches (schedule pinned "
                          "by --pin, else autotuned), or a 256 MiB device copy, for counter runs")
+    ap.add_argument("--resident-cols", type=int, default=0,
+                    help="--kernel-only reg3/uneven: resident schedule with tiles of this many columns")
     ap.add_argument("--storage", choices=["bf16", "f32"], default="f32", help="--kernel-only: X storage")
     ap.add_argument("--l", type=int, default=4, help="--kernel-only lifted: components")
     ap.add_argument("--l-active", type=int, default=0, help="--kernel-only lifted: active components (0: all)")

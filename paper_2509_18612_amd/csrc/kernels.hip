@@ -592,19 +592,16 @@ __device__ __forceinline__ void gather_window(const StepArgs& a, const T* __rest
   constexpr int W = Tune<T, L, VEC>::W;
   const size_t B = (size_t)a.B;
   static_assert(W <= kSlotPad, "window reads past the staged slots");
-  // branch-free slot reads (the staging array is padded), then the slots past the share
-  // are replaced by row 0
+  // branch-free slot reads: past the share they are the next team's slots or, past the
+  // item's last slot, the zero padding (row 0); those gathers are in bounds and not folded
   const int rem = pe - p;
   int sl[W];
 #pragma unroll
-  for (int q = 0; q < W; ++q) {
-    const int v = s_slot[p + q];
-    sl[q] = q < rem ? v : 0;
-  }
+  for (int q = 0; q < W; ++q) sl[q] = s_slot[p + q];
   typename IO::raw xr[W][L];
 #pragma unroll
   for (int q = 0; q < W; ++q) {
-    // slots past the share read row 0 (always present) and are not folded: no branch per load
+    // slots past the share are gathered (in bounds) and not folded: no branch per load
 #pragma unroll
     for (int i = 0; i < L; ++i) xr[q][i] = gather_comp<T, VEC, L, ALL>(X + row_offset<VEC>(sl[q], a.C) + i * B + bl, i, na);
   }
@@ -650,15 +647,12 @@ __device__ __forceinline__ void load_window(const StepArgs& a, const T* __restri
                                             int pe, int bl, int na, WinBuf<T, VEC, L, PW>& wb) {
   using IO = VecIO<T, VEC>;
   const size_t B = (size_t)a.B;
-  const int rem = pe - p;
+  (void)pe;
+#pragma unroll
+  for (int q = 0; q < PW; ++q) wb.sl[q] = s_slot[p + q];
 #pragma unroll
   for (int q = 0; q < PW; ++q) {
-    const int v = s_slot[p + q];
-    wb.sl[q] = q < rem ? v : 0;
-  }
-#pragma unroll
-  for (int q = 0; q < PW; ++q) {
-    // slots past the share read row 0 (always present) and are not folded: no branch per load
+    // slots past the share are gathered (in bounds) and not folded: no branch per load
 #pragma unroll
     for (int i = 0; i < L; ++i) wb.xr[q][i] = gather_comp<T, VEC, L, ALL>(X + row_offset<VEC>(wb.sl[q], a.C) + i * B + bl, i, na);
   }
@@ -929,6 +923,7 @@ void k_step(StepArgs a) {
         s_slot[k] = a.slots[s0 + k];
         if (WM != kUnitW) s_sw[k] = a.sw[s0 + k];
       }
+      if (tid < kSlotPad) s_slot[E + tid] = 0;  // windows past the last slot gather row 0
       for (int i = tid; i <= R; i += kThreads) s_rp[i] = a.rp[x + i] + x + i - s0;
       __syncthreads();
       // merge-path split: the team takes exactly the slots [c0, c1); a row cut by a share
@@ -1045,6 +1040,7 @@ void k_step(StepArgs a) {
           s_slot[k] = a.slots[sb + k];
           if (WM != kUnitW) s_sw[k] = a.sw[sb + k];
         }
+        if (tid < kSlotPad) s_slot[E + tid] = 0;
         __syncthreads();
         st.zm = side_mask_raw<T, VEC, L>(st.xv, lifted);
         const int c0 = (E * sgi) >> nsl;
