@@ -60,6 +60,7 @@ struct Schedule {
   int rbt = 0;
   int rmax_rows = 0;
   std::vector<int4> ritems;  // {graph, first row, end row, first column}
+  std::vector<int4> rgs;     // per graph: {stream offset, slots per thread, slots, first slot}
 };
 
 // LDS a workgroup may use (queried once; gfx950 allows up to 160 KB per workgroup).
@@ -79,8 +80,9 @@ constexpr int kResidentStaticLds = 2048;
 
 struct Layout {
   size_t xalt, bits0, bits1, bits2, best_bits, mask, acc, cur_cut, best_cut, best_step, ctrl, dw, eta,
-      slots, sw, items, seg, goff, thr, delta, l_active, flags, xt0, xt1, ritems, total;
+      slots, sw, items, seg, goff, thr, delta, l_active, flags, xt0, xt1, ritems, rstream, rwstream, rgs, total;
   long long items_cap;
+  long long rstream_cap;  // ints of the resident schedule's slot streams
   int R;
 };
 
@@ -146,6 +148,12 @@ Layout layout_for(long long n, long long nnz, int G, const deco_params* p, bool 
   L.xt1 = take(dense ? (size_t)n * C * elem_size(p->x_dtype) : 0);
   // resident schedule: one work item per (graph, column) at most
   L.ritems = take(dense || p->l != 1 ? 0 : sizeof(int4) * (size_t)G * p->B);
+  // and the graphs' slot lists split into equal shares per thread, interleaved (each graph's
+  // shares are rounded up to 4 slots for at most 1024 threads)
+  L.rstream_cap = dense || p->l != 1 ? 0 : (n + nnz) + 4LL * 1024 * G;
+  L.rstream = take(sizeof(int) * (size_t)L.rstream_cap);
+  L.rwstream = take(weighted ? sizeof(float) * (size_t)L.rstream_cap : 0);
+  L.rgs = take(dense || p->l != 1 ? 0 : sizeof(int4) * (size_t)G);
   L.total = off;
   return L;
 }
@@ -268,6 +276,17 @@ bool build_schedule(deco_handle* h, Schedule& s) {
     for (int g : order)
       for (int c0 = 0; c0 < B; c0 += s.rbt) s.ritems.push_back(make_int4(g, goff[g], goff[g + 1], c0));
     s.rmax_rows = maxr;
+    // equal shares of each graph's slots per thread, rounded up to 4 (one 16-byte load)
+    const int nt = resident_threads(s.rbt);
+    s.rgs.assign(h->G, make_int4(0, 0, 0, 0));
+    long long soff = 0;
+    for (int gi = 0; gi < h->G; ++gi) {
+      const long long E = (long long)(rp[goff[gi + 1]] - rp[goff[gi]]) + (goff[gi + 1] - goff[gi]);
+      const long long per = ((E + nt - 1) / nt + 3) / 4 * 4;
+      s.rgs[gi] = make_int4((int)soff, (int)per, (int)E, rp[goff[gi]] + goff[gi]);
+      soff += per * nt;
+    }
+    if (soff > h->lay.rstream_cap) return false;
     // the step kernel's work list is built too: score-only passes and momentum steps use it
   }
   const int Bt = s.Wc * s.vec;
@@ -318,6 +337,13 @@ deco_status upload_schedule(deco_handle* h) {
   if (h->sched.rbt > 0) {
     HIP_TRY(h, hipMemcpyAsync(ws + h->lay.ritems, h->sched.ritems.data(), sizeof(int4) * h->sched.ritems.size(),
                               hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(ws + h->lay.rgs, h->sched.rgs.data(), sizeof(int4) * h->sched.rgs.size(),
+                              hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, build_resident_stream(h->n + h->nnz, h->G, h->sched.rbt, reinterpret_cast<const int4*>(ws + h->lay.rgs),
+                                     reinterpret_cast<const int*>(ws + h->lay.goff), h->args.slots, h->args.sw,
+                                     reinterpret_cast<int*>(ws + h->lay.rstream),
+                                     h->args.sw ? reinterpret_cast<float*>(ws + h->lay.rwstream) : nullptr,
+                                     h->stream));
     HIP_TRY(h, prepare_resident(h->args, h->dtype, h->sched.rbt, h->sched.rmax_rows));
   }
   // device form: {x, y, first slot, end slot}, {graph, tile, long-row flag, 0}
@@ -408,8 +434,12 @@ deco_status launch_steps(deco_handle* h, int steps, int do_update, int force) {
   a.do_update = do_update;
   a.force_score = force;
   if (h->sched.rbt > 0 && do_update && !force && a.vel == nullptr && !h->dense) {
-    const hipError_t e = launch_resident(a, h->dtype, h->sched.rbt, reinterpret_cast<const int4*>(h->ws + h->lay.ritems),
-                                         (int)h->sched.ritems.size(), h->sched.rmax_rows, steps, h->stream);
+    const hipError_t e =
+        launch_resident(a, h->dtype, h->sched.rbt, reinterpret_cast<const int4*>(h->ws + h->lay.ritems),
+                        (int)h->sched.ritems.size(), reinterpret_cast<const int4*>(h->ws + h->lay.rgs),
+                        reinterpret_cast<const int*>(h->ws + h->lay.rstream),
+                        a.sw ? reinterpret_cast<const float*>(h->ws + h->lay.rwstream) : nullptr, h->sched.rmax_rows,
+                        steps, h->stream);
     return e == hipSuccess ? DECO_OK : poison(h, e);
   }
   for (int s = 0; s < steps; ++s) {
@@ -1064,6 +1094,7 @@ deco_status deco_autotune(deco_handle* h, int32_t steps) {
     Schedule keep = h->sched;
     keep.items.clear();
     keep.ritems.clear();
+    keep.rgs.clear();
     g_cache[cache_key(h)] = keep;
   }
   return deco_start(h, &sa);

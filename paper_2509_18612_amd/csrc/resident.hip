@@ -6,17 +6,15 @@
 // Columns (initialisations) never interact in a step: column b of X_{t+1} depends only on
 // column b of X_t. So a workgroup that owns one graph's rows and a tile of BT columns can run
 // every step of those columns by itself: X_t and X_{t+1} of its tile sit in LDS (two
-// buffers), the neighbour gathers read LDS, the graph structure comes from L2 (every
-// workgroup of a graph reads the same CSR), and the cut of each of its columns is a
-// workgroup reduction. No workgroup waits for another, so the launch needs no grid barrier
-// and any number of workgroups may be in flight. The kernel applies when 2 n_g BT elements of
-// the storage type fit the LDS budget (small and medium graphs, unlifted or l = 1).
+// buffers), the neighbour gathers read LDS, and the cut of each of its columns is a workgroup
+// reduction. No workgroup waits for another, so the launch needs no grid barrier and any
+// number of workgroups may be in flight. The kernel applies when 2 n_g BT elements of the
+// storage type fit the LDS budget (small and medium graphs, unlifted or l = 1).
 //
-// Work item i: {graph, first row, end row, first column}. Thread j of the workgroup owns a
-// contiguous block of rows holding about 1/256 of the graph's slots (rows plus edges), so its
-// column indices stream from one contiguous stretch of the CSR; it sums each row's neighbours
-// in CSR order (the oracle's order) in batches of 8 loads, updates the row into the other
-// buffer, and counts w 1{z_v != z_u} per column. The running best
+// Work item i: {graph, first row, end row, first column}. The graph's slots are split into
+// equal shares, one per thread, read from an interleaved copy of the slot list built once per
+// schedule (k_rstream); rows cut by a share boundary are finished by the thread holding their
+// own slot, which adds the following threads' partial sums in thread order. The running best
 // (cut, step and the sides of the best iterate) stays in LDS and registers during the launch
 // and is written back at the end; the trace and the current cut are written per scored step.
 #include <hip/hip_runtime.h>
@@ -28,8 +26,6 @@
 
 namespace deco {
 namespace {
-
-constexpr int kRThreads = 256;
 
 __device__ __forceinline__ float r_bf2f(uint32_t h16) { return __uint_as_float(h16 << 16); }
 
@@ -104,79 +100,131 @@ struct RowIO {
   }
 };
 
-// Column partials of a workgroup: butterfly inside each wave, then the waves in order.
-template <typename S, int BT>
-__device__ __forceinline__ void block_sums(S (&v)[BT], S* s_red, int tid) {
+// Threads of a resident workgroup: more threads for narrow tiles (each thread walks its share
+// of the graph's slots for every column of the tile).
+template <int BT>
+struct RTeam {
+  static constexpr int NT = BT == 1 ? 1024 : (BT == 2 ? 512 : 256);
+};
+
+// Spare rows after a graph's rows in each LDS buffer, one per lane of a wave: the closing
+// store of a slot that closes no row of this thread lands in its lane's spare row.
+constexpr int kSpareRows = 64;
+
+// Bitwise select: a where m is all ones, b where m is zero.
+__device__ __forceinline__ int r_sel(int m, int a, int b) { return (a & m) | (b & ~m); }
+__device__ __forceinline__ float r_self(int m, float a, float b) {
+  return __int_as_float(r_sel(m, __float_as_int(a), __float_as_int(b)));
+}
+
+// Best sides of a row for the tile's columns (bit c: column c0 + c).
+template <int BT>
+struct RSide {
+  using type = typename std::conditional<(BT <= 8), uint8_t, uint16_t>::type;
+};
+
+// Sides of BT values from their bit patterns: x > 0 (eq. (5)) is bits > 0 as a signed integer;
+// x >= 0 (the lifted rule, -0 included) is the complement of -x > 0.
+template <int BT, int LF>
+__device__ __forceinline__ uint32_t r_sides(const float (&x)[BT]) {
+  uint32_t m = 0;
 #pragma unroll
-  for (int c = 0; c < BT; ++c)
-    for (int o = 32; o > 0; o >>= 1) v[c] += __shfl_xor(v[c], o);
-  if ((tid & 63) == 0) {
-#pragma unroll
-    for (int c = 0; c < BT; ++c) s_red[(tid >> 6) * BT + c] = v[c];
+  for (int c = 0; c < BT; ++c) {
+    const int b = __float_as_int(x[c]);
+    const int z = LF ? 1 - min(max(b ^ (int)0x80000000, 0), 1) : min(max(b, 0), 1);
+    m |= (uint32_t)z << c;
   }
+  return m;
+}
+
+// Slot position of local row v of a graph: its own slot follows the v earlier own slots and
+// the edges of the earlier rows.
+__device__ __forceinline__ int r_pos(const int* rp, int r0, int v) { return rp[r0 + v] - rp[r0] + v; }
+
+// First local row v in [0, nr] whose own slot lies at or after slot position k.
+__device__ __forceinline__ int r_first_row_at(const int* rp, int r0, int nr, long long k) {
+  int lo = 0, hi = nr;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (r_pos(rp, r0, mid) < k) lo = mid + 1; else hi = mid;
+  }
+  return lo;
 }
 
 // WM: 0 unit weights (int counts), 1 integer weights (int counts), 2 real weights (double).
-template <typename T, int BT, int WM>
-__global__ __launch_bounds__(kRThreads) void k_resident(StepArgs a, const int4* __restrict__ items, int max_rows,
-                                                        int steps) {
+//
+// Work split: the E slots of the item's graph (its own slot, then the neighbours, per row, in
+// CSR order) are cut into NT shares of floor(E t / NT) .. floor(E (t + 1) / NT); share t is
+// read from an interleaved copy of the slot list (stream), 4 slots per thread per load, so a
+// wave's loads are contiguous. A share may start inside a row (its 'head' row, owned by an
+// earlier thread): its sums go to LDS for the owner. A row whose own slot lies in share t
+// and that continues past it ('tail' row) is finished by thread t after the first barrier,
+// adding the partial sums of the following threads in thread order. The cut counts
+// w 1{z_v != z_u} are additive, so every thread counts the slots of its share itself.
+// LF: the lifted rounding rule; LAP: the Laplacian form of the gradient (a degree term).
+template <typename T, int BT, int WM, int LF, bool LAP>
+__global__ __launch_bounds__(RTeam<BT>::NT) void k_resident(StepArgs a, const int4* __restrict__ items,
+                                                            const int4* __restrict__ rgs, const int* __restrict__ stream,
+                                                            const float* __restrict__ wstream, int max_rows, int steps) {
+  constexpr int NT = RTeam<BT>::NT;
+  constexpr int NW = NT / 64;
   using S = typename std::conditional<WM == 2, double, int>::type;
+  using SB = typename RSide<BT>::type;
   extern __shared__ __align__(16) unsigned char r_smem[];
-  __shared__ S s_red[(kRThreads / 64) * BT];
-  __shared__ double s_best[BT];
-  __shared__ int s_bstep[BT];
-  __shared__ int s_imp[BT];
-  __shared__ int s_any, s_ever;
-  const int tid = threadIdx.x;
+  __shared__ S s_red[2][NW * BT];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int4 it = items[blockIdx.x];
   const int g = it.x, r0 = it.y, r1 = it.z, c0 = it.w;
   const int nr = r1 - r0;
+  const int4 gs = rgs[g];  // {stream offset, slots per thread (multiple of 4), E, first slot}
+  const int E = gs.z;
   T* buf0 = reinterpret_cast<T*>(r_smem);
-  T* buf1 = buf0 + (size_t)max_rows * BT;
-  uint32_t* s_bb = reinterpret_cast<uint32_t*>(buf1 + (size_t)max_rows * BT);
-  const int nbw = (nr * BT + 31) >> 5;  // words of best bits
+  T* buf1 = buf0 + (size_t)(max_rows + kSpareRows) * BT;
+  SB* s_side = reinterpret_cast<SB*>(buf1 + (size_t)(max_rows + kSpareRows) * BT);
+  float* s_part = reinterpret_cast<float*>(
+      r_smem +
+      ((2 * (size_t)(max_rows + kSpareRows) * BT * sizeof(T) + (size_t)max_rows * sizeof(SB) + 15) & ~(size_t)15));
+  // byte offset of this lane's spare row in either buffer
+  const int spare = (max_rows + lane) * BT * (int)sizeof(T);
   const long long t0 = a.ctrl->t;
   const int every = a.ctrl->score_every;
   const size_t B = (size_t)a.B;
 
+  // this thread's share [lo, hi), its head row, its own rows [ob, oe) and the threads
+  // whose shares start inside its last own row
+  const int lo = (int)((long long)E * tid / NT), hi = (int)((long long)E * (tid + 1) / NT);
+  const int len = hi - lo;
+  const int ob = r_first_row_at(a.rp, r0, nr, lo);
+  const int oe = r_first_row_at(a.rp, r0, nr, hi);
+  const int head_row = (lo < E && (ob >= nr || r_pos(a.rp, r0, ob) != lo)) ? ob - 1 : -1;
+  int ntail = 0;
+  if (oe > ob) {
+    const long long row_end = r_pos(a.rp, r0, oe);  // end of the last own row
+    if (row_end > hi) ntail = (int)((row_end * NT + E - 1) / E) - tid - 1;
+  }
+
   // X_t0 of the tile into buffer 0; running best of the tile's columns
   const T* X0 = reinterpret_cast<const T*>(a.x[t0 & 1]);
-  for (int i = tid; i < nr; i += kRThreads) {
+  for (int i = tid; i < nr; i += NT) {
     float v[BT];
     RowIO<T, BT>::load(X0 + (size_t)(r0 + i) * B + c0, v);
     RowIO<T, BT>::store(buf0 + (size_t)i * BT, v);
+    s_side[i] = 0;
   }
-  for (int i = tid; i < nbw; i += kRThreads) s_bb[i] = 0u;
-  if (tid < BT) {
-    s_best[tid] = a.best_cut[(size_t)g * B + c0 + tid];
-    s_bstep[tid] = a.best_step[(size_t)g * B + c0 + tid];
-    s_imp[tid] = 0;
-  }
-  if (tid == 0) s_ever = 0;
-  float eta[BT], ecw[BT];
+  double best[BT];
+  int bstep[BT];
+  float ecw[BT], eta[BT];
 #pragma unroll
   for (int c = 0; c < BT; ++c) {
+    best[c] = a.best_cut[(size_t)g * B + c0 + c];
+    bstep[c] = a.best_step[(size_t)g * B + c0 + c];
     eta[c] = a.eta[c0 + c];
     ecw[c] = eta[c] * a.cW;
   }
-  const bool lifted = a.lifted != 0;
-  int ever = 0;  // columns improved during this launch (bit c)
-  // this thread's rows [rb, re): slot offsets S(v) = (rp[v] - rp[r0]) + (v - r0) split evenly
-  int rb, re;
-  {
-    const long long E = (long long)(a.rp[r1] - a.rp[r0]) + nr;
-    auto first_row = [&](int j) {
-      const long long target = E * j / kRThreads;
-      int lo = r0, hi = r1;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((long long)(a.rp[mid] - a.rp[r0]) + (mid - r0) < target) lo = mid + 1; else hi = mid;
-      }
-      return lo;
-    };
-    rb = first_row(tid);
-    re = tid + 1 < kRThreads ? first_row(tid + 1) : r1;
-  }
+  uint32_t ever = 0;  // columns improved during this launch (bit c)
+  const int* sp = stream + gs.x + tid * 4;
+  const float* wp = WM != 0 ? wstream + gs.x + tid * 4 : nullptr;
+  const size_t sstride = (size_t)NT * 4;
   __syncthreads();
 
   for (int s = 0; s < steps; ++s) {
@@ -185,113 +233,163 @@ __global__ __launch_bounds__(kRThreads) void k_resident(StepArgs a, const int4* 
     const T* cur = (s & 1) ? buf1 : buf0;
     T* nxt = (s & 1) ? buf0 : buf1;
     S cnt[BT];
+    float acc[BT], xv[BT];
 #pragma unroll
-    for (int c = 0; c < BT; ++c) cnt[c] = 0;
-    int k1 = a.rp[rb];
-    for (int v = rb; v < re; ++v) {
-      const int i = v - r0;
-      float xv[BT], acc[BT];
-      RowIO<T, BT>::load(cur + (size_t)i * BT, xv);
-      uint32_t zv = 0;
+    for (int c = 0; c < BT; ++c) {
+      cnt[c] = 0;
+      acc[c] = 0.0f;
+      xv[c] = 0.0f;
+    }
+    // the open row: byte offset ri in the buffers (the lane's spare row while none of this
+    // thread's rows is open), its values xv, sums acc, sides zv, weighted degree dsum; headm
+    // is all ones while the open row is the share's head row, whose sums go to hacc
+    uint32_t zv = 0;
+    int ri = spare, headm = 0;
+    float dsum = 0.0f, hacc[BT];
 #pragma unroll
-      for (int c = 0; c < BT; ++c) {
-        acc[c] = 0.0f;
-        zv |= (uint32_t)(lifted ? xv[c] >= 0.0f : xv[c] > 0.0f) << c;
-      }
-      const int k0 = k1;
-      k1 = a.rp[v + 1];
-      // neighbours in CSR order, 8 index loads in flight at a time
-      for (int kb = k0; kb < k1; kb += 8) {
-        const int nb = k1 - kb < 8 ? k1 - kb : 8;
-        int uu[8];
-        float ww[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          uu[q] = q < nb ? a.ci[kb + q] - r0 : 0;
-          ww[q] = (WM == 0 || q >= nb) ? 1.0f : a.w[kb + q];
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          if (q < nb) {
-            const float wk = ww[q];
-            float xu[BT];
-            RowIO<T, BT>::load(cur + (size_t)uu[q] * BT, xu);
-#pragma unroll
-            for (int c = 0; c < BT; ++c) {
-              if (WM == 0)
-                acc[c] += xu[c];
-              else
-                acc[c] = fmaf(wk, xu[c], acc[c]);
-            }
-            if (do_score) {
-#pragma unroll
-              for (int c = 0; c < BT; ++c) {
-                const bool zu = lifted ? xu[c] >= 0.0f : xu[c] > 0.0f;
-                if (zu != (bool)((zv >> c) & 1u)) {
-                  if (WM == 2)
-                    cnt[c] += (S)wk;
-                  else if (WM == 1)
-                    cnt[c] += (S)(int)wk;
-                  else
-                    cnt[c] += 1;
-                }
-              }
-            }
-          }
-        }
-      }
-      float y[BT];
+    for (int c = 0; c < BT; ++c) hacc[c] = 0.0f;
+    if (head_row >= 0) {
+      ri = head_row * BT * (int)sizeof(T);
+      headm = -1;
+      RowIO<T, BT>::load(cur + (size_t)head_row * BT, xv);
+      zv = r_sides<BT, LF>(xv);
+    }
+    unsigned char* nxt_b = reinterpret_cast<unsigned char*>(nxt);
+    auto update = [&](float (&y)[BT]) {
 #pragma unroll
       for (int c = 0; c < BT; ++c) {
         float x1;
-        if (a.cD != 0.0f)
-          x1 = fmaf(eta[c], fmaf(a.cD * a.dw[v], xv[c], a.cW * acc[c]), xv[c]);
+        if constexpr (LAP)
+          x1 = fmaf(eta[c], fmaf(a.cD * dsum, xv[c], a.cW * acc[c]), xv[c]);
         else
           x1 = fmaf(ecw[c], acc[c], xv[c]);
         y[c] = __builtin_amdgcn_fmed3f(x1, -1.0f, 1.0f);
       }
-      RowIO<T, BT>::store(nxt + (size_t)i * BT, y);
+    };
+    // one slot, straight-line: an own slot (flag bit) stores the open row's update (to the
+    // spare row unless the open row is one of this thread's) and opens row idx; a neighbour
+    // slot is summed and counted
+    auto slot = [&](int v, float wq, const float (&xu)[BT]) {
+      const int ownm = v >> 31;
+      const int idx = v & 0x7FFFFFFF;
+      const uint32_t zu = r_sides<BT, LF>(xu);
+      float y[BT];
+      update(y);
+      RowIO<T, BT>::store(reinterpret_cast<T*>(nxt_b + r_sel(ownm & ~headm, ri, spare)), y);
+#pragma unroll
+      for (int c = 0; c < BT; ++c) hacc[c] = r_self(ownm & headm, acc[c], hacc[c]);
+      headm &= ~ownm;
+      if (do_score) {
+        const uint32_t d = (zu ^ zv) & ~(uint32_t)ownm;
+#pragma unroll
+        for (int c = 0; c < BT; ++c) {
+          const int bit = (int)((d >> c) & 1u);
+          if (WM == 2)
+            cnt[c] += bit ? (S)wq : (S)0;
+          else if (WM == 1)
+            cnt[c] += (S)((int)wq & -bit);
+          else
+            cnt[c] += bit;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < BT; ++c) {
+        const float an = WM == 0 ? acc[c] + xu[c] : fmaf(wq, xu[c], acc[c]);
+        acc[c] = __int_as_float(__float_as_int(an) & ~ownm);
+        xv[c] = r_self(ownm, xu[c], xv[c]);
+      }
+      zv = (uint32_t)r_sel(ownm, (int)zu, (int)zv);
+      ri = r_sel(ownm, idx * BT * (int)sizeof(T), ri);
+      if constexpr (LAP) dsum = r_self(ownm, WM != 0 ? wq : a.dw[r0 + idx], dsum);
+    };
+    // slots four at a time from the interleaved stream (the next four in flight); whole
+    // batches without predicates, then the share's last partial batch
+    const int full = len & ~3;
+    int4 sv_next = make_int4(0, 0, 0, 0);
+    float4 wv_next = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+    if (len > 0) {
+      sv_next = *reinterpret_cast<const int4*>(sp);
+      if constexpr (WM != 0) wv_next = *reinterpret_cast<const float4*>(wp);
     }
-    if (do_score) block_sums<S, BT>(cnt, s_red, tid);
-    __syncthreads();  // X_t+1 complete; wave partials ready
+    for (int jb = 0; jb < len; jb += 4) {
+      const int4 sv = sv_next;
+      const float4 wv4 = wv_next;
+      if (jb + 4 < len) {
+        sv_next = *reinterpret_cast<const int4*>(sp + (size_t)((jb >> 2) + 1) * sstride);
+        if constexpr (WM != 0) wv_next = *reinterpret_cast<const float4*>(wp + (size_t)((jb >> 2) + 1) * sstride);
+      }
+      const int sl[4] = {sv.x, sv.y, sv.z, sv.w};
+      const float wl[4] = {wv4.x, wv4.y, wv4.z, wv4.w};
+      float xb[4][BT];
+      if (jb < full) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) RowIO<T, BT>::load(cur + (size_t)(sl[q] & 0x7FFFFFFF) * BT, xb[q]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) slot(sl[q], wl[q], xb[q]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) RowIO<T, BT>::load(cur + (size_t)(jb + q < len ? sl[q] & 0x7FFFFFFF : 0) * BT, xb[q]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (jb + q < len) slot(sl[q], wl[q], xb[q]);
+      }
+    }
+    // the head row's sums for its owner (zeros when the share has no head row)
+#pragma unroll
+    for (int c = 0; c < BT; ++c) s_part[tid * BT + c] = headm ? acc[c] : hacc[c];
+    const bool open_own = !headm && ri != spare;
+    const bool tail = open_own && ntail > 0;
+    if (open_own && ntail == 0) {
+      float y[BT];
+      update(y);
+      RowIO<T, BT>::store(reinterpret_cast<T*>(nxt_b + ri), y);
+    }
     if (do_score) {
-      if (tid < BT) {
+#pragma unroll
+      for (int c = 0; c < BT; ++c) {
+        S v = cnt[c];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) s_red[s & 1][wv * BT + c] = v;
+      }
+    }
+    __syncthreads();  // head sums and wave counts are in LDS
+    if (tail) {
+      for (int k = 1; k <= ntail; ++k)
+#pragma unroll
+        for (int c = 0; c < BT; ++c) acc[c] += s_part[(tid + k) * BT + c];
+      float y[BT];
+      update(y);
+      RowIO<T, BT>::store(reinterpret_cast<T*>(nxt_b + ri), y);
+    }
+    __syncthreads();  // X_t+1 complete
+    if (do_score) {
+      uint32_t m = 0;
+#pragma unroll
+      for (int c = 0; c < BT; ++c) {
         S tot = 0;
 #pragma unroll
-        for (int q = 0; q < kRThreads / 64; ++q) tot += s_red[q * BT + tid];
+        for (int q = 0; q < NW; ++q) tot += s_red[s & 1][q * BT + c];
         const double cut = 0.5 * (double)tot;
-        const size_t idx = (size_t)g * B + c0 + tid;
-        a.cur_cut[idx] = cut;
-        if (a.trace) a.trace[(size_t)(t % a.trace_cap) * a.G * B + idx] = cut;
-        const bool imp = cut > s_best[tid];
-        if (imp) {
-          s_best[tid] = cut;
-          s_bstep[tid] = (int)t;
+        if (tid == c) {
+          const size_t idx = (size_t)g * B + c0 + c;
+          a.cur_cut[idx] = cut;
+          if (a.trace) a.trace[(size_t)(t % a.trace_cap) * a.G * B + idx] = cut;
         }
-        s_imp[tid] = imp ? 1 : 0;
+        if (cut > best[c]) {
+          best[c] = cut;
+          bstep[c] = (int)t;
+          m |= 1u << c;
+        }
       }
-      if (tid == 0) s_any = 0;
-      __syncthreads();
-      if (tid < BT && s_imp[tid]) atomicOr(&s_any, 1 << tid);
-      __syncthreads();
-      const int m = s_any;
       ever |= m;
       if (m) {
-        // sides of X_t (buffer cur) of this thread's rows into the best bits, improved columns
-        for (int i = rb - r0; i < re - r0; ++i) {
-          float xv[BT];
-          RowIO<T, BT>::load(cur + (size_t)i * BT, xv);
-#pragma unroll
-          for (int c = 0; c < BT; ++c) {
-            if ((m >> c) & 1) {
-              const int bit = i * BT + c;
-              const bool z = lifted ? xv[c] >= 0.0f : xv[c] > 0.0f;
-              if (z)
-                atomicOr(&s_bb[bit >> 5], 1u << (bit & 31));
-              else
-                atomicAnd(&s_bb[bit >> 5], ~(1u << (bit & 31)));
-            }
-          }
+        // sides of X_t (buffer cur) of this thread's own rows for the improved columns;
+        // the next step rewrites those rows only after this
+        for (int i = ob; i < oe; ++i) {
+          float x[BT];
+          RowIO<T, BT>::load(cur + (size_t)i * BT, x);
+          const uint32_t z = r_sides<BT, LF>(x);
+          s_side[i] = (SB)((s_side[i] & ~m) | (z & m));
         }
       }
     }
@@ -301,40 +399,39 @@ __global__ __launch_bounds__(kRThreads) void k_resident(StepArgs a, const int4* 
   // X_{t0 + steps} back to global memory; running best and its sides
   const T* fin = (steps & 1) ? buf1 : buf0;
   T* Xo = reinterpret_cast<T*>(a.x[(t0 + steps) & 1]);
-  for (int i = tid; i < nr; i += kRThreads) {
+  for (int i = tid; i < nr; i += NT) {
     float v[BT];
     RowIO<T, BT>::load(fin + (size_t)i * BT, v);
     RowIO<T, BT>::store(Xo + (size_t)(r0 + i) * B + c0, v);
   }
   if (tid < BT) {
-    a.best_cut[(size_t)g * B + c0 + tid] = s_best[tid];
-    a.best_step[(size_t)g * B + c0 + tid] = s_bstep[tid];
+#pragma unroll
+    for (int c = 0; c < BT; ++c)
+      if (c == tid) {
+        a.best_cut[(size_t)g * B + c0 + c] = best[c];
+        a.best_step[(size_t)g * B + c0 + c] = bstep[c];
+      }
   }
   if (ever) {
     // best_bits: byte (c0 + c) / 8 of each row; tiles of 8 or more columns own whole bytes,
     // narrower ones share bytes with other workgroups and merge through word atomics
-    for (int i = tid; i < nr; i += kRThreads) {
-      uint32_t bits = 0;
-#pragma unroll
-      for (int c = 0; c < BT; ++c) {
-        const int bit = i * BT + c;
-        bits |= ((s_bb[bit >> 5] >> (bit & 31)) & 1u) << c;
-      }
-      const size_t row = (size_t)(r0 + i) * a.NBY;
+    for (int i = tid; i < nr; i += NT) {
+      const uint32_t bits = s_side[i];
+      const size_t rowb = (size_t)(r0 + i) * a.NBY;
       if constexpr (BT >= 8) {
 #pragma unroll
         for (int q = 0; q < BT / 8; ++q) {
-          const uint32_t mq = ((uint32_t)ever >> (8 * q)) & 0xFFu;
+          const uint32_t mq = (ever >> (8 * q)) & 0xFFu;
           if (mq) {
-            uint8_t* p = a.best_bits + row + (c0 >> 3) + q;
+            uint8_t* p = a.best_bits + rowb + (c0 >> 3) + q;
             *p = (uint8_t)((*p & ~mq) | ((bits >> (8 * q)) & mq));
           }
         }
       } else {
-        const size_t byte = row + (c0 >> 3);
+        const size_t byte = rowb + (c0 >> 3);
         const int sh = (int)((byte & 3) * 8 + (c0 & 7));
         unsigned int* w = reinterpret_cast<unsigned int*>(a.best_bits + (byte & ~(size_t)3));
-        const uint32_t mw = ((uint32_t)ever & ((1u << BT) - 1u)) << sh;
+        const uint32_t mw = (ever & ((1u << BT) - 1u)) << sh;
         atomicAnd(w, ~mw);
         atomicOr(w, (bits << sh) & mw);
       }
@@ -342,42 +439,77 @@ __global__ __launch_bounds__(kRThreads) void k_resident(StepArgs a, const int4* 
   }
 }
 
+// Interleaved slot streams of the resident schedule: slot j of thread t's share of graph g
+// (slot floor(E t / NT) + j of the graph) at stream[off_g + (j / 4) NT 4 + 4 t + j % 4], as a
+// local row index (own slots keep the flag bit), with its weight beside it.
+__global__ void k_rstream(long long nslots, int G, int nt, const int4* __restrict__ rgs, const int* __restrict__ goff,
+                          const int* __restrict__ slots, const float* __restrict__ sw, int* __restrict__ stream,
+                          float* __restrict__ wstream) {
+  const long long K = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (K >= nslots) return;
+  int lo = 0, hi = G - 1;  // last graph whose first slot is <= K
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (rgs[mid].w <= K) lo = mid; else hi = mid - 1;
+  }
+  const int4 gs = rgs[lo];
+  const long long E = gs.z, k = K - gs.w;
+  const long long t = ((k + 1) * nt - 1) / E;
+  const long long j = k - E * t / nt;
+  const size_t dst = (size_t)gs.x + (size_t)(j >> 2) * nt * 4 + (size_t)t * 4 + (size_t)(j & 3);
+  const int v = slots[K];
+  const int r0 = goff[lo];
+  stream[dst] = v < 0 ? (int)(0x80000000u | (unsigned)((v & 0x7FFFFFFF) - r0)) : v - r0;
+  if (wstream) wstream[dst] = sw[K];
+}
+
 // prepare != 0: raise the kernels' dynamic LDS limit (outside any stream capture); else launch.
 template <typename T, int BT>
-hipError_t launch_bt(const StepArgs& a, const int4* items, int nitems, int max_rows, int steps, size_t lds, int wm,
-                     hipStream_t s, int prepare) {
+hipError_t launch_bt(const StepArgs& a, const int4* items, int nitems, const int4* rgs, const int* stream,
+                     const float* wstream, int max_rows, int steps, size_t lds, int wm, hipStream_t s, int prepare) {
   auto go = [&](auto kern) {
     if (prepare)
       return hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)lds);
-    hipLaunchKernelGGL(kern, dim3(nitems), dim3(kRThreads), lds, s, a, items, max_rows, steps);
+    hipLaunchKernelGGL(kern, dim3(nitems), dim3(RTeam<BT>::NT), lds, s, a, items, rgs, stream, wstream, max_rows,
+                       steps);
     return hipGetLastError();
   };
-  if (wm == 0) return go(k_resident<T, BT, 0>);
-  if (wm == 1) return go(k_resident<T, BT, 1>);
-  return go(k_resident<T, BT, 2>);
+  auto by_form = [&](auto lf) {
+    constexpr int LF = decltype(lf)::value;
+    if (a.cD != 0.0f) {
+      if (wm == 0) return go(k_resident<T, BT, 0, LF, true>);
+      if (wm == 1) return go(k_resident<T, BT, 1, LF, true>);
+      return go(k_resident<T, BT, 2, LF, true>);
+    }
+    if (wm == 0) return go(k_resident<T, BT, 0, LF, false>);
+    if (wm == 1) return go(k_resident<T, BT, 1, LF, false>);
+    return go(k_resident<T, BT, 2, LF, false>);
+  };
+  return a.lifted ? by_form(std::integral_constant<int, 1>{}) : by_form(std::integral_constant<int, 0>{});
 }
 
-hipError_t dispatch_bt(const StepArgs& a, int dtype, int bt, const int4* items, int nitems, int max_rows, int steps,
-                       hipStream_t s, int prepare) {
+hipError_t dispatch_bt(const StepArgs& a, int dtype, int bt, const int4* items, int nitems, const int4* rgs,
+                       const int* stream, const float* wstream, int max_rows, int steps, hipStream_t s,
+                       int prepare) {
   const size_t lds = resident_lds_bytes(max_rows, bt, dtype);
   const int wm = a.w == nullptr ? 0 : (a.intw ? 1 : 2);
   if (dtype == 0) {
     switch (bt) {
-      case 1: return launch_bt<float, 1>(a, items, nitems, max_rows, steps, lds, wm, s, prepare);
-      case 2: return launch_bt<float, 2>(a, items, nitems, max_rows, steps, lds, wm, s, prepare);
-      case 4: return launch_bt<float, 4>(a, items, nitems, max_rows, steps, lds, wm, s, prepare);
-      case 8: return launch_bt<float, 8>(a, items, nitems, max_rows, steps, lds, wm, s, prepare);
-      case 16: return launch_bt<float, 16>(a, items, nitems, max_rows, steps, lds, wm, s, prepare);
+      case 1: return launch_bt<float, 1>(a, items, nitems, rgs, stream, wstream, max_rows, steps, lds, wm, s, prepare);
+      case 2: return launch_bt<float, 2>(a, items, nitems, rgs, stream, wstream, max_rows, steps, lds, wm, s, prepare);
+      case 4: return launch_bt<float, 4>(a, items, nitems, rgs, stream, wstream, max_rows, steps, lds, wm, s, prepare);
+      case 8: return launch_bt<float, 8>(a, items, nitems, rgs, stream, wstream, max_rows, steps, lds, wm, s, prepare);
+      case 16: return launch_bt<float, 16>(a, items, nitems, rgs, stream, wstream, max_rows, steps, lds, wm, s, prepare);
       default: return hipErrorInvalidValue;
     }
   }
   switch (bt) {
-    case 1: return launch_bt<uint16_t, 1>(a, items, nitems, max_rows, steps, lds, wm, s, prepare);
-    case 2: return launch_bt<uint16_t, 2>(a, items, nitems, max_rows, steps, lds, wm, s, prepare);
-    case 4: return launch_bt<uint16_t, 4>(a, items, nitems, max_rows, steps, lds, wm, s, prepare);
-    case 8: return launch_bt<uint16_t, 8>(a, items, nitems, max_rows, steps, lds, wm, s, prepare);
-    case 16: return launch_bt<uint16_t, 16>(a, items, nitems, max_rows, steps, lds, wm, s, prepare);
+    case 1: return launch_bt<uint16_t, 1>(a, items, nitems, rgs, stream, wstream, max_rows, steps, lds, wm, s, prepare);
+    case 2: return launch_bt<uint16_t, 2>(a, items, nitems, rgs, stream, wstream, max_rows, steps, lds, wm, s, prepare);
+    case 4: return launch_bt<uint16_t, 4>(a, items, nitems, rgs, stream, wstream, max_rows, steps, lds, wm, s, prepare);
+    case 8: return launch_bt<uint16_t, 8>(a, items, nitems, rgs, stream, wstream, max_rows, steps, lds, wm, s, prepare);
+    case 16: return launch_bt<uint16_t, 16>(a, items, nitems, rgs, stream, wstream, max_rows, steps, lds, wm, s, prepare);
     default: return hipErrorInvalidValue;
   }
 }
@@ -392,19 +524,35 @@ __global__ void k_advance(DevCtrl* ctrl, int steps) {
 
 }  // namespace
 
+int resident_threads(int bt) {
+  return bt == 1 ? RTeam<1>::NT : (bt == 2 ? RTeam<2>::NT : RTeam<4>::NT);
+}
+
 size_t resident_lds_bytes(int max_rows, int bt, int dtype) {
   const size_t es = dtype == 0 ? 4 : 2;
-  return 2 * (size_t)max_rows * bt * es + ((size_t)max_rows * bt + 31) / 32 * 4;
+  const size_t side = bt <= 8 ? 1 : 2;
+  const size_t front = (2 * (size_t)(max_rows + kSpareRows) * bt * es + (size_t)max_rows * side + 15) & ~(size_t)15;
+  return front + (size_t)resident_threads(bt) * bt * sizeof(float);
 }
 
 hipError_t prepare_resident(const StepArgs& a, int dtype, int bt, int max_rows) {
-  return dispatch_bt(a, dtype, bt, nullptr, 0, max_rows, 0, nullptr, 1);
+  return dispatch_bt(a, dtype, bt, nullptr, 0, nullptr, nullptr, nullptr, max_rows, 0, nullptr, 1);
 }
 
-hipError_t launch_resident(const StepArgs& a, int dtype, int bt, const int4* items, int nitems, int max_rows,
-                           int steps, hipStream_t s) {
+hipError_t build_resident_stream(long long nslots, int G, int bt, const int4* rgs, const int* goff, const int* slots,
+                                 const float* sw, int* stream, float* wstream, hipStream_t s) {
+  if (nslots <= 0) return hipSuccess;
+  const int threads = 256;
+  const long long blocks = (nslots + threads - 1) / threads;
+  hipLaunchKernelGGL(k_rstream, dim3((unsigned)blocks), dim3(threads), 0, s, nslots, G, resident_threads(bt), rgs,
+                     goff, slots, sw, stream, wstream);
+  return hipGetLastError();
+}
+
+hipError_t launch_resident(const StepArgs& a, int dtype, int bt, const int4* items, int nitems, const int4* rgs,
+                           const int* stream, const float* wstream, int max_rows, int steps, hipStream_t s) {
   if (nitems <= 0 || steps <= 0) return hipSuccess;
-  hipError_t e = dispatch_bt(a, dtype, bt, items, nitems, max_rows, steps, s, 0);
+  hipError_t e = dispatch_bt(a, dtype, bt, items, nitems, rgs, stream, wstream, max_rows, steps, s, 0);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, a.ctrl, steps);
   return hipGetLastError();
