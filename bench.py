@@ -28,8 +28,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "edge-updates/s (nnz·B·steps/s); time-to-cut within 0.5% of best, plain vs chosen"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_ba10k_B256_traffic.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2509_18612_amd", "csrc", "kernels.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "step_kernels_ba10k_B256_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2509_18612_amd", "csrc", f) for f in ("kernels.hip", "resident.hip")]
 MPNN_WEIGHTS = os.path.join(ROOT, "paper_2509_18612_amd", "data", "mpnn_ba.npy")
 
 
@@ -38,7 +38,7 @@ def log(msg):
 
 
 def measured_traffic(which, schedule):
-    """Fabric bytes per launch of a step-kernel shape from the committed counter summary
+    """Fabric bytes per step of a step-kernel shape from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by the factor a copy of known size gives), or
     None when the kernel source has changed since the counters were taken or the counters
     were taken on another schedule than the one timed here."""
@@ -52,10 +52,10 @@ def measured_traffic(which, schedule):
         if ":" in ln and ln.startswith("- "):
             k, v = ln[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if vals.get("kernels.hip sha256") != sha or vals.get(f"schedule ({which})") != schedule:
+    sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
+    if vals.get("step kernel sources sha256") != sha or vals.get(f"schedule ({which})") != schedule:
         return None
-    v = vals.get(f"traffic bytes per launch ({which})")
+    v = vals.get(f"traffic bytes per step ({which})")
     return int(v) if v else None
 
 
@@ -70,17 +70,25 @@ def parse_schedule(s):
 
 
 def pin_args(sched, dtype_bf16, l):
-    """set_schedule arguments reproducing a schedule string."""
+    """set_schedule arguments reproducing a schedule string (a resident schedule: its tile
+    width, the step kernel's part left at its default)."""
     d = parse_schedule(sched)
     vec = int(d["vec"])
     lane_elems = 4 if (dtype_bf16 and l == 1 and vec == 4) else 0
+    if sched.startswith("resident"):
+        return (int(d["Wc"]), 1 << 30, 0, 128, 2048, lane_elems, int(d["cols"]))
     return (int(d["Wc"]), int(d["dlong"]), int(d["xcd_mode"]), int(d["grid"]) // 8, int(d["nnz_per_item"]),
             lane_elems)
 
 
+def kernel_name(sched):
+    return "k_resident" if sched.startswith("resident") else "k_step"
+
+
 def time_step_kernel(deco, torch, G, B, l, dtype, steps, l_active=None, pin=None, eta=0.01, seed=1):
-    """Average duration per launch (ms) of the fused step kernel, HIP events on the handle's
-    stream; the schedule is the cached autotune winner of the shape unless pinned."""
+    """Average duration per step (ms) of the fused step kernel (one launch per step; a resident
+    schedule runs all the steps in one launch), HIP events on the handle's stream; the schedule
+    is the cached autotune winner of the shape unless pinned."""
     h = deco.Handle(G, B=B, l=l, lifted=l > 1, x_dtype=dtype, eta=eta, seed=seed)
     if pin is not None:
         h.set_schedule(*pin)
@@ -120,6 +128,7 @@ def other_workloads(deco, synth, torch, which):
     if "er800" in which:
         g = synth.erdos_renyi(800, 0.06, 0)
         h = deco.Handle(deco.Graph(g), B=16, eta=0.1)
+        h.autotune(50)
         us = time_handle(torch, h, 200, deco.INIT_UNIFORM)
         A = algorithmic_bytes(g.n, g.nnz, 16, 1, 4, 0)
         out["er800_B16_f32"] = {"us_per_step": round(us, 3), "edge_updates_per_s": g.nnz * 16 / us * 1e6,
@@ -129,7 +138,7 @@ def other_workloads(deco, synth, torch, which):
     if "uneven" in which:
         g = synth.uneven_batch(512, 7)
         h = deco.Handle(deco.Graph(g), B=64, x_dtype=deco.BF16, eta=0.01)
-        h.autotune(5)
+        h.autotune(20)
         us = time_handle(torch, h, 50, deco.INIT_IDI, scale=1e4, sigma2=0.8)
         A = algorithmic_bytes(g.n, g.nnz, 64, 512, 2, 0)
         out["uneven512_B64_bf16"] = {"us_per_step": round(us, 2), "edge_updates_per_s": g.nnz * 64 / us * 1e6,
@@ -500,7 +509,8 @@ def main():
     achieved = dk["bytes"] / (dk["us"] * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(f"f32 {dom}", dk["schedule"]),
-                "kernel": f"k_step {dom} f32" + (f" l={l_max} ({l_act} active)" if dom == "lifted" else ""),
+                "kernel": f"{kernel_name(dk['schedule'])} {dom} f32" +
+                          (f" l={l_max} ({l_act} active)" if dom == "lifted" else ""),
                 "bytes_per_launch": dk["bytes"], "us_per_launch": round(dk["us"], 3),
                 "schedule": dk["schedule"]}
 

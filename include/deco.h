@@ -183,8 +183,10 @@ deco_status deco_set_trace(deco_handle *h, double *trace, int32_t capacity);
 /* Index of the current iterate (number of steps taken since deco_start). Host-side. */
 int64_t deco_current_step(const deco_handle *h);
 
-/* Choose the kernel schedule (b-tile width, long-row threshold, work item size, XCD layout)
- * by timing candidates for 'steps' steps each on the device; the winner is kept in the
+/* Choose the kernel schedule (b-tile width, long-row threshold, work item size, XCD layout,
+ * or the resident schedule for unlifted and l = 1 handles) by timing candidates over a call
+ * of 'steps' steps each on the device (a resident schedule has a fixed cost per call, so
+ * 'steps' should be the length of the calls that will follow); the winner is kept in the
  * handle and in a per-process cache keyed by the graph and batch shape. It overwrites X
  * and the running best (call deco_start afterwards). Synchronous. */
 deco_status deco_autotune(deco_handle *h, int32_t steps);
@@ -207,8 +209,10 @@ typedef struct deco_schedule {
                             deco_step call in one launch, one workgroup per (graph, tile of
                             resident_cols columns) holding that tile of the graph's rows in
                             LDS for all the steps (1, 2, 4, 8 or 16 dividing B; the graph's
-                            rows times the tile, two buffers, must fit one workgroup's LDS,
-                            else DECO_E_UNSUPPORTED); score-only passes and momentum steps
+                            rows plus 64 spare rows times the tile, two buffers, must fit one
+                            workgroup's LDS, else DECO_E_UNSUPPORTED; the graph's slots are
+                            split evenly over 1024, 512 or 256 threads for tiles of 1, 2 or
+                            more columns); score-only passes and momentum steps
                             keep the step kernel with its default schedule (the other fields
                             are not used then). 0: the step kernel with the fields above */
 } deco_schedule;
@@ -276,8 +280,9 @@ typedef struct deco_solve_params {
   const int32_t *l0;    /* host [K]: initial lift dimensions, or NULL (drawn) */
   const double *target_cut; /* host [G] or NULL */
   int32_t use_graph;    /* capture the step loops in hipGraphs */
-  int32_t autotune;     /* run deco_autotune on both handles first (a shape already tuned in
-                           this process reuses its cached winner) */
+  int32_t autotune;     /* run deco_autotune on both handles first, over calls of the run's
+                           own length (check_every, else the longer batch; 10 to 50 steps); a
+                           shape already tuned in this process reuses its cached winner */
   int32_t T_min;        /* > 0: the unlifted step count is searched per member in [T_min, T_q]
                            (Sec. 4.3: drawn uniformly, evolved by deco_evo_next_steps; a member
                            past its count keeps its columns still with a step of 0); 0: T_q */

@@ -80,7 +80,8 @@ constexpr int kResidentStaticLds = 2048;
 
 struct Layout {
   size_t xalt, bits0, bits1, bits2, best_bits, mask, acc, cur_cut, best_cut, best_step, ctrl, dw, eta,
-      slots, sw, items, seg, goff, thr, delta, l_active, flags, xt0, xt1, ritems, rstream, rwstream, rgs, total;
+      slots, sw, items, seg, goff, thr, delta, l_active, flags, xt0, xt1, ritems, rstream, rwstream, rgs, rbest, rimp,
+      total;
   long long items_cap;
   long long rstream_cap;  // ints of the resident schedule's slot streams
   int R;
@@ -149,11 +150,14 @@ Layout layout_for(long long n, long long nnz, int G, const deco_params* p, bool 
   // resident schedule: one work item per (graph, column) at most
   L.ritems = take(dense || p->l != 1 ? 0 : sizeof(int4) * (size_t)G * p->B);
   // and the graphs' slot lists split into equal shares per thread, interleaved (each graph's
-  // shares are rounded up to 4 slots for at most 1024 threads)
-  L.rstream_cap = dense || p->l != 1 ? 0 : (n + nnz) + 4LL * 1024 * G;
+  // shares are rounded up to 4 slots, after 4 ints of header, for at most 1024 threads)
+  L.rstream_cap = dense || p->l != 1 ? 0 : (n + nnz) + 8LL * 1024 * G;
   L.rstream = take(sizeof(int) * (size_t)L.rstream_cap);
   L.rwstream = take(weighted ? sizeof(float) * (size_t)L.rstream_cap : 0);
   L.rgs = take(dense || p->l != 1 ? 0 : sizeof(int4) * (size_t)G);
+  // best sides of resident tiles narrower than a byte of best_bits, and their improved flags
+  L.rbest = take(dense || p->l != 1 ? 0 : (size_t)n * p->B);
+  L.rimp = take(dense || p->l != 1 ? 0 : (size_t)G * p->B);
   L.total = off;
   return L;
 }
@@ -284,7 +288,7 @@ bool build_schedule(deco_handle* h, Schedule& s) {
       const long long E = (long long)(rp[goff[gi + 1]] - rp[goff[gi]]) + (goff[gi + 1] - goff[gi]);
       const long long per = ((E + nt - 1) / nt + 3) / 4 * 4;
       s.rgs[gi] = make_int4((int)soff, (int)per, (int)E, rp[goff[gi]] + goff[gi]);
-      soff += per * nt;
+      soff += (4 + per) * nt;  // 4 ints of header per thread, then its slots
     }
     if (soff > h->lay.rstream_cap) return false;
     // the step kernel's work list is built too: score-only passes and momentum steps use it
@@ -340,7 +344,8 @@ deco_status upload_schedule(deco_handle* h) {
     HIP_TRY(h, hipMemcpyAsync(ws + h->lay.rgs, h->sched.rgs.data(), sizeof(int4) * h->sched.rgs.size(),
                               hipMemcpyHostToDevice, h->stream));
     HIP_TRY(h, build_resident_stream(h->n + h->nnz, h->G, h->sched.rbt, reinterpret_cast<const int4*>(ws + h->lay.rgs),
-                                     reinterpret_cast<const int*>(ws + h->lay.goff), h->args.slots, h->args.sw,
+                                     reinterpret_cast<const int*>(ws + h->lay.goff), h->args.rp, h->args.slots,
+                                     h->args.sw,
                                      reinterpret_cast<int*>(ws + h->lay.rstream),
                                      h->args.sw ? reinterpret_cast<float*>(ws + h->lay.rwstream) : nullptr,
                                      h->stream));
@@ -438,8 +443,9 @@ deco_status launch_steps(deco_handle* h, int steps, int do_update, int force) {
         launch_resident(a, h->dtype, h->sched.rbt, reinterpret_cast<const int4*>(h->ws + h->lay.ritems),
                         (int)h->sched.ritems.size(), reinterpret_cast<const int4*>(h->ws + h->lay.rgs),
                         reinterpret_cast<const int*>(h->ws + h->lay.rstream),
-                        a.sw ? reinterpret_cast<const float*>(h->ws + h->lay.rwstream) : nullptr, h->sched.rmax_rows,
-                        steps, h->stream);
+                        a.sw ? reinterpret_cast<const float*>(h->ws + h->lay.rwstream) : nullptr,
+                        reinterpret_cast<uint8_t*>(h->ws + h->lay.rbest), reinterpret_cast<uint8_t*>(h->ws + h->lay.rimp),
+                        reinterpret_cast<const int*>(h->ws + h->lay.goff), h->sched.rmax_rows, steps, h->stream);
     return e == hipSuccess ? DECO_OK : poison(h, e);
   }
   for (int s = 0; s < steps; ++s) {
@@ -1566,9 +1572,13 @@ deco_status deco_solver_create(deco_solver** out, const deco_graph* g, const dec
     return st;
   }
   if (sp->autotune) {
-    // shapes tuned earlier in this process already run their cached winner
-    if ((!schedule_cached(v->hq) && (st = deco_autotune(v->hq, 10))) ||
-        (!schedule_cached(v->hl) && (st = deco_autotune(v->hl, 10)))) {
+    // shapes tuned earlier in this process already run their cached winner; candidates are
+    // timed over calls as long as the run's own (a target check or a whole batch, 10 to 50
+    // steps), so a schedule with a fixed cost per call is judged at its real share
+    const int call = sp->check_every > 0 ? sp->check_every : std::max(sp->T_q, sp->T_l);
+    const int tune = std::max(10, std::min(50, call));
+    if ((!schedule_cached(v->hq) && (st = deco_autotune(v->hq, tune))) ||
+        (!schedule_cached(v->hl) && (st = deco_autotune(v->hl, tune)))) {
       solver_free(v);
       return st;
     }

@@ -121,15 +121,19 @@ hipError_t launch_fill_eta(float* eta, int B, float v, hipStream_t s);
 // graph's rows in LDS; then the step counter advances by 'steps'. prepare_resident raises the
 // kernels' LDS limit once per schedule (outside stream capture).
 // The slots of each graph are split into equal shares over resident_threads(bt) threads and
-// read from an interleaved stream (build_resident_stream, once per schedule): rgs[g] =
-// {stream offset, slots per thread rounded up to 4, slots E_g, first slot of graph g}.
+// read from an interleaved stream (build_resident_stream, once per schedule: 4 ints of header
+// per thread, then the slots): rgs[g] = {stream offset, slots per thread rounded up to 4,
+// slots E_g, first slot of graph g}.
 int resident_threads(int bt);
 size_t resident_lds_bytes(int max_rows, int bt, int dtype);
 hipError_t prepare_resident(const StepArgs& a, int dtype, int bt, int max_rows);
-hipError_t build_resident_stream(long long nslots, int G, int bt, const int4* rgs, const int* goff, const int* slots,
-                                 const float* sw, int* stream, float* wstream, hipStream_t s);
+hipError_t build_resident_stream(long long nslots, int G, int bt, const int4* rgs, const int* goff, const int* rp,
+                                 const int* slots, const float* sw, int* stream, float* wstream, hipStream_t s);
+// rbest (B / bt byte arrays of n rows) and rimp (G x B / bt flags) carry the best sides of
+// tiles narrower than 8 columns to a merge kernel after the launch.
 hipError_t launch_resident(const StepArgs& a, int dtype, int bt, const int4* items, int nitems, const int4* rgs,
-                           const int* stream, const float* wstream, int max_rows, int steps, hipStream_t s);
+                           const int* stream, const float* wstream, uint8_t* rbest, uint8_t* rimp, const int* goff,
+                           int max_rows, int steps, hipStream_t s);
 // Component sums of a many-component batch (l > kMaxL) into the score handle's iterate.
 hipError_t launch_sides(const void* x0, const void* x1, void* s0, void* s1, const DevCtrl* cx, const DevCtrl* cs,
                         long long n, int B, int l, int dtype, hipStream_t s);

@@ -165,7 +165,8 @@ __device__ __forceinline__ int r_first_row_at(const int* rp, int r0, int nr, lon
 template <typename T, int BT, int WM, int LF, bool LAP>
 __global__ __launch_bounds__(RTeam<BT>::NT) void k_resident(StepArgs a, const int4* __restrict__ items,
                                                             const int4* __restrict__ rgs, const int* __restrict__ stream,
-                                                            const float* __restrict__ wstream, int max_rows, int steps) {
+                                                            const float* __restrict__ wstream, uint8_t* __restrict__ rbest,
+                                                            uint8_t* __restrict__ rimp, int max_rows, int steps) {
   constexpr int NT = RTeam<BT>::NT;
   constexpr int NW = NT / 64;
   using S = typename std::conditional<WM == 2, double, int>::type;
@@ -190,18 +191,12 @@ __global__ __launch_bounds__(RTeam<BT>::NT) void k_resident(StepArgs a, const in
   const int every = a.ctrl->score_every;
   const size_t B = (size_t)a.B;
 
-  // this thread's share [lo, hi), its head row, its own rows [ob, oe) and the threads
-  // whose shares start inside its last own row
+  // this thread's share [lo, hi) and its header (built with the stream): head row, the
+  // threads whose shares start inside its last own row, its own rows [ob, oe)
   const int lo = (int)((long long)E * tid / NT), hi = (int)((long long)E * (tid + 1) / NT);
   const int len = hi - lo;
-  const int ob = r_first_row_at(a.rp, r0, nr, lo);
-  const int oe = r_first_row_at(a.rp, r0, nr, hi);
-  const int head_row = (lo < E && (ob >= nr || r_pos(a.rp, r0, ob) != lo)) ? ob - 1 : -1;
-  int ntail = 0;
-  if (oe > ob) {
-    const long long row_end = r_pos(a.rp, r0, oe);  // end of the last own row
-    if (row_end > hi) ntail = (int)((row_end * NT + E - 1) / E) - tid - 1;
-  }
+  const int4 hdr = *reinterpret_cast<const int4*>(stream + gs.x + 4 * tid);
+  const int head_row = hdr.x, ntail = hdr.y, ob = hdr.z, oe = hdr.w;
 
   // X_t0 of the tile into buffer 0; running best of the tile's columns
   const T* X0 = reinterpret_cast<const T*>(a.x[t0 & 1]);
@@ -222,8 +217,8 @@ __global__ __launch_bounds__(RTeam<BT>::NT) void k_resident(StepArgs a, const in
     ecw[c] = eta[c] * a.cW;
   }
   uint32_t ever = 0;  // columns improved during this launch (bit c)
-  const int* sp = stream + gs.x + tid * 4;
-  const float* wp = WM != 0 ? wstream + gs.x + tid * 4 : nullptr;
+  const int* sp = stream + gs.x + 4 * NT + tid * 4;
+  const float* wp = WM != 0 ? wstream + gs.x + 4 * NT + tid * 4 : nullptr;
   const size_t sstride = (size_t)NT * 4;
   __syncthreads();
 
@@ -412,13 +407,12 @@ __global__ __launch_bounds__(RTeam<BT>::NT) void k_resident(StepArgs a, const in
         a.best_step[(size_t)g * B + c0 + c] = bstep[c];
       }
   }
-  if (ever) {
-    // best_bits: byte (c0 + c) / 8 of each row; tiles of 8 or more columns own whole bytes,
-    // narrower ones share bytes with other workgroups and merge through word atomics
-    for (int i = tid; i < nr; i += NT) {
-      const uint32_t bits = s_side[i];
-      const size_t rowb = (size_t)(r0 + i) * a.NBY;
-      if constexpr (BT >= 8) {
+  if constexpr (BT >= 8) {
+    // best_bits: tiles of 8 or more columns own whole bytes of each row
+    if (ever) {
+      for (int i = tid; i < nr; i += NT) {
+        const uint32_t bits = s_side[i];
+        const size_t rowb = (size_t)(r0 + i) * a.NBY;
 #pragma unroll
         for (int q = 0; q < BT / 8; ++q) {
           const uint32_t mq = (ever >> (8 * q)) & 0xFFu;
@@ -427,21 +421,78 @@ __global__ __launch_bounds__(RTeam<BT>::NT) void k_resident(StepArgs a, const in
             *p = (uint8_t)((*p & ~mq) | ((bits >> (8 * q)) & mq));
           }
         }
-      } else {
-        const size_t byte = rowb + (c0 >> 3);
-        const int sh = (int)((byte & 3) * 8 + (c0 & 7));
-        unsigned int* w = reinterpret_cast<unsigned int*>(a.best_bits + (byte & ~(size_t)3));
-        const uint32_t mw = (ever & ((1u << BT) - 1u)) << sh;
-        atomicAnd(w, ~mw);
-        atomicOr(w, (bits << sh) & mw);
       }
     }
+  } else {
+    // narrower tiles share bytes of best_bits with other workgroups: the sides go to the
+    // tile's own byte array (rows in order) and the improved columns to a flag byte, which
+    // k_rbest merges after the launch
+    const int tile = c0 / BT;
+    if (tid == 0) rimp[(size_t)g * (B / BT) + tile] = (uint8_t)ever;
+    if (ever)
+      for (int i = tid; i < nr; i += NT) rbest[(size_t)tile * a.n + r0 + i] = (uint8_t)s_side[i];
   }
 }
 
-// Interleaved slot streams of the resident schedule: slot j of thread t's share of graph g
-// (slot floor(E t / NT) + j of the graph) at stream[off_g + (j / 4) NT 4 + 4 t + j % 4], as a
-// local row index (own slots keep the flag bit), with its weight beside it.
+// Merge of the narrow resident tiles' best sides into best_bits: byte k of row r takes, for
+// each tile of the byte's columns improved during the launch, that tile's bits.
+template <int BT>
+__global__ void k_rbest(StepArgs a, const uint8_t* __restrict__ rbest, const uint8_t* __restrict__ rimp,
+                        const int* __restrict__ goff) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n * a.NBY) return;
+  const long long r = i / a.NBY;
+  const int k = (int)(i % a.NBY);
+  int lo = 0, hi = a.G - 1;  // graph of row r
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (goff[mid] <= r) lo = mid; else hi = mid - 1;
+  }
+  const int ntile = a.B / BT;
+  uint32_t byte = a.best_bits[i];
+  const uint32_t old = byte;
+#pragma unroll
+  for (int q = 0; q < 8 / BT; ++q) {
+    const int t = k * (8 / BT) + q;
+    if (t < ntile) {
+      const uint32_t m = rimp[(size_t)lo * ntile + t];
+      if (m) {
+        const uint32_t bits = rbest[(size_t)t * a.n + r];
+        byte = (byte & ~(m << (q * BT))) | ((bits & m) << (q * BT));
+      }
+    }
+  }
+  if (byte != old) a.best_bits[i] = (uint8_t)byte;
+}
+
+// Headers of the resident schedule's shares: for thread t of graph g (share [lo, hi) of the
+// graph's E slots) {head row (the row holding slot lo when that is not its own slot, else
+// -1), the number of following threads whose shares start inside its last own row when that
+// row continues past hi, first own row, end of its own rows} at stream[off_g + 4 t].
+__global__ void k_rhead(int G, int nt, const int4* __restrict__ rgs, const int* __restrict__ goff,
+                        const int* __restrict__ rp, int* __restrict__ stream) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)G * nt) return;
+  const int g = (int)(i / nt), t = (int)(i % nt);
+  const int4 gs = rgs[g];
+  const int r0 = goff[g], nr = goff[g + 1] - r0;
+  const long long E = gs.z;
+  const int lo = (int)(E * t / nt), hi = (int)(E * (t + 1) / nt);
+  const int ob = r_first_row_at(rp, r0, nr, lo);
+  const int oe = r_first_row_at(rp, r0, nr, hi);
+  const int head_row = (lo < E && (ob >= nr || r_pos(rp, r0, ob) != lo)) ? ob - 1 : -1;
+  int ntail = 0;
+  if (oe > ob) {
+    const long long row_end = r_pos(rp, r0, oe);  // end of the last own row
+    if (row_end > hi) ntail = (int)((row_end * nt + E - 1) / E) - t - 1;
+  }
+  reinterpret_cast<int4*>(stream + gs.x)[t] = make_int4(head_row, ntail, ob, oe);
+}
+
+// Interleaved slot streams of the resident schedule: after the headers, slot j of thread t's
+// share of graph g (slot floor(E t / NT) + j of the graph) at
+// stream[off_g + 4 NT + (j / 4) NT 4 + 4 t + j % 4], as a local row index (own slots keep the
+// flag bit), with its weight beside it.
 __global__ void k_rstream(long long nslots, int G, int nt, const int4* __restrict__ rgs, const int* __restrict__ goff,
                           const int* __restrict__ slots, const float* __restrict__ sw, int* __restrict__ stream,
                           float* __restrict__ wstream) {
@@ -456,7 +507,7 @@ __global__ void k_rstream(long long nslots, int G, int nt, const int4* __restric
   const long long E = gs.z, k = K - gs.w;
   const long long t = ((k + 1) * nt - 1) / E;
   const long long j = k - E * t / nt;
-  const size_t dst = (size_t)gs.x + (size_t)(j >> 2) * nt * 4 + (size_t)t * 4 + (size_t)(j & 3);
+  const size_t dst = (size_t)gs.x + (size_t)nt * 4 + (size_t)(j >> 2) * nt * 4 + (size_t)t * 4 + (size_t)(j & 3);
   const int v = slots[K];
   const int r0 = goff[lo];
   stream[dst] = v < 0 ? (int)(0x80000000u | (unsigned)((v & 0x7FFFFFFF) - r0)) : v - r0;
@@ -466,14 +517,22 @@ __global__ void k_rstream(long long nslots, int G, int nt, const int4* __restric
 // prepare != 0: raise the kernels' dynamic LDS limit (outside any stream capture); else launch.
 template <typename T, int BT>
 hipError_t launch_bt(const StepArgs& a, const int4* items, int nitems, const int4* rgs, const int* stream,
-                     const float* wstream, int max_rows, int steps, size_t lds, int wm, hipStream_t s, int prepare) {
+                     const float* wstream, uint8_t* rbest, uint8_t* rimp, const int* goff, int max_rows, int steps,
+                     size_t lds, int wm, hipStream_t s, int prepare) {
   auto go = [&](auto kern) {
     if (prepare)
       return hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)lds);
-    hipLaunchKernelGGL(kern, dim3(nitems), dim3(RTeam<BT>::NT), lds, s, a, items, rgs, stream, wstream, max_rows,
-                       steps);
-    return hipGetLastError();
+    hipLaunchKernelGGL(kern, dim3(nitems), dim3(RTeam<BT>::NT), lds, s, a, items, rgs, stream, wstream, rbest, rimp,
+                       max_rows, steps);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && BT < 8) {
+      const long long work = a.n * a.NBY;
+      hipLaunchKernelGGL(k_rbest<BT < 8 ? BT : 1>, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, a, rbest,
+                         rimp, goff);
+      e = hipGetLastError();
+    }
+    return e;
   };
   auto by_form = [&](auto lf) {
     constexpr int LF = decltype(lf)::value;
@@ -490,26 +549,26 @@ hipError_t launch_bt(const StepArgs& a, const int4* items, int nitems, const int
 }
 
 hipError_t dispatch_bt(const StepArgs& a, int dtype, int bt, const int4* items, int nitems, const int4* rgs,
-                       const int* stream, const float* wstream, int max_rows, int steps, hipStream_t s,
-                       int prepare) {
+                       const int* stream, const float* wstream, uint8_t* rbest, uint8_t* rimp, const int* goff,
+                       int max_rows, int steps, hipStream_t s, int prepare) {
   const size_t lds = resident_lds_bytes(max_rows, bt, dtype);
   const int wm = a.w == nullptr ? 0 : (a.intw ? 1 : 2);
   if (dtype == 0) {
     switch (bt) {
-      case 1: return launch_bt<float, 1>(a, items, nitems, rgs, stream, wstream, max_rows, steps, lds, wm, s, prepare);
-      case 2: return launch_bt<float, 2>(a, items, nitems, rgs, stream, wstream, max_rows, steps, lds, wm, s, prepare);
-      case 4: return launch_bt<float, 4>(a, items, nitems, rgs, stream, wstream, max_rows, steps, lds, wm, s, prepare);
-      case 8: return launch_bt<float, 8>(a, items, nitems, rgs, stream, wstream, max_rows, steps, lds, wm, s, prepare);
-      case 16: return launch_bt<float, 16>(a, items, nitems, rgs, stream, wstream, max_rows, steps, lds, wm, s, prepare);
+      case 1: return launch_bt<float, 1>(a, items, nitems, rgs, stream, wstream, rbest, rimp, goff, max_rows, steps, lds, wm, s, prepare);
+      case 2: return launch_bt<float, 2>(a, items, nitems, rgs, stream, wstream, rbest, rimp, goff, max_rows, steps, lds, wm, s, prepare);
+      case 4: return launch_bt<float, 4>(a, items, nitems, rgs, stream, wstream, rbest, rimp, goff, max_rows, steps, lds, wm, s, prepare);
+      case 8: return launch_bt<float, 8>(a, items, nitems, rgs, stream, wstream, rbest, rimp, goff, max_rows, steps, lds, wm, s, prepare);
+      case 16: return launch_bt<float, 16>(a, items, nitems, rgs, stream, wstream, rbest, rimp, goff, max_rows, steps, lds, wm, s, prepare);
       default: return hipErrorInvalidValue;
     }
   }
   switch (bt) {
-    case 1: return launch_bt<uint16_t, 1>(a, items, nitems, rgs, stream, wstream, max_rows, steps, lds, wm, s, prepare);
-    case 2: return launch_bt<uint16_t, 2>(a, items, nitems, rgs, stream, wstream, max_rows, steps, lds, wm, s, prepare);
-    case 4: return launch_bt<uint16_t, 4>(a, items, nitems, rgs, stream, wstream, max_rows, steps, lds, wm, s, prepare);
-    case 8: return launch_bt<uint16_t, 8>(a, items, nitems, rgs, stream, wstream, max_rows, steps, lds, wm, s, prepare);
-    case 16: return launch_bt<uint16_t, 16>(a, items, nitems, rgs, stream, wstream, max_rows, steps, lds, wm, s, prepare);
+    case 1: return launch_bt<uint16_t, 1>(a, items, nitems, rgs, stream, wstream, rbest, rimp, goff, max_rows, steps, lds, wm, s, prepare);
+    case 2: return launch_bt<uint16_t, 2>(a, items, nitems, rgs, stream, wstream, rbest, rimp, goff, max_rows, steps, lds, wm, s, prepare);
+    case 4: return launch_bt<uint16_t, 4>(a, items, nitems, rgs, stream, wstream, rbest, rimp, goff, max_rows, steps, lds, wm, s, prepare);
+    case 8: return launch_bt<uint16_t, 8>(a, items, nitems, rgs, stream, wstream, rbest, rimp, goff, max_rows, steps, lds, wm, s, prepare);
+    case 16: return launch_bt<uint16_t, 16>(a, items, nitems, rgs, stream, wstream, rbest, rimp, goff, max_rows, steps, lds, wm, s, prepare);
     default: return hipErrorInvalidValue;
   }
 }
@@ -536,23 +595,27 @@ size_t resident_lds_bytes(int max_rows, int bt, int dtype) {
 }
 
 hipError_t prepare_resident(const StepArgs& a, int dtype, int bt, int max_rows) {
-  return dispatch_bt(a, dtype, bt, nullptr, 0, nullptr, nullptr, nullptr, max_rows, 0, nullptr, 1);
+  return dispatch_bt(a, dtype, bt, nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, max_rows, 0, nullptr,
+                     1);
 }
 
-hipError_t build_resident_stream(long long nslots, int G, int bt, const int4* rgs, const int* goff, const int* slots,
-                                 const float* sw, int* stream, float* wstream, hipStream_t s) {
+hipError_t build_resident_stream(long long nslots, int G, int bt, const int4* rgs, const int* goff, const int* rp,
+                                 const int* slots, const float* sw, int* stream, float* wstream, hipStream_t s) {
   if (nslots <= 0) return hipSuccess;
-  const int threads = 256;
+  const int threads = 256, nt = resident_threads(bt);
+  const long long hblocks = ((long long)G * nt + threads - 1) / threads;
+  hipLaunchKernelGGL(k_rhead, dim3((unsigned)hblocks), dim3(threads), 0, s, G, nt, rgs, goff, rp, stream);
   const long long blocks = (nslots + threads - 1) / threads;
-  hipLaunchKernelGGL(k_rstream, dim3((unsigned)blocks), dim3(threads), 0, s, nslots, G, resident_threads(bt), rgs,
-                     goff, slots, sw, stream, wstream);
+  hipLaunchKernelGGL(k_rstream, dim3((unsigned)blocks), dim3(threads), 0, s, nslots, G, nt, rgs, goff, slots, sw,
+                     stream, wstream);
   return hipGetLastError();
 }
 
 hipError_t launch_resident(const StepArgs& a, int dtype, int bt, const int4* items, int nitems, const int4* rgs,
-                           const int* stream, const float* wstream, int max_rows, int steps, hipStream_t s) {
+                           const int* stream, const float* wstream, uint8_t* rbest, uint8_t* rimp, const int* goff,
+                           int max_rows, int steps, hipStream_t s) {
   if (nitems <= 0 || steps <= 0) return hipSuccess;
-  hipError_t e = dispatch_bt(a, dtype, bt, items, nitems, rgs, stream, wstream, max_rows, steps, s, 0);
+  hipError_t e = dispatch_bt(a, dtype, bt, items, nitems, rgs, stream, wstream, rbest, rimp, goff, max_rows, steps, s, 0);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, a.ctrl, steps);
   return hipGetLastError();
