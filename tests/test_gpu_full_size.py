@@ -171,6 +171,55 @@ def test_ba10k_B256_full_rows(dtype, l):
     h.destroy()
 
 
+@pytest.mark.parametrize("dtype", [deco.F32, deco.BF16])
+def test_ba10k_B256_resident_full_rows(dtype):
+    """The bench's unlifted batch on the resident schedule the solver tunes to (one column per
+    workgroup; the graph's 89,968 slots split evenly over 1024 threads, so hub rows span many
+    threads' shares and are finished from their partial sums): 12 teacher-forced steps, one
+    launch each, every row and column within the per-row float32 summation bound (plus one
+    bfloat16 ulp), exact cuts of every iterate, and more than 30% of the entries of degree <= 8
+    rows moving by more than the tolerance in the oracle's step (so a dropped update fails);
+    then 12 steps in one launch equal, bit for bit, to the same 12 steps one launch each."""
+    g = synth.barabasi_albert(10_000, 4, 0)
+    G = deco.Graph(g)
+    B, T, eta = 256, 12, 0.05
+    h = deco.Handle(G, B=B, x_dtype=dtype, eta=eta, seed=1)
+    h.set_schedule(64, 1 << 30, 0, 128, 2048, 0, 1)
+    assert h.schedule().startswith("resident cols=1")
+    h.start(deco.INIT_UNIFORM, batch=0)
+    tr = h.set_trace(2 * T + 1)
+    low = g.degrees() <= 8
+    x = to_np(h.read_x()).astype(np.float64)
+    moved_low = total_low = 0
+    for t in range(T):
+        h.step(1, use_graph=True)
+        xn = to_np(h.read_x()).astype(np.float64)
+        want = oracle.step(g, x, eta)
+        cmp, tol = step_tol(g, x, want, eta, dtype)
+        d = np.abs(xn - cmp)
+        assert np.all(d <= tol), f"step {t}: {(d > tol).sum()} elements off, max {d.max():.3e}"
+        assert np.array_equal(tr.cpu().numpy()[t], oracle_cuts(g, x, B, 1, False)[0]), f"cut at step {t}"
+        mv = np.abs(want - x) > tol
+        moved_low += int(mv[low].sum())
+        total_low += int(mv[low].size)
+        x = xn
+    assert moved_low > 0.3 * total_low, (moved_low, total_low)
+    x_mid = h.read_x().clone()
+    h.step(T)
+    one = to_np(h.read_x())
+    h2 = deco.Handle(G, B=B, x_dtype=dtype, eta=eta, seed=1)
+    h2.set_schedule(64, 1 << 30, 0, 128, 2048, 0, 1)
+    h2.start(deco.INIT_USER, x0=x_mid)
+    tr2 = h2.set_trace(T + 1)
+    for _ in range(T):
+        h2.step(1)
+    assert np.array_equal(one, to_np(h2.read_x()))
+    assert np.array_equal(tr.cpu().numpy()[T:2 * T], tr2.cpu().numpy()[:T])
+    print(f"BA10k resident dtype={dtype}: {moved_low / total_low:.1%} of low-degree entries moved beyond tolerance")
+    h.destroy()
+    h2.destroy()
+
+
 def test_ba10k_B256_cuts_every_step():
     """Exact cuts of every iterate of the bench's lifted shape (l = 4, bfloat16) from an IDI
     start, the start the solver uses."""
