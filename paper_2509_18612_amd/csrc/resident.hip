@@ -268,9 +268,19 @@ __global__ __launch_bounds__(RTeam<BT>::NT) void k_resident(StepArgs a, const in
       const int ownm = v >> 31;
       const int idx = v & 0x7FFFFFFF;
       const uint32_t zu = r_sides<BT, LF>(xu);
-      float y[BT];
-      update(y);
-      RowIO<T, BT>::store(reinterpret_cast<T*>(nxt_b + r_sel(ownm & ~headm, ri, spare)), y);
+      if constexpr (BT >= 4) {
+        // wide tiles: the update costs BT fused multiply-adds, so only waves with a lane on
+        // an own slot take it (long rows make those slots rare)
+        if (ownm & ~headm) {
+          float y[BT];
+          update(y);
+          RowIO<T, BT>::store(reinterpret_cast<T*>(nxt_b + ri), y);
+        }
+      } else {
+        float y[BT];
+        update(y);
+        RowIO<T, BT>::store(reinterpret_cast<T*>(nxt_b + r_sel(ownm & ~headm, ri, spare)), y);
+      }
 #pragma unroll
       for (int c = 0; c < BT; ++c) hacc[c] = r_self(ownm & headm, acc[c], hacc[c]);
       headm &= ~ownm;
