@@ -13,10 +13,11 @@
 //
 // Work item i: {graph, first row, end row, first column}. The graph's slots are split into
 // equal shares, one per thread, read from an interleaved copy of the slot list built once per
-// schedule (k_rstream); rows cut by a share boundary are finished by the thread holding their
-// own slot, which adds the following threads' partial sums in thread order. The running best
-// (cut, step and the sides of the best iterate) stays in LDS and registers during the launch
-// and is written back at the end; the trace and the current cut are written per scored step.
+// schedule (k_rhead, k_rstream); rows cut by a share boundary are finished by the thread holding
+// their own slot, which adds the following threads' partial sums in thread order. The running
+// best (cut, step and the sides of the best iterate) stays in LDS and registers during the
+// launch and is written back at the end (tiles narrower than a byte of best_bits through
+// k_rbest); the trace and the current cut are written per scored step.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
