@@ -448,7 +448,7 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=200)
     ap.add_argument("--others", default="er800,uneven,reg3,dense",
                     help="comma list of other workload shapes to time (empty: none)")
-    ap.add_argument("--kernel-only", choices=["unlifted", "lifted", "copy", "reg3", "uneven"], default=None,
+    ap.add_argument("--kernel-only", choices=["unlifted", "lifted", "copy", "reg3", "uneven", "round"], default=None,
                     help="run only the step kernel of that shape for --kernel-steps launches (schedule pinned "
                          "by --pin, else autotuned), or a 256 MiB device copy, for counter runs")
     ap.add_argument("--resident-cols", type=int, default=0,
@@ -475,6 +475,11 @@ def main():
     csr = synth.barabasi_albert(n, m, 0)
     G = deco.Graph(csr)
     K, l_max = 8, 4
+    if args.kernel_only == "round":
+        # the float32 arm alone (its warm-up and timed rounds), for a kernel trace of the round
+        arm = solver_arm(deco, torch, G, B, K, l_max, args, deco.F32, 0, args.warmup, args.steps)
+        print(f"# round: {arm['value']:.3e} EU/s, {arm['ms_per_round']:.1f} ms per round", flush=True)
+        return
     if args.kernel_only:
         kernel_only(deco, torch, G, B, args)
         return

@@ -723,7 +723,6 @@ deco_status deco_init(deco_handle** out, const deco_graph* g, const deco_params*
   // every component active until a start says otherwise
   h->lact_host.assign(p->B, p->l);
   a.lact = reinterpret_cast<const int*>(ws + lay.l_active);
-  a.lall = 1;
   if (e == hipSuccess)
     e = hipMemcpyAsync(ws + lay.l_active, h->lact_host.data(), sizeof(int) * p->B, hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = launch_reset(a, a.acc, 2LL * lay.R * h->G * p->B, p->score_every, h->stream);
@@ -790,16 +789,17 @@ deco_status deco_start(deco_handle* h, const deco_start_args* s) {
       for (int b = 0; b < h->p.B; ++b) h->lact_host[b] = s->l_active ? s->l_active[b] : h->p.l;
       HIP_TRY(h, hipMemcpyAsync(ws + lay.l_active, h->lact_host.data(), sizeof(int) * h->p.B, hipMemcpyHostToDevice,
                                 h->stream));
-      int all = 1;
-      for (int b = 0; b < h->p.B; ++b) all = all && h->lact_host[b] == h->p.l;
-      if (all != h->args.lall) {
-        // captured launches hold the other step kernel
-        h->args.lall = all;
-        for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
-        h->graphs.clear();
-      }
     }
     if (s->l_active) lact = reinterpret_cast<int*>(ws + lay.l_active);
+    // the step kernel runs the largest active count of components (at least 1)
+    int lrun = 1;
+    for (int b = 0; b < h->p.B; ++b) lrun = std::max(lrun, h->lact_host[b]);
+    if (lrun != h->args.L) {
+      // captured launches hold another step kernel
+      h->args.L = lrun;
+      for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+      h->graphs.clear();
+    }
   }
   int* goff_dev = reinterpret_cast<int*>(ws + lay.goff);
   if (s->kind == DECO_INIT_USER) {
@@ -866,6 +866,11 @@ deco_status deco_start(deco_handle* h, const deco_start_args* s) {
     HIP_TRY(h, launch_init(ia, h->stream));
   }
   if (h->dense) HIP_TRY(h, launch_dense_transpose(h->X, h->args.xT[0], h->n, h->C, h->stream));
+  // components past the step kernel's count are never written by the steps: the start wrote
+  // them as 0 into X_0; the other buffer (the start's scratch, and earlier batches may have run
+  // more components) is cleared
+  if (!h->dense && h->args.L < h->p.l)
+    HIP_TRY(h, launch_zero(ws + lay.xalt, (size_t)h->n * h->C * elem_size(h->dtype), h->stream));
   if (h->args.vel)  // a new start begins at rest
     HIP_TRY(h, hipMemsetAsync(h->args.vel, 0, sizeof(float) * (size_t)h->n * h->C, h->stream));
   HIP_TRY(h, launch_reset(h->args, h->args.acc, 2LL * h->R * h->G * h->p.B, h->p.score_every, h->stream));

@@ -48,7 +48,10 @@ struct StepArgs {
   const float* w;   // NULL = unit weights
   const float* dw;  // weighted degree (Laplacian form), may be NULL for the cut form
   void* x[2];       // ping-pong iterates; x[t & 1] holds X_t
-  int C, B, L, lifted;
+  int C, B, lifted;
+  int L;            // components per initialisation the step kernel runs: the handle's l, or the
+                    // largest active count when that is smaller (the components past it are 0 in
+                    // both iterate buffers and no kernel writes them)
   int Wc;           // lanes per row team (power of two, <= 64; Wc * VEC <= 256)
   const int* slots; // slot list (n + nnz)
   const float* sw;  // slot weights (n + nnz), NULL for unit weights
@@ -58,8 +61,6 @@ struct StepArgs {
   const float* eta; // [B]
   const int* lact;  // [B] active components of each initialisation (components at and past
                     // it are exactly 0 in X and are not gathered), or NULL (all l active)
-  int lall;         // host side: 1 when every initialisation has all L components active (the
-                    // launch then takes the step kernel without load predicates)
   uint8_t* bits[3]; // cut bits of the iterate scored at step t live in bits[t % 3]
   uint8_t* best_bits;
   uint8_t* mask;    // [2][G][NBY]: improvements of scored step t in mask[t & 1]
@@ -116,6 +117,8 @@ hipError_t launch_drain(StepArgs a, long long n, const int* goff, hipStream_t s)
 // Workgroups that complete one step's G * B cuts (256 each, at most 64).
 int completion_blocks(long long GB);
 hipError_t launch_fill_eta(float* eta, int B, float v, hipStream_t s);
+// Zeroes 'bytes' bytes (an even count) of device memory with a kernel.
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // Resident steps (resident.hip): 'steps' steps of an unlifted (or l = 1) batch in one launch,
 // one workgroup per item {graph, first row, end row, first column} holding bt columns of the
 // graph's rows in LDS; then the step counter advances by 'steps'. prepare_resident raises the

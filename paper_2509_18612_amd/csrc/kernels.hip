@@ -780,8 +780,9 @@ __device__ __forceinline__ void complete_step(const StepArgs& a, long long t, bo
 
 // LF: the lifted flag known when compiling (0 or 1, rows of one component) or -1 (read from a).
 // MOM: heavy-ball momentum (velocity in a.vel); without it the update code has no velocity path.
-// ALL: every component of every initialisation is active (l > 1 rows gather without
-// predicates; chosen at launch from the host's copy of the active counts).
+// ALL: l > 1 rows gather every component without predicates (4-value lanes of up to 4
+// components: the launch runs the largest active count, and the components of an
+// initialisation with fewer are gathered as the zeros they are).
 template <typename T, int VEC, int L, int WM, int LF, bool MOM, bool ALL = false>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(DECO_STEP_WAVES_PER_EU)))
 void k_step(StepArgs a) {
@@ -1447,42 +1448,42 @@ hipError_t step_dispatch(const StepArgs& a, int wmode, int grid, hipStream_t s) 
   } else {
   // rows of one component take the lifted flag (which selects x > 0 or x >= 0 as the side)
   // as a compile-time constant; with l > 1 components the side is always sum >= 0, and
-  // 4-value lanes with every component active take the kernel without load predicates
+  // 4-value lanes take the kernel without load predicates: the launch runs the largest active
+  // count of components, and gathering the zeros of an initialisation with fewer was measured
+  // faster than predicating the loads
   constexpr int kOff = LL == 1 ? 0 : -1, kOn = LL == 1 ? 1 : -1;
   const bool on = LL == 1 && a.lifted;
   if constexpr (LL > 1 && LL <= 4 && VEC == 4) {
-    if (a.lact == nullptr || a.lall) {
-      if (wmode == kUnitW)
-        hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW, -1, false, true>), g, b, 0, s, a);
-      else if (wmode == kPm1W)
-        hipLaunchKernelGGL((k_step<T, VEC, LL, kPm1W, -1, false, true>), g, b, 0, s, a);
-      else if (wmode == kIntW)
-        hipLaunchKernelGGL((k_step<T, VEC, LL, kIntW, -1, false, true>), g, b, 0, s, a);
-      else
-        hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW, -1, false, true>), g, b, 0, s, a);
-      return hipGetLastError();
-    }
-  }
-  if (wmode == kUnitW) {
-    if (on)
-      hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW, kOn, false>), g, b, 0, s, a);
+    if (wmode == kUnitW)
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW, -1, false, true>), g, b, 0, s, a);
+    else if (wmode == kPm1W)
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kPm1W, -1, false, true>), g, b, 0, s, a);
+    else if (wmode == kIntW)
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kIntW, -1, false, true>), g, b, 0, s, a);
     else
-      hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW, kOff, false>), g, b, 0, s, a);
-  } else if (wmode == kPm1W) {
-    if (on)
-      hipLaunchKernelGGL((k_step<T, VEC, LL, kPm1W, kOn, false>), g, b, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_step<T, VEC, LL, kPm1W, kOff, false>), g, b, 0, s, a);
-  } else if (wmode == kIntW) {
-    if (on)
-      hipLaunchKernelGGL((k_step<T, VEC, LL, kIntW, kOn, false>), g, b, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_step<T, VEC, LL, kIntW, kOff, false>), g, b, 0, s, a);
+      hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW, -1, false, true>), g, b, 0, s, a);
   } else {
-    if (on)
-      hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW, kOn, false>), g, b, 0, s, a);
-    else
-      hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW, kOff, false>), g, b, 0, s, a);
+    if (wmode == kUnitW) {
+      if (on)
+        hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW, kOn, false>), g, b, 0, s, a);
+      else
+        hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW, kOff, false>), g, b, 0, s, a);
+    } else if (wmode == kPm1W) {
+      if (on)
+        hipLaunchKernelGGL((k_step<T, VEC, LL, kPm1W, kOn, false>), g, b, 0, s, a);
+      else
+        hipLaunchKernelGGL((k_step<T, VEC, LL, kPm1W, kOff, false>), g, b, 0, s, a);
+    } else if (wmode == kIntW) {
+      if (on)
+        hipLaunchKernelGGL((k_step<T, VEC, LL, kIntW, kOn, false>), g, b, 0, s, a);
+      else
+        hipLaunchKernelGGL((k_step<T, VEC, LL, kIntW, kOff, false>), g, b, 0, s, a);
+    } else {
+      if (on)
+        hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW, kOn, false>), g, b, 0, s, a);
+      else
+        hipLaunchKernelGGL((k_step<T, VEC, LL, kRealW, kOff, false>), g, b, 0, s, a);
+    }
   }
   return hipGetLastError();
   }
@@ -1663,6 +1664,12 @@ __global__ void k_merge(StepArgs a, long long n, const int* goff) {
 __global__ void k_fill(float* p, int n, float v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
+}
+
+// Zeroes n 16-bit words (grid-stride).
+__global__ void k_zero16(uint16_t* p, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0;
 }
 
 // ------------------------------------------------------------------ starting points
@@ -1923,6 +1930,14 @@ hipError_t launch_sides(const void* x0, const void* x1, void* s0, void* s1, cons
 
 hipError_t launch_fill_eta(float* eta, int B, float v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3(blocks_for(B, 256)), dim3(256), 0, s, eta, B, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const long long n = (long long)(bytes / 2);
+  if (n <= 0) return hipSuccess;
+  const long long blocks = (n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192;
+  hipLaunchKernelGGL(k_zero16, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<uint16_t*>(p), n);
   return hipGetLastError();
 }
 
