@@ -1030,10 +1030,11 @@ deco_status deco_autotune(deco_handle* h, int32_t steps) {
   // were measured slower at BA(10^4, 4), B = 256: set_schedule still accepts them)
   const int mt = min_tile(h->p.B, h->p.l);
   const int wspan = 4;
-  // lane widths: the native one, and 4 bfloat16 per lane for unlifted bfloat16 rows (twice the
-  // lanes per tile: one row team per wave at B = 256)
+  // lane widths: the native one, and 4 values per lane for unlifted bfloat16 rows (twice the
+  // lanes per tile: one row team per wave at B = 256) and lifted float32 rows (half the lanes
+  // per tile, twice the registers per lane)
   std::vector<int> vecs{vec};
-  if (h->dtype == DECO_BF16 && vec == 8) vecs.push_back(4);
+  if ((h->dtype == DECO_BF16 && vec == 8) || (h->dtype == DECO_F32 && vec == 2)) vecs.push_back(4);
   for (int vw : vecs) {
     const int wmax_v = max_wc(vw, h->p.B);
     for (int Wc = wmax_v; Wc >= 1 && Wc * vw >= mt && Wc * wspan >= wmax_v; Wc /= 2) {
@@ -1127,8 +1128,10 @@ deco_status deco_set_schedule(deco_handle* h, const deco_schedule* q) {
     return DECO_E_INVAL;
   Schedule s = default_schedule(h);
   if (q->lane_elems != 0) {
-    // 4 bfloat16 per lane is the one alternative width (unlifted bfloat16 rows)
-    if (q->lane_elems != 4 || h->dtype != DECO_BF16 || s.vec != 8) return DECO_E_INVAL;
+    // 4 values per lane is the one alternative width (unlifted bfloat16 rows, float32 rows of
+    // 2 to 4 components)
+    if (q->lane_elems != 4 || !((h->dtype == DECO_BF16 && s.vec == 8) || (h->dtype == DECO_F32 && s.vec == 2)))
+      return DECO_E_INVAL;
     s.vec = 4;
   }
   s.Wc = q->lanes_per_row;

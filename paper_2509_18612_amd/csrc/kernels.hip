@@ -11,7 +11,7 @@
 //
 // Mapping. X is node-major: row v holds its l*B values contiguously. One initialisation
 // tile of a row (Bt = Wc*VEC columns, at most 256, for every component) is held by a row
-// team of Wc lanes with 16-byte loads (8-byte for lifted bfloat16 rows); a 256-thread
+// team of Wc lanes with 16-byte loads (8-byte for lifted rows of 2 to 4 components); a 256-thread
 // workgroup has NS = 256/Wc teams. The graph is read through its slot list: row v is its
 // own index (top bit set) followed by its neighbours, so a team walks a flat stream of
 // slots and never waits on a row boundary. Work items are row ranges of one graph and one
@@ -68,6 +68,20 @@ struct VecIO<float, 4> {
   }
   static __device__ __forceinline__ void store(float* p, const float (&o)[4]) {
     *reinterpret_cast<float4*>(p) = make_float4(o[0], o[1], o[2], o[3]);
+  }
+};
+
+template <>
+struct VecIO<float, 2> {
+  using raw = float2;
+  static __device__ __forceinline__ raw load_raw(const float* p) { return *reinterpret_cast<const float2*>(p); }
+  static __device__ __forceinline__ raw zero() { return make_float2(0.f, 0.f); }
+  static __device__ __forceinline__ void unpack(const raw& v, float (&o)[2]) {
+    o[0] = v.x;
+    o[1] = v.y;
+  }
+  static __device__ __forceinline__ void store(float* p, const float (&o)[2]) {
+    *reinterpret_cast<float2*>(p) = make_float2(o[0], o[1]);
   }
 };
 
@@ -1453,7 +1467,7 @@ hipError_t step_dispatch(const StepArgs& a, int wmode, int grid, hipStream_t s) 
   // faster than predicating the loads
   constexpr int kOff = LL == 1 ? 0 : -1, kOn = LL == 1 ? 1 : -1;
   const bool on = LL == 1 && a.lifted;
-  if constexpr (LL > 1 && LL <= 4 && VEC == 4) {
+  if constexpr (LL > 1 && LL <= 4 && (VEC == 4 || VEC == 2)) {
     if (wmode == kUnitW)
       hipLaunchKernelGGL((k_step<T, VEC, LL, kUnitW, -1, false, true>), g, b, 0, s, a);
     else if (wmode == kPm1W)
@@ -1490,11 +1504,17 @@ hipError_t step_dispatch(const StepArgs& a, int wmode, int grid, hipStream_t s) 
 }
 
 // All component counts for float32 and one-element lanes; bfloat16 runs unlifted rows 8 or
-// 4 values per lane and lifted rows (l > 1) 4 values per lane.
+// 4 values per lane and lifted rows (l > 1) 4 values per lane; 2-value float32 lanes run
+// rows of 2 to 4 components without momentum (launch_step maps the rest to 4-value lanes).
 template <typename T, int VEC, bool MOM>
 hipError_t step_dispatch_l(const StepArgs& a, int wmode, int grid, hipStream_t s) {
   constexpr bool bf_wide = sizeof(T) == 2 && VEC == 8;
-  if (a.L == 1) return step_dispatch<T, VEC, 1, MOM>(a, wmode, grid, s);
+  constexpr bool f32_pair = sizeof(T) == 4 && VEC == 2;
+  if constexpr (f32_pair) {
+    if (MOM || a.L == 1) return hipErrorInvalidValue;
+  } else {
+    if (a.L == 1) return step_dispatch<T, VEC, 1, MOM>(a, wmode, grid, s);
+  }
   if constexpr (!bf_wide) {
     switch (a.L) {
       case 2: return step_dispatch<T, VEC, 2, MOM>(a, wmode, grid, s);
@@ -1515,6 +1535,8 @@ hipError_t launch_step_impl(const StepArgs& a, int dtype, int vec, int grid, hip
   const int wmode = step_weight_mode(a);
   if (dtype == 0) {
     if (vec == 4) return step_dispatch_l<float, 4, MOM>(a, wmode, grid, s);
+    if constexpr (!MOM)
+      if (vec == 2) return step_dispatch_l<float, 2, MOM>(a, wmode, grid, s);
     if (vec == 1) return step_dispatch_l<float, 1, MOM>(a, wmode, grid, s);
   } else {
     if (vec == 8) return step_dispatch_l<uint16_t, 8, MOM>(a, wmode, grid, s);
@@ -1818,7 +1840,7 @@ inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1)
 }  // namespace
 
 #ifndef DECO_KERNELS_ONLY_TU  // the host launchers live in this translation unit only
-int native_vec(int dtype, int L) { return dtype == 0 ? 4 : (L == 1 ? 8 : 4); }
+int native_vec(int dtype, int L) { return dtype == 0 ? (L >= 2 && L <= 4 ? 2 : 4) : (L == 1 ? 8 : 4); }
 
 hipError_t launch_dense_transpose(const void* X, void* XT, long long n, int C, hipStream_t s) {
   hipLaunchKernelGGL(k_transpose_bf16, dim3((unsigned)(n / 64), (unsigned)(C / 64)), dim3(256), 0, s,
@@ -1839,6 +1861,14 @@ hipError_t launch_dense_validate(const uint16_t* W, int n, float* dw, int* flags
 }
 
 hipError_t launch_step(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s) {
+  if (dtype == 0 && vec == 2 && (a.L == 1 || a.L > 4 || a.vel != nullptr)) {
+    // a tile of Wc 2-value lanes is the same tile as Wc/2 4-value lanes (the work list
+    // depends on the tile only): run the kernels of 4-value lanes on it
+    if (a.Wc < 2) return hipErrorInvalidValue;
+    StepArgs b = a;
+    b.Wc = a.Wc / 2;
+    return launch_step(b, dtype, 4, grid, s);
+  }
   if (a.L > 4) return launch_step_wide(a, dtype, vec, grid, s);
   if (a.vel != nullptr) return launch_step_momentum(a, dtype, vec, grid, s);
   return launch_step_impl<false>(a, dtype, vec, grid, s);

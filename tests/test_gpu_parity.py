@@ -155,6 +155,31 @@ LANES4 = {
 }
 
 
+# float32 rows of 2 to 4 components run 2 values per lane by default; 4 values per lane
+# (lane_elems = 4) is the alternative the autotuner also tries. A batch whose members all have
+# one active component runs the 4-value kernels on the same tile with half the lanes.
+F32_LIFTED_LANES = {
+    "l2_B64_four": (lambda: synth.barabasi_albert(500, 3, 30), 64, 2, (8, 1 << 30, 1, 4096, 256, 4), None),
+    "l3_B16_four": (lambda: synth.erdos_renyi(400, 0.05, 31), 16, 3, (4, 1 << 30, 0, 4096, 512, 4), None),
+    "l4_B32_four": (lambda: synth.barabasi_albert(400, 4, 32), 32, 4, (8, 1 << 30, 0, 4096, 128, 4), None),
+    "l4_B32_two_wide": (lambda: synth.barabasi_albert(400, 4, 33), 32, 4, (16, 1 << 30, 0, 4096, 128, 0), None),
+    "l4_B32_two_active1": (lambda: synth.erdos_renyi(400, 0.05, 34), 32, 4, None, np.ones(32, np.int32)),
+    "l3_B64_two_active_mix": (lambda: synth.barabasi_albert(500, 3, 35), 64, 3, (16, 1 << 30, 1, 4096, 256, 0),
+                              np.array([1 + (b % 3) for b in range(64)], np.int32)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(F32_LIFTED_LANES))
+def test_f32_lifted_lane_width_parity(name):
+    """Lifted float32 rows under both lane widths: teacher-forced parity with the oracle,
+    exact cuts and the running best."""
+    make, B, l, sched, la = F32_LIFTED_LANES[name]
+    g = make()
+    worst, _, s = check_run(g, B, 20, l=l, lifted=True, schedule=sched, l_active=la)
+    assert ("vec=4" if name.split("_")[2] == "four" else "vec=2") in s
+    print(f"{name}: max |dX| = {worst:.2e}, schedule: {s}")
+
+
 @pytest.mark.parametrize("name", sorted(LANES4))
 def test_bf16_four_lane_schedule_parity(name):
     """Unlifted bfloat16 rows with 4 values per lane (8-byte loads, one row team per wave at
@@ -211,13 +236,19 @@ def test_negated_start_gives_bitwise_negated_trajectory():
 
 
 def test_lifted_columns_equal_unlifted_runs_bitwise():
-    """Under one schedule (same teams, same item cuts, so the same summation order) each
-    component of a lifted run evolves exactly as an unlifted run of those columns."""
+    """Under one schedule (same lane width and teams, same item cuts, so the same summation
+    order) each component of a lifted run evolves exactly as an unlifted run of those
+    columns. Lifted float32 rows take the 4-value lanes of the unlifted kernels here
+    (lane_elems = 4): their default 2-value lanes put twice the lanes on a tile, so a
+    workgroup has half the row teams, the item's slots split at other points and the partial
+    sums of a split row add in another order; those are held to the oracle's step bound
+    (test_f32_lifted_lane_width_parity)."""
     g = synth.erdos_renyi(400, 0.05, 2)
     B, l = 16, 3
     x0 = synth.uniform_batch(g.n, l * B, 4)
     sched = (4, 1 << 30, 0, 4096, 512)
-    lifted = run_teacher_forced(g, B, 10, l=l, lifted=True, x0=x0, schedule=sched)
+    lifted = run_teacher_forced(g, B, 10, l=l, lifted=True, x0=x0, schedule=sched + (4,))
+    assert "vec=4" in lifted["handle"].schedule()
     for i in range(l):
         un = run_teacher_forced(g, B, 10, x0=np.ascontiguousarray(x0[:, i * B:(i + 1) * B]), schedule=sched)
         for xl, xu in zip(lifted["xs"], un["xs"]):
