@@ -112,12 +112,6 @@ struct RTeam {
 // store of a slot that closes no row of this thread lands in its lane's spare row.
 constexpr int kSpareRows = 64;
 
-// Bitwise select: a where m is all ones, b where m is zero.
-__device__ __forceinline__ int r_sel(int m, int a, int b) { return (a & m) | (b & ~m); }
-__device__ __forceinline__ float r_self(int m, float a, float b) {
-  return __int_as_float(r_sel(m, __float_as_int(a), __float_as_int(b)));
-}
-
 // Best sides of a row for the tile's columns (bit c: column c0 + c).
 template <int BT>
 struct RSide {
@@ -137,6 +131,16 @@ __device__ __forceinline__ uint32_t r_sides(const float (&x)[BT]) {
   }
   return m;
 }
+
+// Bitwise select: a where m is all ones, b where m is zero.
+__device__ __forceinline__ int r_sel(int m, int a, int b) { return (a & m) | (b & ~m); }
+__device__ __forceinline__ float r_self(int m, float a, float b) {
+  return __int_as_float(r_sel(m, __float_as_int(a), __float_as_int(b)));
+}
+
+// Side of one value: x > 0 (eq. (5)), or x >= 0 under the lifted rule (-0 included).
+template <int LF>
+__device__ __forceinline__ bool r_side(float x) { return LF ? x >= 0.0f : x > 0.0f; }
 
 // Slot position of local row v of a graph: its own slot follows the v earlier own slots and
 // the edges of the earlier rows.
@@ -237,20 +241,36 @@ __global__ __launch_bounds__(RTeam<BT>::NT) void k_resident(StepArgs a, const in
       xv[c] = 0.0f;
     }
     // the open row: byte offset ri in the buffers (the lane's spare row while none of this
-    // thread's rows is open), its values xv, sums acc, sides zv, weighted degree dsum; headm
-    // is all ones while the open row is the share's head row, whose sums go to hacc
+    // thread's rows is open), its values xv, sums acc, weighted degree dsum; while it is the
+    // share's head row its sums go to hacc. Narrow tiles (one or two columns per thread) keep
+    // the flags as per-lane booleans (head), so each select is one vector instruction with
+    // its mask in scalar registers; wide tiles keep them as integer masks (headm all ones
+    // while in the head row) and the open row's sides as bits (zv), so their selects stay
+    // vector bit operations rather than a scalar mask operation per column.
+    // Narrow tiles address the open row's store directly (sa) and, with float32 storage,
+    // point it at the thread's s_part entry while the open row is the head row: the store
+    // that closes the head row writes its sums there (kHeadStore), with no select per slot
+    // for hacc.
+    constexpr bool kNarrow = BT < 4;
+    constexpr bool kHeadStore = kNarrow && sizeof(T) == 4;
+    bool head = false;
+    int headm = 0;
     uint32_t zv = 0;
-    int ri = spare, headm = 0;
+    int ri = spare;
     float dsum = 0.0f, hacc[BT];
 #pragma unroll
     for (int c = 0; c < BT; ++c) hacc[c] = 0.0f;
+    unsigned char* nxt_b = reinterpret_cast<unsigned char*>(nxt);
+    unsigned char* const spare_b = nxt_b + spare;
+    unsigned char* sa = spare_b;
     if (head_row >= 0) {
       ri = head_row * BT * (int)sizeof(T);
+      head = true;
       headm = -1;
+      sa = kHeadStore ? reinterpret_cast<unsigned char*>(s_part + tid * BT) : nxt_b + ri;
       RowIO<T, BT>::load(cur + (size_t)head_row * BT, xv);
-      zv = r_sides<BT, LF>(xv);
+      if constexpr (!kNarrow) zv = r_sides<BT, LF>(xv);
     }
-    unsigned char* nxt_b = reinterpret_cast<unsigned char*>(nxt);
     auto update = [&](float (&y)[BT]) {
 #pragma unroll
       for (int c = 0; c < BT; ++c) {
@@ -266,47 +286,77 @@ __global__ __launch_bounds__(RTeam<BT>::NT) void k_resident(StepArgs a, const in
     // spare row unless the open row is one of this thread's) and opens row idx; a neighbour
     // slot is summed and counted
     auto slot = [&](int v, float wq, const float (&xu)[BT]) {
-      const int ownm = v >> 31;
       const int idx = v & 0x7FFFFFFF;
-      const uint32_t zu = r_sides<BT, LF>(xu);
-      if constexpr (BT >= 4) {
-        // wide tiles: the update costs BT fused multiply-adds, so only waves with a lane on
-        // an own slot take it (long rows make those slots rare)
+      if constexpr (kNarrow) {
+        const bool own = v < 0;
+        float y[BT];
+        update(y);
+        if constexpr (kHeadStore) {
+#pragma unroll
+          for (int c = 0; c < BT; ++c) y[c] = head ? acc[c] : y[c];
+          RowIO<T, BT>::store(reinterpret_cast<T*>(own ? sa : spare_b), y);
+        } else {
+          RowIO<T, BT>::store(reinterpret_cast<T*>(own && !head ? sa : spare_b), y);
+#pragma unroll
+          for (int c = 0; c < BT; ++c) hacc[c] = own && head ? acc[c] : hacc[c];
+        }
+        head = head && !own;
+        if (do_score) {
+#pragma unroll
+          for (int c = 0; c < BT; ++c) {
+            const bool d = r_side<LF>(xu[c]) != r_side<LF>(xv[c]) && !own;
+            if (WM == 2)
+              cnt[c] += d ? (S)wq : (S)0;
+            else if (WM == 1)
+              cnt[c] += d ? (S)(int)wq : (S)0;
+            else
+              cnt[c] += (S)d;
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < BT; ++c) {
+          const float an = WM == 0 ? acc[c] + xu[c] : fmaf(wq, xu[c], acc[c]);
+          acc[c] = own ? 0.0f : an;
+          xv[c] = own ? xu[c] : xv[c];
+        }
+        sa = own ? nxt_b + (size_t)idx * BT * sizeof(T) : sa;
+        if constexpr (LAP) dsum = own ? (WM != 0 ? wq : a.dw[r0 + idx]) : dsum;
+      } else {
+        const int ownm = v >> 31;
+        const uint32_t zu = r_sides<BT, LF>(xu);
+        // the update costs BT fused multiply-adds, so only waves with a lane on an own slot
+        // take it (long rows make those slots rare)
         if (ownm & ~headm) {
           float y[BT];
           update(y);
           RowIO<T, BT>::store(reinterpret_cast<T*>(nxt_b + ri), y);
         }
-      } else {
-        float y[BT];
-        update(y);
-        RowIO<T, BT>::store(reinterpret_cast<T*>(nxt_b + r_sel(ownm & ~headm, ri, spare)), y);
-      }
 #pragma unroll
-      for (int c = 0; c < BT; ++c) hacc[c] = r_self(ownm & headm, acc[c], hacc[c]);
-      headm &= ~ownm;
-      if (do_score) {
-        const uint32_t d = (zu ^ zv) & ~(uint32_t)ownm;
+        for (int c = 0; c < BT; ++c) hacc[c] = r_self(ownm & headm, acc[c], hacc[c]);
+        headm &= ~ownm;
+        if (do_score) {
+          const uint32_t d = (zu ^ zv) & ~(uint32_t)ownm;
+#pragma unroll
+          for (int c = 0; c < BT; ++c) {
+            const int bit = (int)((d >> c) & 1u);
+            if (WM == 2)
+              cnt[c] += bit ? (S)wq : (S)0;
+            else if (WM == 1)
+              cnt[c] += (S)((int)wq & -bit);
+            else
+              cnt[c] += bit;
+          }
+        }
 #pragma unroll
         for (int c = 0; c < BT; ++c) {
-          const int bit = (int)((d >> c) & 1u);
-          if (WM == 2)
-            cnt[c] += bit ? (S)wq : (S)0;
-          else if (WM == 1)
-            cnt[c] += (S)((int)wq & -bit);
-          else
-            cnt[c] += bit;
+          const float an = WM == 0 ? acc[c] + xu[c] : fmaf(wq, xu[c], acc[c]);
+          acc[c] = __int_as_float(__float_as_int(an) & ~ownm);
+          xv[c] = r_self(ownm, xu[c], xv[c]);
         }
+        zv = (uint32_t)r_sel(ownm, (int)zu, (int)zv);
+        ri = r_sel(ownm, idx * BT * (int)sizeof(T), ri);
+        if constexpr (LAP) dsum = r_self(ownm, WM != 0 ? wq : a.dw[r0 + idx], dsum);
       }
-#pragma unroll
-      for (int c = 0; c < BT; ++c) {
-        const float an = WM == 0 ? acc[c] + xu[c] : fmaf(wq, xu[c], acc[c]);
-        acc[c] = __int_as_float(__float_as_int(an) & ~ownm);
-        xv[c] = r_self(ownm, xu[c], xv[c]);
-      }
-      zv = (uint32_t)r_sel(ownm, (int)zu, (int)zv);
-      ri = r_sel(ownm, idx * BT * (int)sizeof(T), ri);
-      if constexpr (LAP) dsum = r_self(ownm, WM != 0 ? wq : a.dw[r0 + idx], dsum);
     };
     // slots four at a time from the interleaved stream (the next four in flight); whole
     // batches without predicates, then the share's last partial batch
@@ -341,9 +391,20 @@ __global__ __launch_bounds__(RTeam<BT>::NT) void k_resident(StepArgs a, const in
       }
     }
     // the head row's sums for its owner (zeros when the share has no head row)
+    const bool in_head = kNarrow ? head : headm != 0;
+    if constexpr (kNarrow) {
+      if (!in_head) ri = (int)(sa - nxt_b);
+    }
+    if constexpr (kHeadStore) {
+      // a head row closed inside the share has stored its sums already
+      if (in_head || head_row < 0)
 #pragma unroll
-    for (int c = 0; c < BT; ++c) s_part[tid * BT + c] = headm ? acc[c] : hacc[c];
-    const bool open_own = !headm && ri != spare;
+        for (int c = 0; c < BT; ++c) s_part[tid * BT + c] = in_head ? acc[c] : 0.0f;
+    } else {
+#pragma unroll
+      for (int c = 0; c < BT; ++c) s_part[tid * BT + c] = in_head ? acc[c] : hacc[c];
+    }
+    const bool open_own = !in_head && ri != spare;
     const bool tail = open_own && ntail > 0;
     if (open_own && ntail == 0) {
       float y[BT];
