@@ -184,9 +184,10 @@ deco_status deco_set_trace(deco_handle *h, double *trace, int32_t capacity);
 int64_t deco_current_step(const deco_handle *h);
 
 /* Choose the kernel schedule (b-tile width, long-row threshold, work item size, XCD layout,
- * or the resident schedule for unlifted and l = 1 handles) by timing candidates over a call
- * of 'steps' steps each on the device (a resident schedule has a fixed cost per call, so
- * 'steps' should be the length of the calls that will follow); the winner is kept in the
+ * or the resident schedule for unlifted and l = 1 handles) by timing candidates on the
+ * device and comparing their time per step: resident schedules over a call of 'steps'
+ * steps (they have a fixed cost per call, so 'steps' should be the length of the calls that
+ * will follow), step-kernel schedules over min(steps, 50) steps; the winner is kept in the
  * handle and in a per-process cache keyed by the graph and batch shape. It overwrites X
  * and the running best (call deco_start afterwards). Synchronous. */
 deco_status deco_autotune(deco_handle *h, int32_t steps);
@@ -281,7 +282,7 @@ typedef struct deco_solve_params {
   const double *target_cut; /* host [G] or NULL */
   int32_t use_graph;    /* capture the step loops in hipGraphs */
   int32_t autotune;     /* run deco_autotune on both handles first, over calls of the run's
-                           own length (check_every, else the longer batch; 10 to 50 steps); a
+                           own length (check_every, else the longer batch; 10 to 1000 steps); a
                            shape already tuned in this process reuses its cached winner */
   int32_t T_min;        /* > 0: the unlifted step count is searched per member in [T_min, T_q]
                            (Sec. 4.3: drawn uniformly, evolved by deco_evo_next_steps; a member

@@ -1066,7 +1066,11 @@ deco_status deco_autotune(deco_handle* h, int32_t steps) {
   HIP_TRY(h, hipEventCreate(&e0));
   HIP_TRY(h, hipEventCreate(&e1));
   // the default comes first; each candidate is timed twice (the faster run counts) and
-  // replaces the best only when more than 3% faster, so near-ties keep the earlier choice
+  // replaces the best only when its time per step is more than 3% lower, so near-ties keep
+  // the earlier choice. Step-kernel candidates cost the same per step at any call length and
+  // are timed over at most kStepTrial steps; resident ones carry a fixed cost per call and are
+  // timed over the whole call.
+  constexpr int kStepTrial = 50;
   cand.insert(cand.begin(), base);
   float best_ms = 1e30f;
   Schedule best = h->sched;
@@ -1080,15 +1084,16 @@ deco_status deco_autotune(deco_handle* h, int32_t steps) {
     deco_status st = deco_start(h, &sa);
     if (st) return st;
     if ((st = launch_steps(h, 2, 1, 0))) return st;  // warm caches
+    const int n_steps = s.rbt > 0 ? steps : std::min(steps, kStepTrial);
     float ms = 1e30f;
     for (int rep = 0; rep < 2; ++rep) {
       HIP_TRY(h, hipEventRecord(e0, h->stream));
-      if ((st = launch_steps(h, steps, 1, 0))) return st;
+      if ((st = launch_steps(h, n_steps, 1, 0))) return st;
       HIP_TRY(h, hipEventRecord(e1, h->stream));
       HIP_TRY(h, hipEventSynchronize(e1));
       float r = 0.0f;
       HIP_TRY(h, hipEventElapsedTime(&r, e0, e1));
-      ms = std::min(ms, r);
+      ms = std::min(ms, r / (float)n_steps);
     }
     if (ms < 0.97f * best_ms) {
       best_ms = ms;
@@ -1580,11 +1585,11 @@ deco_status deco_solver_create(deco_solver** out, const deco_graph* g, const dec
     return st;
   }
   if (sp->autotune) {
-    // shapes tuned earlier in this process already run their cached winner; candidates are
-    // timed over calls as long as the run's own (a target check or a whole batch, 10 to 50
-    // steps), so a schedule with a fixed cost per call is judged at its real share
+    // shapes tuned earlier in this process already run their cached winner; resident
+    // candidates are timed over calls as long as the run's own (a target check or a whole
+    // batch, 10 to 1000 steps), so their fixed cost per call is judged at its real share
     const int call = sp->check_every > 0 ? sp->check_every : std::max(sp->T_q, sp->T_l);
-    const int tune = std::max(10, std::min(50, call));
+    const int tune = std::max(10, std::min(1000, call));
     if ((!schedule_cached(v->hq) && (st = deco_autotune(v->hq, tune))) ||
         (!schedule_cached(v->hl) && (st = deco_autotune(v->hl, tune)))) {
       solver_free(v);
