@@ -11,11 +11,12 @@
 //
 // Mapping. X is node-major: row v holds its l*B values contiguously. One initialisation
 // tile of a row (Bt = Wc*VEC columns, at most 256, for every component) is held by a row
-// team of Wc lanes with 16-byte loads (8-byte for lifted rows of 2 to 4 components); a 256-thread
-// workgroup has NS = 256/Wc teams. The graph is read through its slot list: row v is its
-// own index (top bit set) followed by its neighbours, so a team walks a flat stream of
-// slots and never waits on a row boundary. Work items are row ranges of one graph and one
-// tile, grouped per XCD (workgroup i runs on XCD i % 8) and walked by a persistent grid:
+// team of Wc lanes with 16-byte loads (8-byte for lifted rows of 2 to 4 components, or 4-byte
+// bfloat16 pairs); a 256-thread workgroup has NS = 256/Wc teams. The graph is read through
+// its slot list: row v is its own index (top bit set) followed by its neighbours, so a team
+// walks a flat stream of slots and never waits on a row boundary. Work items are row ranges
+// of one graph and one tile, grouped per XCD (workgroup i runs on XCD i % 8) and walked by a
+// persistent grid:
 //  * a normal item (rows of degree <= the long-row threshold, at most kEmax slots and
 //    kRmax rows) copies its slots (and slot weights) into LDS with coalesced loads; team s
 //    takes the rows whose own slot lies in the s-th equal share of the item's slots and
@@ -145,6 +146,33 @@ struct VecIO<uint16_t, 4> {
     *reinterpret_cast<uint2*>(p) = v;
   }
 };
+
+template <>
+struct VecIO<uint16_t, 2> {
+  using raw = uint32_t;
+  static __device__ __forceinline__ raw load_raw(const uint16_t* p) { return *reinterpret_cast<const uint32_t*>(p); }
+  static __device__ __forceinline__ raw zero() { return 0u; }
+  static __device__ __forceinline__ void unpack(const raw& v, float (&o)[2]) {
+    o[0] = bf2f(v & 0xFFFFu);
+    o[1] = bf2f(v >> 16);
+  }
+  static __device__ __forceinline__ void store(uint16_t* p, const float (&o)[2]) {
+    *reinterpret_cast<uint32_t*>(p) = pack_bf16(o[0], o[1]);
+  }
+};
+
+// The 32-bit words (bfloat16 pairs) of a raw bfloat16 load.
+__device__ __forceinline__ void raw_words(const uint4& v, uint32_t (&w)[4]) {
+  w[0] = v.x;
+  w[1] = v.y;
+  w[2] = v.z;
+  w[3] = v.w;
+}
+__device__ __forceinline__ void raw_words(const uint2& v, uint32_t (&w)[2]) {
+  w[0] = v.x;
+  w[1] = v.y;
+}
+__device__ __forceinline__ void raw_words(const uint32_t& v, uint32_t (&w)[1]) { w[0] = v; }
 
 template <>
 struct VecIO<uint16_t, 1> {
@@ -441,15 +469,7 @@ __device__ __forceinline__ void open_row(RowState<T, L, VEC, WM>& st, int row,
     // z = 1{x > 0} = 1 - 1{x <= 0} unlifted; z = 1{x >= 0} = 1{-x <= 0} lifted
     const uint32_t flip = lifted ? 0x80008000u : 0u, inv = lifted ? 0u : 0x00010001u;
     uint32_t wd[VEC / 2];
-    if constexpr (VEC == 8) {
-      wd[0] = xr[0].x;
-      wd[1] = xr[0].y;
-      wd[2] = xr[0].z;
-      wd[3] = xr[0].w;
-    } else {
-      wd[0] = xr[0].x;
-      wd[1] = xr[0].y;
-    }
+    raw_words(xr[0], wd);
     uint32_t zm = 0;
 #pragma unroll
     for (int k = 0; k < VEC / 2; ++k) {
@@ -474,15 +494,7 @@ __device__ __forceinline__ void take_slot(RowState<T, L, VEC, WM>& st, const typ
   using ST = typename ScoreType<WM>::type;
   if constexpr (RowState<T, L, VEC, WM>::kPacked) {
     uint32_t wd[VEC / 2];
-    if constexpr (VEC == 8) {
-      wd[0] = xr[0].x;
-      wd[1] = xr[0].y;
-      wd[2] = xr[0].z;
-      wd[3] = xr[0].w;
-    } else {
-      wd[0] = xr[0].x;
-      wd[1] = xr[0].y;
-    }
+    raw_words(xr[0], wd);
     const uint32_t wlo = WM == kUnitW ? st.ulo : (__float_as_uint(wq) >> 16);
     const uint32_t whi = WM == kUnitW ? st.uhi : wlo << 16;
 #pragma unroll
@@ -510,15 +522,7 @@ __device__ __forceinline__ void take_slot(RowState<T, L, VEC, WM>& st, const typ
 #pragma unroll
     for (int i = 0; i < L; ++i) {
       uint32_t wd[VEC / 2];
-      if constexpr (VEC == 8) {
-        wd[0] = xr[i].x;
-        wd[1] = xr[i].y;
-        wd[2] = xr[i].z;
-        wd[3] = xr[i].w;
-      } else {
-        wd[0] = xr[i].x;
-        wd[1] = xr[i].y;
-      }
+      raw_words(xr[i], wd);
 #pragma unroll
       for (int k = 0; k < VEC / 2; ++k) {
         st.acc[i][2 * k] = dot2_bf16(wd[k], wlo, st.acc[i][2 * k]);
@@ -1504,13 +1508,14 @@ hipError_t step_dispatch(const StepArgs& a, int wmode, int grid, hipStream_t s) 
 }
 
 // All component counts for float32 and one-element lanes; bfloat16 runs unlifted rows 8 or
-// 4 values per lane and lifted rows (l > 1) 4 values per lane; 2-value float32 lanes run
-// rows of 2 to 4 components without momentum (launch_step maps the rest to 4-value lanes).
+// 4 values per lane and lifted rows (l > 1) 4 values per lane; 2-value lanes (float32 by
+// default, bfloat16 as a tuned choice) run rows of 2 to 4 components without momentum
+// (launch_step maps the rest to 4-value lanes).
 template <typename T, int VEC, bool MOM>
 hipError_t step_dispatch_l(const StepArgs& a, int wmode, int grid, hipStream_t s) {
   constexpr bool bf_wide = sizeof(T) == 2 && VEC == 8;
-  constexpr bool f32_pair = sizeof(T) == 4 && VEC == 2;
-  if constexpr (f32_pair) {
+  constexpr bool pair = VEC == 2;
+  if constexpr (pair) {
     if (MOM || a.L == 1) return hipErrorInvalidValue;
   } else {
     if (a.L == 1) return step_dispatch<T, VEC, 1, MOM>(a, wmode, grid, s);
@@ -1541,6 +1546,8 @@ hipError_t launch_step_impl(const StepArgs& a, int dtype, int vec, int grid, hip
   } else {
     if (vec == 8) return step_dispatch_l<uint16_t, 8, MOM>(a, wmode, grid, s);
     if (vec == 4) return step_dispatch_l<uint16_t, 4, MOM>(a, wmode, grid, s);
+    if constexpr (!MOM)
+      if (vec == 2) return step_dispatch_l<uint16_t, 2, MOM>(a, wmode, grid, s);
     if (vec == 1) return step_dispatch_l<uint16_t, 1, MOM>(a, wmode, grid, s);
   }
   return hipErrorInvalidValue;
@@ -1861,7 +1868,7 @@ hipError_t launch_dense_validate(const uint16_t* W, int n, float* dw, int* flags
 }
 
 hipError_t launch_step(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s) {
-  if (dtype == 0 && vec == 2 && (a.L == 1 || a.L > 4 || a.vel != nullptr)) {
+  if (vec == 2 && (a.L == 1 || a.L > 4 || a.vel != nullptr)) {
     // a tile of Wc 2-value lanes is the same tile as Wc/2 4-value lanes (the work list
     // depends on the tile only): run the kernels of 4-value lanes on it
     if (a.Wc < 2) return hipErrorInvalidValue;

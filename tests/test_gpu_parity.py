@@ -180,6 +180,32 @@ def test_f32_lifted_lane_width_parity(name):
     print(f"{name}: max |dX| = {worst:.2e}, schedule: {s}")
 
 
+# bfloat16 rows of 2 to 4 components with 2 values per lane (lane_elems = 2, 4-byte loads;
+# the autotuner's alternative to the native 4); one-component members and momentum run the
+# 4-value kernels on the same tile.
+BF16_LIFTED_PAIRS = {
+    "l2_B64": (lambda: synth.barabasi_albert(500, 3, 40), 64, 2, (16, 1 << 30, 1, 4096, 256, 2), None),
+    "l3_B16_pm1": (lambda: synth.with_rademacher_weights(synth.erdos_renyi(400, 0.05, 41), 5), 16, 3,
+                   (8, 1 << 30, 0, 4096, 512, 2), None),
+    "l4_B32": (lambda: synth.barabasi_albert(400, 4, 42), 32, 4, (16, 1 << 30, 0, 4096, 128, 2), None),
+    "l4_B32_active1": (lambda: synth.erdos_renyi(400, 0.05, 43), 32, 4, (16, 1 << 30, 0, 4096, 128, 2),
+                       np.ones(32, np.int32)),
+    "l4_B64_active_mix": (lambda: synth.barabasi_albert(500, 3, 44), 64, 4, (32, 1 << 30, 1, 4096, 256, 2),
+                          np.array([1 + (b % 4) for b in range(64)], np.int32)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(BF16_LIFTED_PAIRS))
+def test_bf16_lifted_pair_lane_parity(name):
+    """Lifted bfloat16 rows, 2 values per lane: teacher-forced parity with the oracle (one
+    bfloat16 ulp plus the float32 step bound), exact cuts and the running best."""
+    make, B, l, sched, la = BF16_LIFTED_PAIRS[name]
+    g = make()
+    worst, _, s = check_run(g, B, 20, l=l, lifted=True, dtype=deco.BF16, schedule=sched, l_active=la)
+    assert "vec=2" in s
+    print(f"{name} bf16 2-lane: max |dX| = {worst:.2e}, schedule: {s}")
+
+
 @pytest.mark.parametrize("name", sorted(LANES4))
 def test_bf16_four_lane_schedule_parity(name):
     """Unlifted bfloat16 rows with 4 values per lane (8-byte loads, one row team per wave at
