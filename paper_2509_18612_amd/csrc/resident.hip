@@ -285,7 +285,9 @@ __global__ __launch_bounds__(RTeam<BT>::NT) void k_resident(StepArgs a, const in
     // one slot, straight-line: an own slot (flag bit) stores the open row's update (to the
     // spare row unless the open row is one of this thread's) and opens row idx; a neighbour
     // slot is summed and counted
-    auto slot = [&](int v, float wq, const float (&xu)[BT]) {
+    // nxt minus cur in bytes: the store address of a row from the address it was gathered at
+    const ptrdiff_t dnc = nxt_b - reinterpret_cast<const unsigned char*>(cur);
+    auto slot = [&](int v, float wq, const float (&xu)[BT], const T* lp) {
       const int idx = v & 0x7FFFFFFF;
       if constexpr (kNarrow) {
         const bool own = v < 0;
@@ -319,7 +321,7 @@ __global__ __launch_bounds__(RTeam<BT>::NT) void k_resident(StepArgs a, const in
           acc[c] = own ? 0.0f : an;
           xv[c] = own ? xu[c] : xv[c];
         }
-        sa = own ? nxt_b + (size_t)idx * BT * sizeof(T) : sa;
+        sa = own ? const_cast<unsigned char*>(reinterpret_cast<const unsigned char*>(lp)) + dnc : sa;
         if constexpr (LAP) dsum = own ? (WM != 0 ? wq : a.dw[r0 + idx]) : dsum;
       } else {
         const int ownm = v >> 31;
@@ -377,17 +379,24 @@ __global__ __launch_bounds__(RTeam<BT>::NT) void k_resident(StepArgs a, const in
       const int sl[4] = {sv.x, sv.y, sv.z, sv.w};
       const float wl[4] = {wv4.x, wv4.y, wv4.z, wv4.w};
       float xb[4][BT];
+      const T* lp[4];
       if (jb < full) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) RowIO<T, BT>::load(cur + (size_t)(sl[q] & 0x7FFFFFFF) * BT, xb[q]);
+        for (int q = 0; q < 4; ++q) {
+          lp[q] = cur + (size_t)(sl[q] & 0x7FFFFFFF) * BT;
+          RowIO<T, BT>::load(lp[q], xb[q]);
+        }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) slot(sl[q], wl[q], xb[q]);
+        for (int q = 0; q < 4; ++q) slot(sl[q], wl[q], xb[q], lp[q]);
       } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) RowIO<T, BT>::load(cur + (size_t)(jb + q < len ? sl[q] & 0x7FFFFFFF : 0) * BT, xb[q]);
+        for (int q = 0; q < 4; ++q) {
+          lp[q] = cur + (size_t)(jb + q < len ? sl[q] & 0x7FFFFFFF : 0) * BT;
+          RowIO<T, BT>::load(lp[q], xb[q]);
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          if (jb + q < len) slot(sl[q], wl[q], xb[q]);
+          if (jb + q < len) slot(sl[q], wl[q], xb[q], lp[q]);
       }
     }
     // the head row's sums for its owner (zeros when the share has no head row)
