@@ -679,6 +679,17 @@ RESIDENT = {
     "per_init_eta_bt2": ("per_init_eta", 2, deco.F32),
     "B1_bt1": ("B1", 1, deco.F32),
     "B2_bt2_bf16": ("B2", 2, deco.BF16),
+    # one- and two-column tiles (per-lane boolean flags) under every weight mode, both
+    # rounding rules and the Laplacian form
+    "laplacian_B16_bt1": ("laplacian_B16", 1, deco.F32),
+    "laplacian_B16_bt2_bf16": ("laplacian_B16", 2, deco.BF16),
+    "intw_B8_bt2": ("er_intw_B8", 2, deco.F32),
+    "intw_B8_bt1_bf16": ("er_intw_B8", 1, deco.BF16),
+    "er_pm1_B24_bt1": ("er_pm1_B24_tiles", 1, deco.F32),
+    "er_pm1_B24_bt2_bf16": ("er_pm1_B24_tiles", 2, deco.BF16),
+    "lifted_l1_B16_bt1": ("unlifted_as_l1_lifted", 1, deco.F32),
+    "lifted_l1_B16_bt2_bf16": ("unlifted_as_l1_lifted", 2, deco.BF16),
+    "ba_hubs_B64_bt1_bf16": ("ba_hubs_B64", 1, deco.BF16),
 }
 
 
@@ -707,7 +718,13 @@ def test_resident_multi_graph_batch_and_real_weights():
     g = synth.erdos_renyi(300, 0.06, 21)
     m = g.nnz // 2
     g = synth.with_weights(g, np.random.default_rng(3).uniform(0.1, 2.0, m).astype(np.float32))
-    r = run_teacher_forced(g, 16, 10, schedule=resident(16))
+    for bt in (16, 2, 1):
+        _real_weights_resident(g, bt)
+
+
+def _real_weights_resident(g, bt):
+    r = run_teacher_forced(g, 16, 10, schedule=resident(bt))
+    assert r["handle"].schedule().startswith(f"resident cols={bt}")
     for t, X in enumerate(r["xs"]):
         cuts, _ = oracle_cuts(g, X, 16, 1, False)
         if t < 10:
