@@ -127,6 +127,18 @@ def _intw_graph():
 CASES["er_intw_B8"] = (_intw_graph, 8, {})
 
 
+def _realw_graph():
+    g = synth.erdos_renyi(300, 0.06, 25)
+    m = g.nnz // 2
+    return synth.with_weights(g, np.random.default_rng(4).uniform(0.1, 2.0, m).astype(np.float32))
+
+
+# lifted rows under the other weight modes (float32 runs them 2 values per lane)
+CASES["lifted_l3_pm1_B16"] = (lambda: synth.with_rademacher_weights(synth.erdos_renyi(350, 0.06, 26), 6), 16,
+                              dict(l=3, lifted=True))
+CASES["lifted_l2_intw_B32"] = (_intw_graph, 32, dict(l=2, lifted=True))
+
+
 @pytest.mark.parametrize("name", sorted(CASES))
 def test_fp32_teacher_forced_parity(name):
     make, B, kw = CASES[name]
@@ -192,6 +204,7 @@ BF16_LIFTED_PAIRS = {
                        np.ones(32, np.int32)),
     "l4_B64_active_mix": (lambda: synth.barabasi_albert(500, 3, 44), 64, 4, (32, 1 << 30, 1, 4096, 256, 2),
                           np.array([1 + (b % 4) for b in range(64)], np.int32)),
+    "l2_B32_intw": (_intw_graph, 32, 2, (16, 1 << 30, 0, 4096, 256, 2), None),
 }
 
 
@@ -231,6 +244,31 @@ def test_float_weights_cut_within_bound():
         want = oracle.step(g, X, 0.1) if t < 10 else None
         if want is not None:
             assert np.abs(r["xs"][t + 1] - want).max() <= 1e-5
+    r["handle"].destroy()
+
+
+@pytest.mark.parametrize("dtype,l,sched", [(deco.F32, 4, None), (deco.F32, 2, (4, 1 << 30, 0, 4096, 256, 4)),
+                                           (deco.BF16, 3, (8, 1 << 30, 0, 4096, 256, 2))])
+def test_lifted_float_weights_cut_within_bound(dtype, l, sched):
+    """Lifted rows with real weights (float32 on its default 2-value lanes and on 4-value
+    lanes; bfloat16 on 2-value lanes): cuts within the bound of float32 partials, steps within
+    1e-5 of the oracle's (bfloat16: one ulp more)."""
+    g = _realw_graph()
+    B = 16
+    r = run_teacher_forced(g, B, 10, l=l, lifted=True, dtype=dtype, schedule=sched)
+    want_vec = "vec=4" if sched is not None and sched[5] == 4 else "vec=2"
+    assert want_vec in r["handle"].schedule()
+    tol = 0.5 * np.abs(g.w.astype(np.float64)).sum() * 2048 * 2.0 ** -24
+    for t, X in enumerate(r["xs"]):
+        cuts, _ = oracle_cuts(g, X, B, l, True)
+        assert np.all(np.abs(r["trace"][t] - cuts) <= tol), f"cut at step {t}"
+        if t < 10:
+            want = oracle.step(g, X, 0.1)
+            if dtype == deco.BF16:
+                emu = oracle.to_bf16(want.astype(np.float32)).astype(np.float64)
+                assert np.all(np.abs(r["xs"][t + 1] - emu) <= bf16_ulp(emu) + 1e-5), f"step {t}"
+            else:
+                assert np.abs(r["xs"][t + 1] - want).max() <= 1e-5, f"step {t}"
     r["handle"].destroy()
 
 
