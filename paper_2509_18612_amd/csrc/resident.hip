@@ -240,17 +240,17 @@ __global__ __launch_bounds__(RTeam<BT>::NT) void k_resident(StepArgs a, const in
       acc[c] = 0.0f;
       xv[c] = 0.0f;
     }
-    // the open row: byte offset ri in the buffers (the lane's spare row while none of this
+    // The open row: byte offset ri in the buffers (the lane's spare row while none of this
     // thread's rows is open), its values xv, sums acc, weighted degree dsum; while it is the
-    // share's head row its sums go to hacc. Narrow tiles (one or two columns per thread) keep
-    // the flags as per-lane booleans (head), so each select is one vector instruction with
-    // its mask in scalar registers; wide tiles keep them as integer masks (headm all ones
-    // while in the head row) and the open row's sides as bits (zv), so their selects stay
-    // vector bit operations rather than a scalar mask operation per column.
-    // Narrow tiles address the open row's store directly (sa) and, with float32 storage,
-    // point it at the thread's s_part entry while the open row is the head row: the store
-    // that closes the head row writes its sums there (kHeadStore), with no select per slot
-    // for hacc.
+    // share's head row its sums go to hacc.
+    // Narrow tiles (one or two columns per thread) keep the flags as per-lane booleans (head),
+    // so each select is one vector instruction with its mask in scalar registers, and carry
+    // the open row's store address (sa) instead of ri; with float32 storage sa points at the
+    // thread's s_part entry while the open row is the head row, so the store that closes the
+    // head row writes its sums there (kHeadStore) and no select per slot keeps hacc.
+    // Wide tiles keep integer masks (headm all ones while in the head row) and the open
+    // row's sides as bits (zv): their selects stay vector bit operations rather than a
+    // scalar mask operation per column.
     constexpr bool kNarrow = BT < 4;
     constexpr bool kHeadStore = kNarrow && sizeof(T) == 4;
     bool head = false;
@@ -282,11 +282,11 @@ __global__ __launch_bounds__(RTeam<BT>::NT) void k_resident(StepArgs a, const in
         y[c] = __builtin_amdgcn_fmed3f(x1, -1.0f, 1.0f);
       }
     };
-    // one slot, straight-line: an own slot (flag bit) stores the open row's update (to the
-    // spare row unless the open row is one of this thread's) and opens row idx; a neighbour
-    // slot is summed and counted
     // nxt minus cur in bytes: the store address of a row from the address it was gathered at
     const ptrdiff_t dnc = nxt_b - reinterpret_cast<const unsigned char*>(cur);
+    // one slot (lp: the address its value was gathered at), straight-line: an own slot (flag
+    // bit) stores the open row's update (to the spare row unless the open row is one of this
+    // thread's) and opens row idx; a neighbour slot is summed and counted
     auto slot = [&](int v, float wq, const float (&xu)[BT], const T* lp) {
       const int idx = v & 0x7FFFFFFF;
       if constexpr (kNarrow) {
