@@ -195,14 +195,14 @@ deco_status deco_autotune(deco_handle *h, int32_t steps);
 /* Set the kernel schedule explicitly (instead of the default or the autotuner's choice).
  * lanes_per_row: lanes of one row team, which holds one row's initialisation tile (power
  * of two <= 64; the tile is lanes_per_row * (16 bytes / element size) columns, 8 bytes for
- * lifted bfloat16 and for float32 handles of l = 2..4; it must divide B, hold at most 256 columns, and at least 64 when 64
+ * lifted bfloat16 and for float32 handles of l = 2..8; it must divide B, hold at most 256 columns, and at least 64 when 64
  * divides B for unlifted handles, 16 when 16 divides B for lifted ones); long_row: rows with more neighbours get a work item of their own (>= 16; rows
  * with more slots than nnz_per_item always do); xcd_mode: 0 = each XCD owns a row range
  * for every tile, 1 = each XCD owns tiles; blocks_per_xcd: workgroups per XCD (1..4096;
  * with more items than workgroups a workgroup walks several); nnz_per_item: target slots
  * (edges plus rows) per work item (128..2048); lane_elems: 0 = the native lane width, or
  * 4 = four values per lane: for unlifted bfloat16 rows (8-byte loads, twice the lanes per
- * tile) and for float32 handles of l = 2..4 (16-byte loads, half the lanes per tile), or
+ * tile) and for float32 handles of l = 2..8 (16-byte loads, half the lanes per tile), or
  * 2 = two values per lane for bfloat16 handles of l = 2..4 (4-byte loads, twice the lanes). DECO_E_INVAL when the values do not fit B or the limits.
  * Synchronous (uploads the work list). */
 typedef struct deco_schedule {

@@ -1154,8 +1154,8 @@ deco_status deco_set_schedule(deco_handle* h, const deco_schedule* q) {
     return DECO_E_INVAL;
   Schedule s = default_schedule(h);
   if (q->lane_elems != 0) {
-    // 4 values per lane is the one alternative width (unlifted bfloat16 rows, float32 rows of
-    // 2 to 4 components)
+    // the alternative widths: 4 values per lane (unlifted bfloat16 rows, float32 rows of 2 to
+    // 8 components) and 2 (bfloat16 rows of 2 to 4 components)
     if (q->lane_elems == 2 && h->dtype == DECO_BF16 && s.vec == 4 && h->p.l >= 2 && h->p.l <= 4) {
       s.vec = 2;
     } else {

@@ -1509,8 +1509,8 @@ hipError_t step_dispatch(const StepArgs& a, int wmode, int grid, hipStream_t s) 
 
 // All component counts for float32 and one-element lanes; bfloat16 runs unlifted rows 8 or
 // 4 values per lane and lifted rows (l > 1) 4 values per lane; 2-value lanes (float32 by
-// default, bfloat16 as a tuned choice) run rows of 2 to 4 components without momentum
-// (launch_step maps the rest to 4-value lanes).
+// default, bfloat16 as a tuned choice) run rows of 2 to 4 components here and float32 rows
+// of 5 to 8 in step_wide.hip, without momentum (launch_step maps the rest to 4-value lanes).
 template <typename T, int VEC, bool MOM>
 hipError_t step_dispatch_l(const StepArgs& a, int wmode, int grid, hipStream_t s) {
   constexpr bool bf_wide = sizeof(T) == 2 && VEC == 8;
@@ -1847,7 +1847,7 @@ inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1)
 }  // namespace
 
 #ifndef DECO_KERNELS_ONLY_TU  // the host launchers live in this translation unit only
-int native_vec(int dtype, int L) { return dtype == 0 ? (L >= 2 && L <= 4 ? 2 : 4) : (L == 1 ? 8 : 4); }
+int native_vec(int dtype, int L) { return dtype == 0 ? (L >= 2 && L <= 8 ? 2 : 4) : (L == 1 ? 8 : 4); }
 
 hipError_t launch_dense_transpose(const void* X, void* XT, long long n, int C, hipStream_t s) {
   hipLaunchKernelGGL(k_transpose_bf16, dim3((unsigned)(n / 64), (unsigned)(C / 64)), dim3(256), 0, s,
@@ -1868,7 +1868,7 @@ hipError_t launch_dense_validate(const uint16_t* W, int n, float* dw, int* flags
 }
 
 hipError_t launch_step(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s) {
-  if (vec == 2 && (a.L == 1 || a.L > 4 || a.vel != nullptr)) {
+  if (vec == 2 && (a.L == 1 || (a.L > 4 && dtype != 0) || a.vel != nullptr)) {
     // a tile of Wc 2-value lanes is the same tile as Wc/2 4-value lanes (the work list
     // depends on the tile only): run the kernels of 4-value lanes on it
     if (a.Wc < 2) return hipErrorInvalidValue;
