@@ -75,7 +75,7 @@ def pin_args(sched, dtype_bf16, l):
     d = parse_schedule(sched)
     vec = int(d["vec"])
     lane_elems = 4 if vec == 4 and ((dtype_bf16 and l == 1) or (not dtype_bf16 and 2 <= l <= 8)) else 0
-    if dtype_bf16 and 2 <= l <= 4 and vec == 2:
+    if dtype_bf16 and 2 <= l <= 8 and vec == 2:
         lane_elems = 2
     if sched.startswith("resident"):
         return (int(d["Wc"]), 1 << 30, 0, 128, 2048, lane_elems, int(d["cols"]))

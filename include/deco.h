@@ -203,7 +203,7 @@ deco_status deco_autotune(deco_handle *h, int32_t steps);
  * (edges plus rows) per work item (128..2048); lane_elems: 0 = the native lane width, or
  * 4 = four values per lane: for unlifted bfloat16 rows (8-byte loads, twice the lanes per
  * tile) and for float32 handles of l = 2..8 (16-byte loads, half the lanes per tile), or
- * 2 = two values per lane for bfloat16 handles of l = 2..4 (4-byte loads, twice the lanes). DECO_E_INVAL when the values do not fit B or the limits.
+ * 2 = two values per lane for bfloat16 handles of l = 2..8 (4-byte loads, twice the lanes). DECO_E_INVAL when the values do not fit B or the limits.
  * Synchronous (uploads the work list). */
 typedef struct deco_schedule {
   int32_t lanes_per_row, long_row, xcd_mode, blocks_per_xcd, nnz_per_item, lane_elems;

@@ -1035,7 +1035,7 @@ deco_status deco_autotune(deco_handle* h, int32_t steps) {
   // per tile, twice the registers per lane)
   std::vector<int> vecs{vec};
   if ((h->dtype == DECO_BF16 && vec == 8) || (h->dtype == DECO_F32 && vec == 2)) vecs.push_back(4);
-  if (h->dtype == DECO_BF16 && vec == 4 && h->p.l >= 2 && h->p.l <= 4) vecs.push_back(2);
+  if (h->dtype == DECO_BF16 && vec == 4 && h->p.l >= 2 && h->p.l <= 8) vecs.push_back(2);
   for (int vw : vecs) {
     const int wmax_v = max_wc(vw, h->p.B);
     for (int Wc = wmax_v; Wc >= 1 && Wc * vw >= mt && Wc * wspan >= wmax_v; Wc /= 2) {
@@ -1155,8 +1155,8 @@ deco_status deco_set_schedule(deco_handle* h, const deco_schedule* q) {
   Schedule s = default_schedule(h);
   if (q->lane_elems != 0) {
     // the alternative widths: 4 values per lane (unlifted bfloat16 rows, float32 rows of 2 to
-    // 8 components) and 2 (bfloat16 rows of 2 to 4 components)
-    if (q->lane_elems == 2 && h->dtype == DECO_BF16 && s.vec == 4 && h->p.l >= 2 && h->p.l <= 4) {
+    // 8 components) and 2 (bfloat16 rows of 2 to 8 components)
+    if (q->lane_elems == 2 && h->dtype == DECO_BF16 && s.vec == 4 && h->p.l >= 2 && h->p.l <= 8) {
       s.vec = 2;
     } else {
       if (q->lane_elems != 4 || !((h->dtype == DECO_BF16 && s.vec == 8) || (h->dtype == DECO_F32 && s.vec == 2)))

@@ -11,8 +11,8 @@
 //
 // Mapping. X is node-major: row v holds its l*B values contiguously. One initialisation
 // tile of a row (Bt = Wc*VEC columns, at most 256, for every component) is held by a row
-// team of Wc lanes with 16-byte loads (8-byte for lifted rows of 2 to 4 components, or 4-byte
-// bfloat16 pairs); a 256-thread workgroup has NS = 256/Wc teams. The graph is read through
+// team of Wc lanes with 16-byte loads (8-byte for lifted rows, or 4-byte bfloat16 pairs); a
+// 256-thread workgroup has NS = 256/Wc teams. The graph is read through
 // its slot list: row v is its own index (top bit set) followed by its neighbours, so a team
 // walks a flat stream of slots and never waits on a row boundary. Work items are row ranges
 // of one graph and one tile, grouped per XCD (workgroup i runs on XCD i % 8) and walked by a
@@ -1509,8 +1509,8 @@ hipError_t step_dispatch(const StepArgs& a, int wmode, int grid, hipStream_t s) 
 
 // All component counts for float32 and one-element lanes; bfloat16 runs unlifted rows 8 or
 // 4 values per lane and lifted rows (l > 1) 4 values per lane; 2-value lanes (float32 by
-// default, bfloat16 as a tuned choice) run rows of 2 to 4 components here and float32 rows
-// of 5 to 8 in step_wide.hip, without momentum (launch_step maps the rest to 4-value lanes).
+// default, bfloat16 as a tuned choice) run rows of 2 to 4 components here and of 5 to 8 in
+// step_wide.hip, without momentum (launch_step maps the rest to 4-value lanes).
 template <typename T, int VEC, bool MOM>
 hipError_t step_dispatch_l(const StepArgs& a, int wmode, int grid, hipStream_t s) {
   constexpr bool bf_wide = sizeof(T) == 2 && VEC == 8;
@@ -1868,7 +1868,7 @@ hipError_t launch_dense_validate(const uint16_t* W, int n, float* dw, int* flags
 }
 
 hipError_t launch_step(const StepArgs& a, int dtype, int vec, int grid, hipStream_t s) {
-  if (vec == 2 && (a.L == 1 || (a.L > 4 && dtype != 0) || a.vel != nullptr)) {
+  if (vec == 2 && (a.L == 1 || a.vel != nullptr)) {
     // a tile of Wc 2-value lanes is the same tile as Wc/2 4-value lanes (the work list
     // depends on the tile only): run the kernels of 4-value lanes on it
     if (a.Wc < 2) return hipErrorInvalidValue;

@@ -192,7 +192,7 @@ def test_f32_lifted_lane_width_parity(name):
     print(f"{name}: max |dX| = {worst:.2e}, schedule: {s}")
 
 
-# bfloat16 rows of 2 to 4 components with 2 values per lane (lane_elems = 2, 4-byte loads;
+# bfloat16 rows of 2 to 8 components with 2 values per lane (lane_elems = 2, 4-byte loads;
 # the autotuner's alternative to the native 4); one-component members and momentum run the
 # 4-value kernels on the same tile.
 BF16_LIFTED_PAIRS = {
@@ -205,6 +205,9 @@ BF16_LIFTED_PAIRS = {
     "l4_B64_active_mix": (lambda: synth.barabasi_albert(500, 3, 44), 64, 4, (32, 1 << 30, 1, 4096, 256, 2),
                           np.array([1 + (b % 4) for b in range(64)], np.int32)),
     "l2_B32_intw": (_intw_graph, 32, 2, (16, 1 << 30, 0, 4096, 256, 2), None),
+    "l6_B24": (lambda: synth.erdos_renyi(250, 0.06, 45), 24, 6, (4, 1 << 30, 0, 4096, 256, 2), None),
+    "l8_B16_active_mix": (lambda: synth.barabasi_albert(300, 3, 46), 16, 8, (8, 1 << 30, 0, 4096, 256, 2),
+                          np.array([1 + (5 * b) % 8 for b in range(16)], np.int32)),
 }
 
 
